@@ -1,0 +1,113 @@
+// C entry points of the oracle, loaded with ctypes by the test suite and by
+// the CPU-baseline leg of the benchmark.  TEST INFRASTRUCTURE ONLY.
+#include <cstring>
+#include <string>
+
+#include "orc.hpp"
+
+namespace {
+thread_local std::string g_err;
+int fail(const std::string& e) {
+  g_err = e;
+  return -1;
+}
+}  // namespace
+
+extern "C" {
+
+const char* orc_last_error(void) { return g_err.c_str(); }
+
+int orc_mesh_build(const int32_t* T, int level_min, int level_max, orc::Phi0Fn phi0, void* user,
+                   double band, const int32_t* leaves, int64_t n_leaves, void** out) {
+  orc::Mesh* m = new orc::Mesh();
+  int t[3] = {T[0], T[1], T[2]};
+  std::string err =
+      orc::build_mesh(t, level_min, level_max, phi0, user, band, leaves, n_leaves, *m);
+  if (!err.empty()) {
+    delete m;
+    return fail(err);
+  }
+  *out = m;
+  return 0;
+}
+
+void orc_mesh_free(void* m) { delete (orc::Mesh*)m; }
+
+// sizes: n_leaves, n_nodes, n_hanging, n_constraint_entries, level_max
+void orc_mesh_sizes(void* mp, int64_t* s) {
+  const orc::Mesh& m = *(orc::Mesh*)mp;
+  s[0] = (int64_t)m.leaves.size();
+  s[1] = (int64_t)m.nodes.size();
+  s[2] = (int64_t)m.hang_xyz.size();
+  s[3] = (int64_t)m.hang_ids.size();
+  s[4] = m.D;
+}
+
+void orc_mesh_arrays(void* mp, int32_t* leaves4, int32_t* elem8, int32_t* nodes3, uint8_t* bflags,
+                     int32_t* hang3, int64_t* hang_off, int32_t* hang_ids, double* hang_w) {
+  const orc::Mesh& m = *(orc::Mesh*)mp;
+  for (size_t e = 0; e < m.leaves.size(); ++e) {
+    leaves4[4 * e] = (int32_t)m.leaves[e].x;
+    leaves4[4 * e + 1] = (int32_t)m.leaves[e].y;
+    leaves4[4 * e + 2] = (int32_t)m.leaves[e].z;
+    leaves4[4 * e + 3] = m.leaves[e].level;
+    for (int c = 0; c < 8; ++c) elem8[8 * e + c] = m.elem[e][c];
+  }
+  for (size_t i = 0; i < m.nodes.size(); ++i) {
+    for (int d = 0; d < 3; ++d) nodes3[3 * i + d] = (int32_t)m.nodes[i][d];
+    bflags[i] = m.bflags[i];
+  }
+  for (size_t i = 0; i < m.hang_xyz.size(); ++i)
+    for (int d = 0; d < 3; ++d) hang3[3 * i + d] = (int32_t)m.hang_xyz[i][d];
+  for (size_t i = 0; i < m.hang_off.size(); ++i) hang_off[i] = m.hang_off[i];
+  for (size_t i = 0; i < m.hang_ids.size(); ++i) {
+    hang_ids[i] = m.hang_ids[i];
+    hang_w[i] = m.hang_w[i];
+  }
+}
+
+int orc_residual(void* m, const orc::Params* p, int block, const double* Unew, const double* Uold,
+                 const double* forcing, double* R) {
+  std::string e = orc::residual(*(orc::Mesh*)m, *p, block, Unew, Uold, forcing, R);
+  return e.empty() ? 0 : fail(e);
+}
+
+int orc_jvp(void* m, const orc::Params* p, int block, const double* Unew, const double* Uold,
+            const double* dU, double* JdU) {
+  std::string e = orc::jvp(*(orc::Mesh*)m, *p, block, Unew, Uold, dU, JdU);
+  return e.empty() ? 0 : fail(e);
+}
+
+int orc_residual_rows(void* m, const orc::Params* p, int block, const double* Unew,
+                      const double* Uold, const int32_t* rows, int64_t nrows, const double* dU,
+                      double* out) {
+  std::string e = orc::residual_rows(*(orc::Mesh*)m, *p, block, Unew, Uold, rows, nrows, dU, out);
+  return e.empty() ? 0 : fail(e);
+}
+
+int orc_diag_blocks(void* m, const orc::Params* p, int block, const double* Unew,
+                    const double* Uold, double* out) {
+  std::string e = orc::diag_blocks(*(orc::Mesh*)m, *p, block, Unew, Uold, out);
+  return e.empty() ? 0 : fail(e);
+}
+
+void orc_diagnostics(void* m, const orc::Params* p, const double* U, double* mass,
+                     double* energy) {
+  orc::diagnostics(*(orc::Mesh*)m, *p, U, mass, energy);
+}
+
+int orc_step(void* m, const orc::Params* p, const orc::SolverOpts* o, double* U,
+             const double* forcing, orc::StepStats* st) {
+  std::string e = orc::step(*(orc::Mesh*)m, *p, *o, U, forcing, st);
+  return e.empty() ? 0 : fail(e);
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  extern int omp_get_max_threads(void);
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+}

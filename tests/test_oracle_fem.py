@@ -1,0 +1,444 @@
+"""Pins of the oracle's element loop (Sec. 3 and 3.4) against closed forms,
+exact algebraic identities and finite differences.
+
+Each pin is chosen so that a plausible slip in the oracle (a dropped term, a
+wrong sign or coefficient, a transposed index, the wrong time level) fails
+at least one of them."""
+import numpy as np
+import pytest
+
+from paper_1912_12453_amd import workloads as W
+from tests import fem_closed_forms as CF
+from tests import uniform_quadrature as UQ
+
+CH, NS = 0, 1
+
+
+def P(orc, **kw):
+    base = dict(Cn=0.3, Pe=2.0, Re=7.0, We=3.0, Fr=1.5, rho_minus=0.25, eta_minus=0.4,
+                dt=0.05, g=(0.0, -1.0, 0.0), C_I=6.0, flux_mode=0)
+    base.update(kw)
+    return orc.Params.make(**base)
+
+
+@pytest.fixture(scope="module")
+def uni3(orc):
+    m = orc.Mesh((1, 1, 1), 3, 3)
+    return m, CF.lattice_index(m.nodes, 3)
+
+
+@pytest.fixture(scope="module")
+def adaptive(orc):
+    leaves = W.random_leaves((1, 1, 1), 4, 7, p_split=0.3, level_min=2)
+    m = orc.Mesh((1, 1, 1), 0, 4, leaves=leaves)
+    assert m.hang_xyz.shape[0] > 50
+    return m
+
+
+def interior_centre(idx):
+    c = idx.shape[0] // 2
+    return c, c, c
+
+
+# ------------------------------------------------------- Q1 stencils ------
+def test_mass_stencil(orc, uni3):
+    """(q, (phi^{k+1}-phi^k)/dt) with phi^{k+1} = dt e_n is the mass matrix
+    column: h^3 * (8/27, 2/27, 1/54, 1/216) for centre, face, edge, corner."""
+    m, idx = uni3
+    h = 1 / 8
+    p = P(orc)
+    i, j, k = interior_centre(idx)
+    n = idx[i, j, k]
+    U1 = np.zeros((m.n_nodes, 6))
+    U1[n, 0] = p.dt
+    R = m.residual(p, CH, U1, np.zeros_like(U1))
+    expect = {0: 8 / 27, 1: 2 / 27, 2: 1 / 54, 3: 1 / 216}
+    for o in CF.offsets():
+        nb = idx[i + o[0], j + o[1], k + o[2]]
+        assert R[nb, 0] == pytest.approx(expect[sum(map(abs, o))] * h ** 3, rel=1e-14)
+        assert R[nb, 0] == pytest.approx(CF.mass(o, h), rel=1e-14)
+    assert R[:, 0].sum() == pytest.approx(h ** 3, rel=1e-14)
+
+
+def test_stiffness_stencil(orc, uni3):
+    """1/(Pe Cn) (dq/dx_i, dmu~/dx_i) with mu~ = e_n and Pe Cn = 1 is the
+    stiffness column: (8/3, 0, -1/6, -1/12) h; row sum 0."""
+    m, idx = uni3
+    h = 1 / 8
+    p = P(orc, Cn=0.5, Pe=2.0)
+    i, j, k = interior_centre(idx)
+    n = idx[i, j, k]
+    U1 = np.zeros((m.n_nodes, 6))
+    U1[n, 1] = 2.0
+    R = m.residual(p, CH, U1, np.zeros_like(U1))
+    expect = {0: 8 / 3, 1: 0.0, 2: -1 / 6, 3: -1 / 12}
+    for o in CF.offsets():
+        nb = idx[i + o[0], j + o[1], k + o[2]]
+        assert R[nb, 0] == pytest.approx(expect[sum(map(abs, o))] * h, rel=1e-13, abs=1e-15)
+    assert abs(R[:, 0].sum()) < 1e-14
+
+
+def test_cahn_number_and_mass_in_mu_row(orc, uni3):
+    """mu row: -(q, mu~) + Cn^2 (dq/dx_i, dphi~/dx_i); at phi~ = e_n the psi'
+    term contributes (q, phi~^3 - phi~) evaluated at the Gauss points."""
+    m, idx = uni3
+    h = 1 / 8
+    Cn = 0.3
+    p = P(orc, Cn=Cn)
+    i, j, k = interior_centre(idx)
+    n = idx[i, j, k]
+    U1 = np.zeros((m.n_nodes, 6))
+    U1[n, 1] = 2.0   # mu~ = e_n
+    R = m.residual(p, CH, U1, np.zeros_like(U1))
+    for o in CF.offsets():
+        nb = idx[i + o[0], j + o[1], k + o[2]]
+        assert R[nb, 1] == pytest.approx(-CF.mass(o, h), rel=1e-14)
+    U1[:] = 0
+    U1[n, 0] = 2e-6  # phi~ = 1e-6 e_n: psi' ~ -phi~ (cubic part 1e-18)
+    R = m.residual(p, CH, U1, np.zeros_like(U1))
+    for o in CF.offsets():
+        nb = idx[i + o[0], j + o[1], k + o[2]]
+        exp = 1e-6 * (Cn ** 2 * CF.stiffness(o, h) - CF.mass(o, h))
+        assert R[nb, 1] == pytest.approx(exp, rel=1e-9, abs=1e-22)
+
+
+# ----------------------------------------- hanging-node gather/scatter ----
+def test_partition_of_unity_adaptive(orc, adaptive):
+    m = adaptive
+    p = P(orc)
+    U1 = np.zeros((m.n_nodes, 6))
+    U1[:, 0] = p.dt
+    R = m.residual(p, CH, U1, np.zeros_like(U1))
+    assert R[:, 0].sum() == pytest.approx(1.0, rel=1e-14)
+    assert (R[:, 0] > 0).all()
+
+
+def test_patch_test_adaptive(orc, adaptive):
+    """For a linear mu~ the stiffness rows of interior nodes vanish on a 2:1
+    mesh with hanging nodes (the constrained space reproduces linears)."""
+    m = adaptive
+    p = P(orc, Cn=1.0, Pe=1.0)
+    x = m.node_xyz()
+    U1 = np.zeros((m.n_nodes, 6))
+    U1[:, 1] = 2 * (0.3 + 1.7 * x[:, 0] - 0.6 * x[:, 1] + 2.2 * x[:, 2])
+    R = m.residual(p, CH, U1, np.zeros_like(U1))
+    interior = (m.bflags & 1) == 0
+    assert interior.sum() > 100
+    assert np.abs(R[interior, 0]).max() < 1e-13
+    assert np.abs(R[~interior, 0]).max() > 1e-3
+
+
+# ------------------------------------------------ CH block identities ----
+def random_ch_state(m, seed, amp=0.8):
+    rng = np.random.default_rng(seed)
+    n = m.n_nodes
+    U0 = np.zeros((n, 6))
+    U1 = np.zeros((n, 6))
+    U0[:, 0] = rng.uniform(-amp, amp, n)
+    U1[:, 0] = U0[:, 0] + rng.normal(0, 0.1, n)
+    U0[:, 1] = rng.normal(0, 0.5, n)
+    U1[:, 1] = rng.normal(0, 0.5, n)
+    U0[:, 2:5] = rng.normal(0, 0.3, (n, 3))
+    U1[:, 2:5] = rng.normal(0, 0.3, (n, 3))
+    U0[:, 5] = rng.normal(0, 1, n)
+    U1[:, 5] = rng.normal(0, 1, n)
+    return U1, U0
+
+
+def test_ch_constant_state(orc, adaptive):
+    m = adaptive
+    p = P(orc)
+    c = 0.37
+    U = np.zeros((m.n_nodes, 6))
+    U[:, 0] = c
+    U[:, 1] = c ** 3 - c
+    R = m.residual(p, CH, U, U)
+    assert np.abs(R).max() < 1e-15
+
+
+def test_ch_mass_identity(orc, adaptive):
+    """Testing with q = 1 (Prop. 1): the phi rows sum to the change of the
+    integral of phi over dt, for any states; the integral of a trilinear
+    field over a cube of side h is h^3 times the mean of its corner values."""
+    m = adaptive
+    p = P(orc)
+    U1, U0 = random_ch_state(m, 3)
+    R = m.residual(p, CH, U1, U0)
+
+    def integral(u):
+        hv = np.array([(m.hang_w[m.hang_off[i]:m.hang_off[i + 1]] *
+                        u[m.hang_ids[m.hang_off[i]:m.hang_off[i + 1]]]).sum()
+                       for i in range(m.hang_xyz.shape[0])])
+        cv = np.where(m.elem >= 0, u[np.maximum(m.elem, 0)], hv[np.maximum(-1 - m.elem, 0)])
+        h = 2.0 ** (-m.leaves[:, 3].astype(float))
+        return float((h ** 3 * cv.mean(axis=1)).sum())
+
+    lhs = R[:, 0].sum()
+    rhs = (integral(U1[:, 0]) - integral(U0[:, 0])) / p.dt
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+    mass1, _ = m.diagnostics(p, U1)
+    assert mass1 == pytest.approx(integral(U1[:, 0]), rel=1e-13)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ch_energy_identity(orc, uni3, seed):
+    """dt mu~^T R_phi + (phi^{k+1}-phi^k)^T R_mu equals
+    F(phi^{k+1}) - F(phi^k) - int phi~/4 (dphi)^3 - dt int grad mu~ . v~ phi~
+    + dt/(Pe Cn) ||grad mu~||^2 with F = int psi + Cn^2/2 |grad phi|^2.
+    This is the energy argument of Sec. 3.2 (Prop. 2 is exact for the quartic
+    psi with the midpoint): it holds for any states, at quadrature level."""
+    m, idx = uni3
+    h = 1 / 8
+    p = P(orc, Cn=0.3, Pe=2.0, dt=0.05)
+    U1, U0 = random_ch_state(m, 10 + seed)
+    R = m.residual(p, CH, U1, U0)
+    mut = 0.5 * (U1[:, 1] + U0[:, 1])
+    dphi = U1[:, 0] - U0[:, 0]
+    lhs = p.dt * (mut * R[:, 0]).sum() + (dphi * R[:, 1]).sum()
+
+    def F(phi):
+        v, g = UQ.qp_fields(phi, idx, h)
+        return UQ.integrate(0.25 * (v ** 2 - 1) ** 2 + 0.5 * p.Cn ** 2 * (g ** 2).sum(axis=1), h)
+
+    pt, _ = UQ.qp_fields(0.5 * (U1[:, 0] + U0[:, 0]), idx, h)
+    dp, _ = UQ.qp_fields(dphi, idx, h)
+    _, gmu = UQ.qp_fields(mut, idx, h)
+    vt = [UQ.qp_fields(0.5 * (U1[:, 2 + d] + U0[:, 2 + d]), idx, h)[0] for d in range(3)]
+    adv = UQ.integrate(sum(gmu[:, d] * vt[d] for d in range(3)) * pt, h)
+    rhs = (F(U1[:, 0]) - F(U0[:, 0]) - UQ.integrate(pt / 4 * dp ** 3, h)
+           - p.dt * adv + p.dt / (p.Pe * p.Cn) * UQ.integrate((gmu ** 2).sum(axis=1), h))
+    assert lhs == pytest.approx(rhs, rel=1e-12, abs=1e-14)
+
+
+# ------------------------------------------------ NS block special cases --
+@pytest.mark.parametrize("phi,g", [(1.0, (0.0, -1.0, 0.0)), (-1.0, (0.0, -1.0, 0.0)),
+                                   (1.0, (0.0, 0.0, -1.0)), (-1.3, (0.6, 0.0, -0.8))])
+def test_ns_hydrostatic(orc, adaptive, phi, g):
+    """v = 0, constant phi (rho constant, pulled back when |phi| > 1), constant
+    mu (J = 0) and p = (We/Fr) rho g.x at both time levels: (1/We) grad p =
+    rho g / Fr, so R_m = R_c = 0 and every row vanishes."""
+    m = adaptive
+    p = P(orc, g=g)
+    rho_m = p.rho_minus
+    rho = 0.5 * (1 - rho_m) * np.clip(phi, -1, 1) + 0.5 * (1 + rho_m)
+    x = m.node_xyz()
+    U = np.zeros((m.n_nodes, 6))
+    U[:, 0] = phi
+    U[:, 1] = 0.7
+    U[:, 5] = (p.We / p.Fr) * rho * (x @ np.array(g))
+    R = m.residual(p, NS, U, U)
+    assert np.abs(R[:, 2:]).max() < 1e-13
+    # with the gravity term dropped from the pressure the rows do not vanish
+    U2 = U.copy()
+    U2[:, 5] = 0
+    R2 = m.residual(p, NS, U2, U2)
+    assert np.abs(R2[:, 2:]).max() > 1e-4
+
+
+def test_ns_uniform_velocity(orc, adaptive):
+    """A uniform velocity at both time levels (boundary rows carry it) on top of
+    the hydrostatic state: every convective term vanishes."""
+    m = adaptive
+    p = P(orc)
+    x = m.node_xyz()
+    U = np.zeros((m.n_nodes, 6))
+    U[:, 0] = 1.0
+    U[:, 2:5] = [0.3, -0.2, 0.5]
+    U[:, 5] = (p.We / p.Fr) * (x @ np.array(p.g[:]))
+    R = m.residual(p, NS, U, U)
+    assert np.abs(R[:, 2:]).max() < 1e-13
+
+
+def _tau_m(p, h, v=(0.0, 0.0, 0.0), rho=1.0, eta=1.0, J=(0.0, 0.0, 0.0)):
+    G = 4 / h ** 2
+    v = np.array(v)
+    br = (4 / p.dt ** 2 + G * v @ v + G * (v @ np.array(J)) / (rho * p.Pe)
+          + p.C_I * (eta / (rho * p.Re)) ** 2 * 3 * G ** 2)
+    return br ** -0.5
+
+
+def test_ns_capillary_closed_form(orc, uni3):
+    """phi~ = xy (phi^k = 2xy - 3, phi^{k+1} = 3 pulled back to 1, so rho = eta = 1),
+    v = p = 0, no gravity: the capillary divergence is (Cn/We)(x, y, 0) and, by
+    exact integration by parts on interior rows,
+      R_v,a = [Cn/We + 3 tau_m^2 (Cn/We)^2] (x_a, y_a, 0) h^3,
+      R_p,a = -2 tau_m (Cn/We) h^3.
+    Pins the capillary Galerkin term (with phi~), the strong capillary term,
+    the continuity stabilisation sign and the tau_m^2 R R term."""
+    m, idx = uni3
+    h = 1 / 8
+    p = P(orc, g=(0.0, 0.0, 0.0))
+    x = m.node_xyz()
+    U1 = np.zeros((m.n_nodes, 6))
+    U0 = np.zeros((m.n_nodes, 6))
+    U1[:, 0] = 3.0
+    U0[:, 0] = 2 * x[:, 0] * x[:, 1] - 3.0
+    R = m.residual(p, NS, U1, U0)
+    tm = _tau_m(p, h)
+    cw = p.Cn / p.We
+    inner = np.all((m.nodes > 0) & (m.nodes < 8), axis=1)
+    a = np.nonzero(inner)[0]
+    np.testing.assert_allclose(R[a, 2], (cw + 3 * tm ** 2 * cw ** 2) * x[a, 0] * h ** 3, rtol=1e-12)
+    np.testing.assert_allclose(R[a, 3], (cw + 3 * tm ** 2 * cw ** 2) * x[a, 1] * h ** 3, rtol=1e-12)
+    assert np.abs(R[a, 4]).max() < 1e-17
+    np.testing.assert_allclose(R[a, 5], -2 * tm * cw * h ** 3, rtol=1e-12)
+
+
+def _jvp_closed_form(p, h, o, c, J, rho=1.0):
+    """Interior-row JVP entries for dv = e_x at node b = a + o, around a base
+    state with R_m = R_c = 0, uniform velocity c, constant flux J, constant
+    rho and eta = 1 (terms proportional to the base residuals vanish):
+      x-row: M/dt + rho/2 C_c + 1/(2Pe) C_J + (1/(2 Re)) K
+             + tau_m (c.grad N_a)(rho N_b/dt + rho/2 c.grad N_b + 1/(2Pe) J.grad N_b)
+             + (1/Pe)(tau_m/rho)(J.grad N_a)(rho N_b/dt + ...)
+             + (rho tau_c/(2 We)) dN_a/dx dN_b/dx
+      y,z rows: (rho tau_c/(2 We)) dN_a/dx_i dN_b/dx
+      p row: (N_a, dN_b/dx)/2 + (tau_m/rho)(dN_a/dx, rho N_b/dt + ...)"""
+    tm = _tau_m(p, h, v=c, rho=rho, J=J)
+    tc = h ** 2 / (12 * tm)
+    c = np.array(c)
+    J = np.array(J)
+    M = CF.mass(o, h)
+    conv = lambda w: sum(w[j] * CF.n_dN(j, o, h) for j in range(3))          # (N_a, w.grad N_b)
+    supg_m = lambda w: sum(w[j] * CF.dN_n(j, o, h) for j in range(3))        # (w.grad N_a, N_b)
+    supg_k = lambda w1, w2: sum(w1[j] * w2[k] * CF.grad_grad(j, k, o, h)
+                                for j in range(3) for k in range(3))
+    # dR_m,x tested against (c.grad N_a) tau_m and (J.grad N_a) tau_m / (rho Pe)
+    def tested(w, coeff):
+        return coeff * (rho * supg_m(w) / p.dt + 0.5 * rho * supg_k(w, c)
+                        + 0.5 / p.Pe * supg_k(w, J))
+    row_x = (rho * M / p.dt + 0.5 * rho * conv(c) + 0.5 / p.Pe * conv(J)
+             + 0.5 / p.Re * CF.stiffness(o, h)
+             + tested(c, tm) + tested(J, tm / (rho * p.Pe))
+             + rho * tc / (2 * p.We) * CF.grad_grad(0, 0, o, h))
+    row_y = rho * tc / (2 * p.We) * CF.grad_grad(1, 0, o, h)
+    row_z = rho * tc / (2 * p.We) * CF.grad_grad(2, 0, o, h)
+    e_x = np.array([1.0, 0.0, 0.0])
+    row_p = (0.5 * CF.n_dN(0, o, h)
+             + (tm / rho) * (rho * CF.dN_n(0, o, h) / p.dt + 0.5 * rho * supg_k(e_x, c)
+                             + 0.5 / p.Pe * supg_k(e_x, J)))
+    return np.array([row_x, row_y, row_z, row_p])
+
+
+@pytest.mark.parametrize("case", ["rest", "uniform_flow", "flux", "both"])
+def test_ns_jvp_closed_form(orc, uni3, case):
+    """Linearisation about states where R_m = R_c = 0 (so every term that
+    multiplies a base residual, including d tau_m, drops out): the JVP rows of
+    interior nodes are tensor-product closed forms.  'uniform_flow' pins the
+    Galerkin and fine-scale convection terms with tau_m(v); 'flux' pins the
+    mass-flux terms with J = -(alpha/Cn) grad mu~."""
+    m, idx = uni3
+    h = 1 / 8
+    p = P(orc, dt=0.02, rho_minus=0.25)
+    x = m.node_xyz()
+    c = {"rest": (0, 0, 0), "uniform_flow": (0.4, -0.3, 0.25), "flux": (0, 0, 0),
+         "both": (0.2, 0.1, -0.3)}[case]
+    grad_mu = {"rest": (0, 0, 0), "uniform_flow": (0, 0, 0), "flux": (0.5, 0.8, -0.3),
+               "both": (-0.4, 0.3, 0.6)}[case]
+    alpha = 0.5 * (1 - p.rho_minus)
+    J = tuple(-alpha / p.Cn * gm for gm in grad_mu)
+    U = np.zeros((m.n_nodes, 6))
+    U[:, 0] = 1.0
+    U[:, 1] = x @ np.array(grad_mu, float)
+    U[:, 2:5] = c
+    U[:, 5] = (p.We / p.Fr) * (x @ np.array(p.g[:]))
+    i, j, k = interior_centre(idx)
+    b = idx[i, j, k]
+    dU = np.zeros_like(U)
+    dU[b, 2] = 1.0
+    out = m.jvp(p, NS, U, U, dU)
+    for o in CF.offsets():
+        a = idx[i - o[0], j - o[1], k - o[2]]   # b = a + o
+        exp = _jvp_closed_form(p, h, o, c, J)
+        np.testing.assert_allclose(out[a, 2:], exp, rtol=1e-11, atol=1e-14 * np.abs(exp).max())
+
+
+# ------------------------------------------- Jacobian-vector products ----
+def random_state(m, seed):
+    rng = np.random.default_rng(seed)
+    n = m.n_nodes
+    U0 = np.zeros((n, 6))
+    U0[:, 0] = rng.uniform(-1.1, 1.1, n)
+    U0[:, 1] = rng.normal(0, 0.5, n)
+    U0[:, 2:5] = rng.normal(0, 0.3, (n, 3))
+    U0[:, 5] = rng.normal(0, 1, n)
+    U1 = U0 + rng.normal(0, 0.05, U0.shape)
+    return U1, U0
+
+
+@pytest.mark.parametrize("block", [CH, NS])
+@pytest.mark.parametrize("meshkind", ["uniform4", "adaptive"])
+def test_jvp_matches_central_differences(orc, adaptive, block, meshkind):
+    m = orc.Mesh((1, 1, 1), 2, 2) if meshkind == "uniform4" else adaptive
+    p = P(orc, dt=0.05)
+    U1, U0 = random_state(m, 5)
+    f = slice(0, 2) if block == CH else slice(2, 6)
+    dU = np.zeros_like(U1)
+    dU[:, f] = np.random.default_rng(6).normal(0, 1, (U1.shape[0], f.stop - f.start))
+    Jd = m.jvp(p, block, U1, U0, dU)
+    eps = 1e-6 * np.linalg.norm(U1) / np.linalg.norm(dU)
+    Rp = m.residual(p, block, U1 + eps * dU, U0)
+    Rm = m.residual(p, block, U1 - eps * dU, U0)
+    fd = (Rp - Rm) / (2 * eps)
+    err = np.linalg.norm(fd[:, f] - Jd[:, f]) / np.linalg.norm(Jd[:, f])
+    assert err < 1e-7
+    other = slice(2, 6) if block == CH else slice(0, 2)
+    assert np.abs(Jd[:, other]).max() == 0.0
+
+
+@pytest.mark.parametrize("block", [CH, NS])
+def test_jvp_linearity(orc, adaptive, block):
+    m = adaptive
+    p = P(orc)
+    U1, U0 = random_state(m, 8)
+    rng = np.random.default_rng(9)
+    d1, d2 = rng.normal(size=U1.shape), rng.normal(size=U1.shape)
+    a, b = 0.7, -1.9
+    lhs = m.jvp(p, block, U1, U0, a * d1 + b * d2)
+    rhs = a * m.jvp(p, block, U1, U0, d1) + b * m.jvp(p, block, U1, U0, d2)
+    assert np.linalg.norm(lhs - rhs) <= 1e-13 * np.linalg.norm(lhs)
+
+
+@pytest.mark.parametrize("block", [CH, NS])
+def test_diag_blocks_are_jacobian_diagonal(orc, block):
+    """Node-block diagonal vs. columns of the Jacobian probed with unit
+    directions, on a small 2:1 mesh."""
+    leaves = W.random_leaves((1, 1, 1), 3, 2, p_split=0.4, level_min=1)
+    m = orc.Mesh((1, 1, 1), 0, 3, leaves=leaves)
+    assert m.hang_xyz.shape[0] > 0
+    p = P(orc)
+    U1, U0 = random_state(m, 12)
+    B = m.diag_blocks(p, block, U1, U0)
+    f0, nf = (0, 2) if block == CH else (2, 4)
+    rng = np.random.default_rng(0)
+    for n in rng.choice(m.n_nodes, 12, replace=False):
+        for fc in range(nf):
+            dU = np.zeros_like(U1)
+            dU[n, f0 + fc] = 1.0
+            col = m.jvp(p, block, U1, U0, dU)
+            np.testing.assert_allclose(B[n, :, fc], col[n, f0:f0 + nf], rtol=1e-12, atol=1e-14)
+
+
+def test_boundary_rows(orc, adaptive):
+    m = adaptive
+    p = P(orc)
+    U1, U0 = random_state(m, 13)
+    R = m.residual(p, NS, U1, U0)
+    b = (m.bflags & 1) != 0
+    np.testing.assert_array_equal(R[b, 2:5], U1[b, 2:5] - U0[b, 2:5])
+    assert R[0, 5] == U1[0, 5] - U0[0, 5]
+    assert np.abs(R[:, :2]).max() == 0.0
+
+
+def test_tau_bracket_error(orc, uni3):
+    """A velocity against a strong flux makes v.G.J negative enough to turn the
+    tau_m bracket non-positive: reported as an error, not a NaN."""
+    m, _ = uni3
+    p = P(orc, dt=10.0, Re=1e6)
+    x = m.node_xyz()
+    U = np.zeros((m.n_nodes, 6))
+    U[:, 0] = 0.0
+    U[:, 1] = 50.0 * x[:, 0]           # J = -(alpha/Cn) * 50 e_x
+    U[:, 2] = 1.0                       # v along +x: v.G.J < 0
+    with pytest.raises(RuntimeError, match="tau_m"):
+        m.residual(p, NS, U, U)
