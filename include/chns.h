@@ -1,0 +1,207 @@
+/* chns.h -- C ABI of the MI355X (gfx950) matrix-free CHNS element loop.
+ *
+ * Implements the hot path of the Cahn-Hilliard Navier-Stokes method of
+ * Khanwale et al., "Simulating two-phase flows with thermodynamically
+ * consistent energy stable Cahn-Hilliard Navier-Stokes equations on parallel
+ * adaptive octree based meshes" (arXiv 1912.12453):
+ *   - the octree mesh of Sec. 4 (top-down refinement, 2:1 balance, hanging
+ *     nodes as element temporaries), built on the host and uploaded once;
+ *   - the residual and Jacobian-vector product of the two sub-problems of the
+ *     block iteration of Sec. 3 (Fig. 1): the Cahn-Hilliard block (phi, mu;
+ *     Def. 1 with the Crank-Nicolson averages) and the VMS-stabilised
+ *     Navier-Stokes block (v, p; Def. 2 of Sec. 3.4), on trilinear hexahedra;
+ *   - one Crank-Nicolson time step: the block iteration of Fig. 1 with a
+ *     Newton solve per block (Sec. 3.5) and right-preconditioned GMRES.
+ *
+ * Conventions
+ *   - All entry points return an int status (CHNS_OK = 0).  On a negative
+ *     status nothing useful was written; chns_last_error() returns a message
+ *     (thread-local, valid until the next call on the same thread).
+ *   - "device" pointers are addresses in HBM of the current HIP device
+ *     (hipMalloc'd or torch-allocated); the library never frees or keeps
+ *     them.  "stream" is a hipStream_t (NULL = the null stream); every device
+ *     operation of a call is enqueued on it and the call returns without
+ *     synchronising unless stated otherwise.
+ *   - State vectors are node-major with 6 doubles per independent node, in
+ *     the mesh's Morton node order: [phi, mu, u, v, w, p].
+ *   - Errors are never thrown across the ABI.
+ */
+#ifndef CHNS_H
+#define CHNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CHNS_OK = 0,
+  CHNS_NOT_CONVERGED = 1, /* chns_step: outputs and stats written (best iterate) */
+  CHNS_EINVAL = -1,       /* bad argument (null pointer, size, unknown enum)      */
+  CHNS_ENOMEM = -2,       /* device or host allocation failed                     */
+  CHNS_EHIP = -3,         /* a HIP runtime call failed                            */
+  CHNS_ENONFINITE = -4,   /* a NaN or Inf appeared in a residual norm             */
+  CHNS_ETAU = -5,         /* the tau_m bracket of Sec. 3.4 was not positive       */
+  CHNS_ENODEV = -6        /* no usable gfx950 device                              */
+};
+
+/* The two sub-problems of the block iteration (Sec. 3, Fig. 1). */
+enum { CHNS_BLOCK_CH = 0, CHNS_BLOCK_NS = 1 };
+/* Arithmetic of a Jacobian-vector product. */
+enum { CHNS_F64 = 0, CHNS_F32 = 1 };
+
+/* Non-dimensional parameters (Sec. 2).  rho(+1) = 1 and rho(-1) = rho_minus,
+ * i.e. rho = alpha phi + beta with alpha = (1 - rho_minus)/2,
+ * beta = (1 + rho_minus)/2; eta likewise with eta_minus.  gravity is the
+ * unit direction g^ of the momentum equation ((0,-1,0) in the paper).  C_I is
+ * the constant of tau_m (6 in the paper).  flux_mode selects the mass flux of
+ * the thermo-consistency relation: 0 -> J = -(alpha/Cn) grad mu (the value
+ * that makes the continuity equation agree with the CH equation), 1 ->
+ * J = -alpha grad mu (the relation as printed). */
+typedef struct {
+  double Cn, Pe, Re, We, Fr;
+  double rho_minus, eta_minus;
+  double dt;
+  double gravity[3];
+  double C_I;
+  int32_t flux_mode;
+} chns_params;
+
+/* Refinement indicator phi0, evaluated on the host in batches: out[i] =
+ * phi0(xyz[3i], xyz[3i+1], xyz[3i+2]) for i < n. */
+typedef void (*chns_phi0_fn)(const double* xyz, int64_t n, double* out, void* user);
+
+/* Mesh description (Sec. 4 "Refinement").  The domain is a brick of
+ * trees[0] x trees[1] x trees[2] unit cubes; level l means leaf side 2^-l.
+ * Either explicit leaves are given (n_leaves rows of (x, y, z, level) in
+ * integer units of 2^-level_max, tiling the domain; level_min and phi0 are
+ * then ignored), or the mesh is refined top-down from the tree roots: an
+ * octant below level_max is split when it is below level_min, or when phi0
+ * sampled at its 8 corners and centre has |phi0| < band somewhere or changes
+ * sign.  The result is then 2:1 balanced over face, edge and corner
+ * neighbours (Sec. 4 "2:1 Balancing").  level_max <= 16. */
+typedef struct {
+  int32_t trees[3];
+  int32_t level_min, level_max;
+  chns_phi0_fn phi0; /* may be NULL: uniform refinement to level_min */
+  void* user;
+  double band;
+  const int32_t* leaves; /* host, optional */
+  int64_t n_leaves;
+} chns_mesh_spec;
+
+typedef struct chns_mesh chns_mesh;
+
+typedef struct {
+  int64_t n_leaves;       /* elements                                      */
+  int64_t n_nodes;        /* independent nodes (unknowns per field)        */
+  int64_t n_hanging;      /* hanging nodes (not stored as unknowns)        */
+  int64_t n_constraint;   /* entries of the flattened hanging constraints  */
+  int32_t level_max;      /* integer unit = 2^-level_max                   */
+  int32_t max_fanin;      /* largest number of parents of a hanging node   */
+  int64_t device_bytes;   /* HBM held by the mesh once uploaded            */
+} chns_mesh_stats;
+
+/* Builds the balanced octree, numbers its nodes and flattens the hanging
+ * constraints on the host (no GPU needed).  The device copy is made on first
+ * use by a device entry point (or by chns_mesh_upload).  *out is owned by the
+ * library; release it with chns_mesh_free. */
+int chns_mesh_build(const chns_mesh_spec* spec, chns_mesh** out);
+int chns_mesh_info(const chns_mesh* mesh, chns_mesh_stats* out);
+/* Host copies of the mesh arrays, caller-allocated from chns_mesh_info:
+ *   leaves [n_leaves*4]  (x, y, z, level), Morton order;
+ *   elem   [n_leaves*8]  corner c = i + 2j + 4k: node id >= 0, or -1-h for
+ *                        hanging node h;
+ *   nodes  [n_nodes*3]   integer coordinates of the independent nodes;
+ *   bflags [n_nodes]     bit0: on the domain boundary; bit1: pressure pin;
+ *   hang_xyz [n_hanging*3], hang_off [n_hanging+1], hang_ids [n_constraint],
+ *   hang_w [n_constraint]: hanging node h = sum_t hang_w[t] * node hang_ids[t]
+ *                        for hang_off[h] <= t < hang_off[h+1].
+ * Any pointer may be NULL to skip that array. */
+int chns_mesh_arrays(const chns_mesh* mesh, int32_t* leaves, int32_t* elem, int32_t* nodes,
+                     uint8_t* bflags, int32_t* hang_xyz, int64_t* hang_off, int32_t* hang_ids,
+                     double* hang_w);
+/* Node coordinates (physical, [n_nodes*3]) and boundary flags, host arrays. */
+int chns_mesh_nodes(const chns_mesh* mesh, double* xyz, uint8_t* bflags);
+/* Copies the mesh to the current device on `stream` (optional; the device
+ * entry points upload on first use). */
+int chns_mesh_upload(chns_mesh* mesh, void* stream);
+int chns_mesh_free(chns_mesh* mesh);
+
+/* Residual of one block (Sec. 3.4, Def. 2; CH rows from Def. 1) at the
+ * iterate U_new given the previous step U_old (device, n_nodes*6 doubles
+ * each).  R (device, n_nodes*6 doubles) receives the block's rows; the other
+ * block's entries are set to 0.  NS boundary rows: velocity rows of boundary
+ * nodes read v_new - v_old (the wall data travels with the state: no-slip
+ * walls keep v = 0), the pressure row of the pinned node reads
+ * p_new - p_old.  Returns CHNS_ETAU (after the launch completes) when a
+ * tau_m bracket was not positive. */
+int chns_residual(chns_mesh* mesh, const chns_params* params, int block, const double* U_new,
+                  const double* U_old, double* R, void* stream);
+
+/* Jacobian-vector product of the block residual with respect to the block's
+ * unknowns at U_new (Sec. 3.5: the analytic Jacobian, here applied without
+ * being assembled).  dU and JdU are device arrays of n_nodes*6 elements of
+ * type double (prec = CHNS_F64) or float (prec = CHNS_F32, computed in FP32
+ * with FP32 accumulation); only the block's entries of dU are read and the
+ * other block's entries of JdU are set to 0.  Boundary rows are identity
+ * rows. */
+int chns_jvp(chns_mesh* mesh, const chns_params* params, int block, const double* U_new,
+             const double* U_old, const void* dU, void* JdU, int prec, void* stream);
+
+/* Node-block diagonal of the block Jacobian (2x2 for CH, 4x4 for NS per node,
+ * row-major, device, n_nodes*nf*nf doubles), including the hanging-node
+ * couplings; boundary rows are identity rows. */
+int chns_diag_blocks(chns_mesh* mesh, const chns_params* params, int block,
+                     const double* U_new, const double* U_old, double* D, void* stream);
+
+/* Integral of phi and total energy of U (device, n_nodes*6): kinetic
+ * (1/2) rho |v|^2, free (1/(Cn We)) (psi(phi) + Cn^2/2 |grad phi|^2) and
+ * gravitational (1/Fr) rho (-g^ . x) parts (Sec. 2, eqn energy_functional).
+ * Synchronises the stream; results on the host. */
+int chns_diagnostics(chns_mesh* mesh, const chns_params* params, const double* U,
+                     double* mass, double* energy, void* stream);
+
+typedef struct {
+  double newton_rtol;  /* 1e-8: ||R|| <= max(rtol ||R_0||, atol) per block    */
+  double newton_atol;  /* 1e-12                                              */
+  double block_tol;    /* 1e-4: max change of all fields between two sweeps  */
+  double gmres_rtol;   /* 1e-7 (FP64) / 1e-5 is typical for mixed precision  */
+  int32_t newton_max_it_ch, newton_max_it_ns; /* 20, 40                      */
+  int32_t gmres_restart;                      /* 30                          */
+  int32_t gmres_max_it;                       /* 1000 per linear solve       */
+  int32_t block_max_it;                       /* 10                          */
+  int32_t block_min_it;                       /* 1: sweeps 0 and 1 always run */
+  int32_t precision;   /* 0: FP64 throughout; 1: FP32 inner Krylov (JVP,
+                          preconditioner, basis) with FP64 dot products,
+                          Hessenberg, update and Newton residual            */
+  int32_t precond;     /* 0: point Jacobi; 1: node-block Jacobi             */
+} chns_solver_opts;
+
+typedef struct {
+  int32_t block_its;
+  int32_t newton_its[2]; /* indexed by CHNS_BLOCK_*, summed over sweeps      */
+  int32_t gmres_its[2];
+  int32_t converged;     /* every Newton solve and the block iteration met
+                            their tolerances                               */
+  double rel_res[2];     /* final ||R|| / ||R_0|| of the last solve per block */
+  double mass, energy;   /* diagnostics of U^{k+1}                          */
+  double t_ms;           /* wall time of the step                           */
+} chns_step_stats;
+
+/* One Crank-Nicolson step (Fig. 1): U (device, n_nodes*6) holds U^k on entry
+ * and U^{k+1} on return.  Synchronises the stream (the Newton and GMRES
+ * control decisions are taken on the host from device-computed FP64 norms).
+ * Work buffers are allocated on first use and kept with the mesh.  Returns
+ * CHNS_NOT_CONVERGED with U and stats written when a tolerance was missed. */
+int chns_step(chns_mesh* mesh, const chns_params* params, const chns_solver_opts* opts,
+              double* U, chns_step_stats* out, void* stream);
+
+const char* chns_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHNS_H */

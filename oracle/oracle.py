@@ -59,9 +59,9 @@ class StepStats(C.Structure):
 _lib = None
 
 
-def build():
-    from . import build as _b
-    return _b.build()
+def build(verbose=False):
+    from . import build_oracle
+    return build_oracle.build(verbose)
 
 
 def lib():

@@ -1,0 +1,309 @@
+"""ctypes binding of libchns.so (the C ABI declared in include/chns.h).
+
+Argument marshalling only: every step of the element loop, the Krylov vector
+operations and the reductions run in the library's HIP kernels.  Device
+arrays are torch tensors on the current HIP device (float64, or float32 for
+FP32 Jacobian-vector products); the stream is torch's current stream unless
+one is given.  The library must be built (``python -m
+paper_1912_12453_amd.build`` or ``__graft_entry__.build()``); there is no
+fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchns.so")
+
+CHNS_OK = 0
+CHNS_NOT_CONVERGED = 1
+CHNS_EINVAL = -1
+CHNS_ENOMEM = -2
+CHNS_EHIP = -3
+CHNS_ENONFINITE = -4
+CHNS_ETAU = -5
+CHNS_ENODEV = -6
+CHNS_BLOCK_CH = 0
+CHNS_BLOCK_NS = 1
+CHNS_F64 = 0
+CHNS_F32 = 1
+
+PHI0_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double), C.c_void_p)
+
+
+class ChnsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libchns error {code}: {msg}")
+        self.code = code
+
+
+class chns_params(C.Structure):
+    _fields_ = [("Cn", C.c_double), ("Pe", C.c_double), ("Re", C.c_double), ("We", C.c_double),
+                ("Fr", C.c_double), ("rho_minus", C.c_double), ("eta_minus", C.c_double),
+                ("dt", C.c_double), ("gravity", C.c_double * 3), ("C_I", C.c_double),
+                ("flux_mode", C.c_int32)]
+
+
+class chns_mesh_spec(C.Structure):
+    _fields_ = [("trees", C.c_int32 * 3), ("level_min", C.c_int32), ("level_max", C.c_int32),
+                ("phi0", PHI0_FN), ("user", C.c_void_p), ("band", C.c_double),
+                ("leaves", C.POINTER(C.c_int32)), ("n_leaves", C.c_int64)]
+
+
+class chns_mesh_stats(C.Structure):
+    _fields_ = [("n_leaves", C.c_int64), ("n_nodes", C.c_int64), ("n_hanging", C.c_int64),
+                ("n_constraint", C.c_int64), ("level_max", C.c_int32), ("max_fanin", C.c_int32),
+                ("device_bytes", C.c_int64)]
+
+
+class chns_solver_opts(C.Structure):
+    _fields_ = [("newton_rtol", C.c_double), ("newton_atol", C.c_double),
+                ("block_tol", C.c_double), ("gmres_rtol", C.c_double),
+                ("newton_max_it_ch", C.c_int32), ("newton_max_it_ns", C.c_int32),
+                ("gmres_restart", C.c_int32), ("gmres_max_it", C.c_int32),
+                ("block_max_it", C.c_int32), ("block_min_it", C.c_int32),
+                ("precision", C.c_int32), ("precond", C.c_int32)]
+
+
+class chns_step_stats(C.Structure):
+    _fields_ = [("block_its", C.c_int32), ("newton_its", C.c_int32 * 2),
+                ("gmres_its", C.c_int32 * 2), ("converged", C.c_int32),
+                ("rel_res", C.c_double * 2), ("mass", C.c_double), ("energy", C.c_double),
+                ("t_ms", C.c_double)]
+
+    def as_dict(self):
+        return {"block_its": self.block_its, "newton_its": list(self.newton_its),
+                "gmres_its": list(self.gmres_its), "converged": bool(self.converged),
+                "rel_res": list(self.rel_res), "mass": self.mass, "energy": self.energy,
+                "t_ms": self.t_ms}
+
+
+_lib = None
+
+
+def lib():
+    """Loads libchns.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python -m paper_1912_12453_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        L.chns_last_error.restype = C.c_char_p
+        L.chns_mesh_build.argtypes = [C.POINTER(chns_mesh_spec), C.POINTER(vp)]
+        L.chns_mesh_info.argtypes = [vp, C.POINTER(chns_mesh_stats)]
+        L.chns_mesh_arrays.argtypes = [vp] + [vp] * 8
+        L.chns_mesh_nodes.argtypes = [vp, vp, vp]
+        L.chns_mesh_upload.argtypes = [vp, vp]
+        L.chns_mesh_free.argtypes = [vp]
+        L.chns_residual.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp]
+        L.chns_jvp.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp, C.c_int, vp]
+        L.chns_diag_blocks.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp]
+        L.chns_diagnostics.argtypes = [vp, C.POINTER(chns_params), vp, dp, dp, vp]
+        L.chns_step.argtypes = [vp, C.POINTER(chns_params), C.POINTER(chns_solver_opts), vp,
+                                C.POINTER(chns_step_stats), vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc, allow=()):
+    if rc != CHNS_OK and rc not in allow:
+        raise ChnsError(rc, lib().chns_last_error().decode())
+    return rc
+
+
+def make_params(physics):
+    """chns_params from a workloads.Physics (or any object with the same fields)."""
+    p = chns_params()
+    for f in ("Cn", "Pe", "Re", "We", "Fr", "rho_minus", "eta_minus", "dt", "C_I"):
+        setattr(p, f, float(getattr(physics, f)))
+    p.gravity = (C.c_double * 3)(*[float(v) for v in physics.g])
+    p.flux_mode = int(getattr(physics, "flux_mode", 0))
+    return p
+
+
+def make_opts(newton_rtol=1e-8, newton_atol=1e-12, block_tol=1e-4, gmres_rtol=1e-7,
+              newton_max_it_ch=20, newton_max_it_ns=40, gmres_restart=30, gmres_max_it=1000,
+              block_max_it=10, block_min_it=1, precision=0, precond=1):
+    return chns_solver_opts(newton_rtol, newton_atol, block_tol, gmres_rtol, newton_max_it_ch,
+                            newton_max_it_ns, gmres_restart, gmres_max_it, block_max_it,
+                            block_min_it, precision, precond)
+
+
+# ------------------------------------------------ C ABI, same names ------
+def chns_mesh_build(spec):
+    h = C.c_void_p()
+    _check(lib().chns_mesh_build(C.byref(spec), C.byref(h)))
+    return h
+
+
+def chns_mesh_info(mesh):
+    st = chns_mesh_stats()
+    _check(lib().chns_mesh_info(mesh, C.byref(st)))
+    return st
+
+
+def chns_mesh_upload(mesh, stream=None):
+    _check(lib().chns_mesh_upload(mesh, _stream(stream)))
+
+
+def chns_mesh_free(mesh):
+    _check(lib().chns_mesh_free(mesh))
+
+
+def chns_residual(mesh, params, block, U_new, U_old, R, stream=None):
+    _dev(U_new, "float64"), _dev(U_old, "float64"), _dev(R, "float64")
+    return _check(lib().chns_residual(mesh, C.byref(params), block, U_new.data_ptr(),
+                                      U_old.data_ptr(), R.data_ptr(), _stream(stream)))
+
+
+def chns_jvp(mesh, params, block, U_new, U_old, dU, JdU, prec=CHNS_F64, stream=None):
+    dt = "float64" if prec == CHNS_F64 else "float32"
+    _dev(U_new, "float64"), _dev(U_old, "float64"), _dev(dU, dt), _dev(JdU, dt)
+    return _check(lib().chns_jvp(mesh, C.byref(params), block, U_new.data_ptr(), U_old.data_ptr(),
+                                 dU.data_ptr(), JdU.data_ptr(), prec, _stream(stream)))
+
+
+def chns_diag_blocks(mesh, params, block, U_new, U_old, D, stream=None):
+    _dev(U_new, "float64"), _dev(U_old, "float64"), _dev(D, "float64")
+    return _check(lib().chns_diag_blocks(mesh, C.byref(params), block, U_new.data_ptr(),
+                                         U_old.data_ptr(), D.data_ptr(), _stream(stream)))
+
+
+def chns_diagnostics(mesh, params, U, stream=None):
+    _dev(U, "float64")
+    m, e = C.c_double(), C.c_double()
+    _check(lib().chns_diagnostics(mesh, C.byref(params), U.data_ptr(), C.byref(m), C.byref(e),
+                                  _stream(stream)))
+    return m.value, e.value
+
+
+def chns_step(mesh, params, opts, U, stream=None):
+    _dev(U, "float64")
+    st = chns_step_stats()
+    rc = _check(lib().chns_step(mesh, C.byref(params), C.byref(opts), U.data_ptr(), C.byref(st),
+                                _stream(stream)), allow=(CHNS_NOT_CONVERGED,))
+    return rc, st
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if str(t.dtype) != "torch." + dtype:
+        raise TypeError(f"expected torch.{dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+
+
+# ------------------------------------------------------- convenience ------
+class Mesh:
+    """A balanced octree mesh owned by libchns (Sec. 4)."""
+
+    def __init__(self, trees=(1, 1, 1), level_min=0, level_max=0, phi0=None, band=0.9,
+                 leaves=None):
+        spec = chns_mesh_spec()
+        spec.trees = (C.c_int32 * 3)(*trees)
+        spec.level_min = level_min
+        spec.level_max = level_max
+        spec.band = band
+        self._cb = PHI0_FN()
+        if phi0 is not None:
+            def cb(xyz, n, out, user, _f=phi0):
+                pts = np.ctypeslib.as_array(xyz, shape=(n, 3))
+                res = np.ctypeslib.as_array(out, shape=(n,))
+                res[:] = _f(pts)
+            self._cb = PHI0_FN(cb)
+        spec.phi0 = self._cb
+        self._leaves = None
+        if leaves is not None:
+            self._leaves = np.ascontiguousarray(leaves, dtype=np.int32).reshape(-1, 4)
+            spec.leaves = self._leaves.ctypes.data_as(C.POINTER(C.c_int32))
+            spec.n_leaves = self._leaves.shape[0]
+        self.h = chns_mesh_build(spec)
+        self.stats = chns_mesh_info(self.h)
+        self.trees = tuple(trees)
+        self.level_max = level_max
+
+    @classmethod
+    def from_spec(cls, ms):
+        """From a workloads.MeshSpec."""
+        return cls(ms.trees, ms.level_min, ms.level_max, ms.phi0, ms.band)
+
+    def close(self):
+        if getattr(self, "h", None):
+            chns_mesh_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_nodes(self):
+        return int(self.stats.n_nodes)
+
+    @property
+    def n_leaves(self):
+        return int(self.stats.n_leaves)
+
+    def arrays(self):
+        st = self.stats
+        E, n, nh, nc = st.n_leaves, st.n_nodes, st.n_hanging, st.n_constraint
+        out = {"leaves": np.zeros((E, 4), np.int32), "elem": np.zeros((E, 8), np.int32),
+               "nodes": np.zeros((n, 3), np.int32), "bflags": np.zeros(n, np.uint8),
+               "hang_xyz": np.zeros((nh, 3), np.int32), "hang_off": np.zeros(nh + 1, np.int64),
+               "hang_ids": np.zeros(nc, np.int32), "hang_w": np.zeros(nc, np.float64)}
+        _check(lib().chns_mesh_arrays(self.h, *[out[k].ctypes.data for k in
+                                                ("leaves", "elem", "nodes", "bflags", "hang_xyz",
+                                                 "hang_off", "hang_ids", "hang_w")]))
+        return out
+
+    def nodes(self):
+        xyz = np.zeros((self.n_nodes, 3))
+        bf = np.zeros(self.n_nodes, np.uint8)
+        _check(lib().chns_mesh_nodes(self.h, xyz.ctypes.data, bf.ctypes.data))
+        return xyz, bf
+
+    def upload(self, stream=None):
+        chns_mesh_upload(self.h, stream)
+        self.stats = chns_mesh_info(self.h)
+
+    def residual(self, params, block, U_new, U_old, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(U_new)
+        chns_residual(self.h, params, block, U_new, U_old, out)
+        return out
+
+    def jvp(self, params, block, U_new, U_old, dU, prec=CHNS_F64, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(dU)
+        chns_jvp(self.h, params, block, U_new, U_old, dU, out, prec)
+        return out
+
+    def diag_blocks(self, params, block, U_new, U_old):
+        import torch
+        nf = 2 if block == CHNS_BLOCK_CH else 4
+        D = torch.empty((self.n_nodes, nf, nf), dtype=torch.float64, device=U_new.device)
+        chns_diag_blocks(self.h, params, block, U_new, U_old, D)
+        return D
+
+    def diagnostics(self, params, U):
+        return chns_diagnostics(self.h, params, U)
+
+    def step(self, params, opts, U):
+        rc, st = chns_step(self.h, params, opts, U)
+        return rc, st

@@ -1,0 +1,751 @@
+// C ABI of libchns: mesh handles, device upload, element-loop launches and
+// the Crank-Nicolson step driver (block iteration of Fig. 1, Newton per block
+// as in Sec. 3.5, right-preconditioned GMRES with classical Gram-Schmidt).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hip"
+#include "linalg.hpp"
+
+using namespace chns;
+
+namespace {
+
+thread_local std::string g_err;
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(CHNS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+int dalloc(T** p, size_t count, int64_t* bytes) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(CHNS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  if (bytes) *bytes += (int64_t)(count * sizeof(T));
+  return CHNS_OK;
+}
+
+inline unsigned grid_for(int64_t threads, int block = 256) {
+  int64_t g = (threads + block - 1) / block;
+  return (unsigned)std::max<int64_t>(1, g);
+}
+inline unsigned grid_stride(int64_t n, int block = 256, int cap = 2048) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap, (n + block - 1) / block));
+}
+
+struct Workspace {
+  int64_t n = 0;
+  int restart = 0;
+  double *Uk = nullptr, *Uprev = nullptr, *r = nullptr, *x = nullptr;
+  double *D = nullptr, *Di = nullptr;
+  float *Di32 = nullptr, *U1f = nullptr, *U0f = nullptr;
+  double *V64 = nullptr, *Z64 = nullptr, *w64 = nullptr, *b64 = nullptr;
+  float *V32 = nullptr, *Z32 = nullptr, *w32 = nullptr, *b32 = nullptr;
+  double *part = nullptr, *dots = nullptr;
+  double* hdots = nullptr;  // pinned host
+  int* flag = nullptr;
+  int* hflag = nullptr;     // pinned host
+  int nb_part = 0;
+  int64_t bytes = 0;
+};
+
+}  // namespace
+
+struct chns_mesh {
+  HostMesh h;
+  int device = -1;
+  bool uploaded = false;
+  int32_t *d_elem = nullptr, *d_hoff = nullptr, *d_hids = nullptr, *d_bnodes = nullptr,
+          *d_anchor = nullptr;
+  uint8_t* d_level = nullptr;
+  double* d_hw = nullptr;
+  float* d_hw32 = nullptr;
+  int* d_flag = nullptr;
+  int* h_flag = nullptr;
+  double* d_part = nullptr;  // diagnostics partials
+  double* d_sum = nullptr;
+  double* h_sum = nullptr;
+  int64_t nb = 0;
+  int64_t device_bytes = 0;
+  Workspace ws;
+};
+
+namespace {
+
+dev::MeshView view(const chns_mesh* m) {
+  dev::MeshView v;
+  v.elem = m->d_elem;
+  v.level = m->d_level;
+  v.hoff = m->d_hoff;
+  v.hids = m->d_hids;
+  v.hw = m->d_hw;
+  v.hw32 = m->d_hw32;
+  v.E = (int64_t)m->h.leaf_key.size();
+  return v;
+}
+
+int phys_view(const chns_params* p, dev::PhysView& v) {
+  if (!p) return fail(CHNS_EINVAL, "params is NULL");
+  const double vals[] = {p->Cn, p->Pe, p->Re, p->We, p->Fr, p->rho_minus, p->eta_minus, p->dt,
+                         p->gravity[0], p->gravity[1], p->gravity[2], p->C_I};
+  for (double x : vals)
+    if (!std::isfinite(x)) return fail(CHNS_EINVAL, "non-finite parameter");
+  if (p->Cn <= 0 || p->Pe <= 0 || p->Re <= 0 || p->We <= 0 || p->Fr <= 0 || p->dt <= 0)
+    return fail(CHNS_EINVAL, "Cn, Pe, Re, We, Fr and dt must be positive");
+  if (p->rho_minus <= 0 || p->eta_minus <= 0)
+    return fail(CHNS_EINVAL, "density and viscosity ratios must be positive");
+  if (p->flux_mode != 0 && p->flux_mode != 1) return fail(CHNS_EINVAL, "flux_mode must be 0 or 1");
+  v.dt = p->dt;
+  v.inv_dt = 1.0 / p->dt;
+  v.Cn = p->Cn;
+  v.inv_PeCn = 1.0 / (p->Pe * p->Cn);
+  v.Cn2 = p->Cn * p->Cn;
+  v.alpha = 0.5 * (1.0 - p->rho_minus);
+  v.beta = 0.5 * (1.0 + p->rho_minus);
+  v.gamma = 0.5 * (1.0 - p->eta_minus);
+  v.xi = 0.5 * (1.0 + p->eta_minus);
+  v.kappa = p->flux_mode == 1 ? -v.alpha : -v.alpha / p->Cn;
+  v.inv_Pe = 1.0 / p->Pe;
+  v.inv_Re = 1.0 / p->Re;
+  v.inv_We = 1.0 / p->We;
+  v.inv_Fr = 1.0 / p->Fr;
+  v.CnWe = p->Cn / p->We;
+  for (int d = 0; d < 3; ++d) v.g[d] = p->gravity[d];
+  v.C_I = p->C_I;
+  return CHNS_OK;
+}
+
+int upload(chns_mesh* m, hipStream_t s) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (m->uploaded) {
+    if (dev != m->device) return fail(CHNS_EINVAL, "mesh was uploaded to another device");
+    return CHNS_OK;
+  }
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
+    return fail(CHNS_ENODEV, std::string("libchns is built for gfx950, device is ") + prop.gcnArchName);
+  const HostMesh& h = m->h;
+  const size_t E = h.leaf_key.size(), NH = h.hang_key.size(), NC = h.hang_ids.size();
+  if (h.max_fanin > 8) return fail(CHNS_EINVAL, "hanging-node fan-in above 8 is not supported");
+  std::vector<int32_t> anchor(E * 3), bnodes;
+  for (size_t e = 0; e < E; ++e) {
+    uint32_t x, y, z;
+    unkey(h.leaf_key[e], x, y, z);
+    anchor[3 * e] = (int32_t)x;
+    anchor[3 * e + 1] = (int32_t)y;
+    anchor[3 * e + 2] = (int32_t)z;
+  }
+  for (size_t i = 0; i < h.bflags.size(); ++i)
+    if (h.bflags[i] & 1) bnodes.push_back((int32_t)i);
+  std::vector<float> w32(h.hang_w.begin(), h.hang_w.end());
+  int64_t& B = m->device_bytes;
+  B = 0;
+  int rc;
+  if ((rc = dalloc(&m->d_elem, E * 8, &B)) || (rc = dalloc(&m->d_level, E, &B)) ||
+      (rc = dalloc(&m->d_anchor, E * 3, &B)) || (rc = dalloc(&m->d_hoff, NH + 1, &B)) ||
+      (rc = dalloc(&m->d_hids, NC, &B)) || (rc = dalloc(&m->d_hw, NC, &B)) ||
+      (rc = dalloc(&m->d_hw32, NC, &B)) || (rc = dalloc(&m->d_bnodes, bnodes.size(), &B)) ||
+      (rc = dalloc(&m->d_flag, 1, &B)) || (rc = dalloc(&m->d_part, E * 2, &B)) ||
+      (rc = dalloc(&m->d_sum, 2, &B)))
+    return rc;
+  HIPCHK(hipHostMalloc((void**)&m->h_flag, sizeof(int)));
+  HIPCHK(hipHostMalloc((void**)&m->h_sum, 2 * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(m->d_elem, h.elem.data(), E * 8 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(m->d_level, h.leaf_level.data(), E, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(m->d_anchor, anchor.data(), E * 3 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(m->d_hoff, h.hang_off.data(), (NH + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (NC) {
+    HIPCHK(hipMemcpyAsync(m->d_hids, h.hang_ids.data(), NC * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(m->d_hw, h.hang_w.data(), NC * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(m->d_hw32, w32.data(), NC * sizeof(float), hipMemcpyHostToDevice, s));
+  }
+  if (!bnodes.empty())
+    HIPCHK(hipMemcpyAsync(m->d_bnodes, bnodes.data(), bnodes.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  m->nb = (int64_t)bnodes.size();
+  // the host vectors above must outlive the copies
+  HIPCHK(hipStreamSynchronize(s));
+  m->device = dev;
+  m->uploaded = true;
+  return CHNS_OK;
+}
+
+int check_mesh(chns_mesh* m, hipStream_t s) {
+  if (!m) return fail(CHNS_EINVAL, "mesh is NULL");
+  return upload(m, s);
+}
+
+// ----------------------------------------------------------- launches ----
+// Residual of a block into R (ld, off), zeroing R's other entries of each row.
+int launch_residual(chns_mesh* m, const dev::PhysView& pv, int block, const double* U1,
+                    const double* U0, double* R, int ld, int off, hipStream_t s, bool check_tau) {
+  const int64_t E = (int64_t)m->h.leaf_key.size(), n = (int64_t)m->h.node_key.size();
+  const auto mv = view(m);
+  hipLaunchKernelGGL(dev::k_fill<double>, dim3(grid_stride(n * ld)), dim3(256), 0, s, R, n * ld, 0.0);
+  if (block == CHNS_BLOCK_CH) {
+    hipLaunchKernelGGL(dev::k_ch_residual<double>, dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, U1,
+                       U0, R, ld, off);
+    HIPCHK(hipGetLastError());
+    return CHNS_OK;
+  }
+  hipLaunchKernelGGL(dev::k_fill<int>, dim3(1), dim3(64), 0, s, m->d_flag, (int64_t)1, 0);
+  hipLaunchKernelGGL(dev::k_ns_residual<double>, dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, U1, U0,
+                     R, ld, off, m->d_flag);
+  hipLaunchKernelGGL(dev::k_ns_bc_residual, dim3(grid_for(std::max<int64_t>(m->nb, 1))), dim3(256), 0, s,
+                     m->d_bnodes, m->nb, U1, U0, R, ld, off);
+  HIPCHK(hipGetLastError());
+  if (check_tau) {
+    HIPCHK(hipMemcpyAsync(m->h_flag, m->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (*m->h_flag & 1) return fail(CHNS_ETAU, "tau_m bracket is not positive at some Gauss point");
+  }
+  return CHNS_OK;
+}
+
+template <class T, class TS, class TD>
+int launch_jvp(chns_mesh* m, const dev::PhysView& pv, int block, const TS* U1, const TS* U0,
+               const TD* dU, int ldD, int offD, TD* out, int ldO, int offO, hipStream_t s) {
+  const int64_t E = (int64_t)m->h.leaf_key.size(), n = (int64_t)m->h.node_key.size();
+  const auto mv = view(m);
+  hipLaunchKernelGGL(dev::k_fill<TD>, dim3(grid_stride(n * ldO)), dim3(256), 0, s, out, n * ldO, (TD)0);
+  if (block == CHNS_BLOCK_CH) {
+    hipLaunchKernelGGL((dev::k_ch_jvp<T, TS, TD>), dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, U1,
+                       U0, dU, ldD, offD, out, ldO, offO);
+  } else {
+    hipLaunchKernelGGL((dev::k_ns_jvp<T, TS, TD>), dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, U1,
+                       U0, dU, ldD, offD, out, ldO, offO);
+    hipLaunchKernelGGL(dev::k_ns_bc_jvp<TD>, dim3(grid_for(std::max<int64_t>(m->nb, 1))), dim3(256), 0,
+                       s, m->d_bnodes, m->nb, dU, ldD, offD, out, ldO, offO);
+  }
+  HIPCHK(hipGetLastError());
+  return CHNS_OK;
+}
+
+int launch_diag(chns_mesh* m, const dev::PhysView& pv, int block, const double* U1, const double* U0,
+                double* D, hipStream_t s) {
+  const int64_t E = (int64_t)m->h.leaf_key.size(), n = (int64_t)m->h.node_key.size();
+  const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+  const auto mv = view(m);
+  hipLaunchKernelGGL(dev::k_fill<double>, dim3(grid_stride(n * nf * nf)), dim3(256), 0, s, D,
+                     n * nf * nf, 0.0);
+  if (block == CHNS_BLOCK_CH) {
+    hipLaunchKernelGGL((dev::k_diag<double, 0>), dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, U1, U0, D);
+  } else {
+    hipLaunchKernelGGL((dev::k_diag<double, 1>), dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, U1, U0, D);
+    hipLaunchKernelGGL(dev::k_diag_bc, dim3(grid_for(std::max<int64_t>(m->nb, 1))), dim3(256), 0, s,
+                       m->d_bnodes, m->nb, D);
+  }
+  HIPCHK(hipGetLastError());
+  return CHNS_OK;
+}
+
+int launch_diagnostics(chns_mesh* m, const dev::PhysView& pv, const double* U, double* mass,
+                       double* energy, hipStream_t s) {
+  const int64_t E = (int64_t)m->h.leaf_key.size();
+  const auto mv = view(m);
+  hipLaunchKernelGGL(dev::k_diagnostics, dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, m->d_anchor,
+                     std::ldexp(1.0, -m->h.D), U, m->d_part);
+  hipLaunchKernelGGL(dev::k_finish_sum, dim3(2), dim3(256), 0, s, m->d_part, (int)E, 2, m->d_sum);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(m->h_sum, m->d_sum, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *mass = m->h_sum[0];
+  *energy = m->h_sum[1];
+  return CHNS_OK;
+}
+
+// --------------------------------------------------------------- solver ----
+struct Solver {
+  chns_mesh* m;
+  dev::PhysView pv;
+  chns_solver_opts o;
+  hipStream_t s;
+  Workspace& w;
+  int64_t n;
+  Solver(chns_mesh* m_, const dev::PhysView& pv_, const chns_solver_opts& o_, hipStream_t s_)
+      : m(m_), pv(pv_), o(o_), s(s_), w(m_->ws), n((int64_t)m_->h.node_key.size()) {}
+
+  int ensure_workspace() {
+    const int restart = o.gmres_restart;
+    if (w.n == n && w.restart >= restart) return CHNS_OK;
+    if (w.n) {
+      void* ptrs[] = {w.Uk, w.Uprev, w.r, w.x, w.D, w.Di, w.Di32, w.U1f, w.U0f, w.V64, w.Z64,
+                      w.w64, w.b64, w.V32, w.Z32, w.w32, w.b32, w.part, w.dots, w.flag};
+      for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+      if (w.hdots) (void)hipHostFree(w.hdots);
+      if (w.hflag) (void)hipHostFree(w.hflag);
+      w = Workspace();
+    }
+    const size_t N = (size_t)n * 4;
+    w.nb_part = (int)grid_stride((int64_t)N, 256, 1024);
+    int rc;
+    int64_t& B = w.bytes;
+    if ((rc = dalloc(&w.Uk, n * 6, &B)) || (rc = dalloc(&w.Uprev, n * 6, &B)) ||
+        (rc = dalloc(&w.r, N, &B)) || (rc = dalloc(&w.x, N, &B)) || (rc = dalloc(&w.D, n * 16, &B)) ||
+        (rc = dalloc(&w.Di, n * 16, &B)) || (rc = dalloc(&w.Di32, n * 16, &B)) ||
+        (rc = dalloc(&w.part, (size_t)w.nb_part * dev::kMaxBasis, &B)) ||
+        (rc = dalloc(&w.dots, dev::kMaxBasis, &B)) || (rc = dalloc(&w.flag, 1, &B)))
+      return rc;
+    if (o.precision == 0) {
+      if ((rc = dalloc(&w.V64, N * (restart + 1), &B)) || (rc = dalloc(&w.Z64, N * restart, &B)) ||
+          (rc = dalloc(&w.w64, N, &B)) || (rc = dalloc(&w.b64, N, &B)))
+        return rc;
+    } else {
+      if ((rc = dalloc(&w.V32, N * (restart + 1), &B)) || (rc = dalloc(&w.Z32, N * restart, &B)) ||
+          (rc = dalloc(&w.w32, N, &B)) || (rc = dalloc(&w.b32, N, &B)) ||
+          (rc = dalloc(&w.U1f, n * 6, &B)) || (rc = dalloc(&w.U0f, n * 6, &B)))
+        return rc;
+    }
+    HIPCHK(hipHostMalloc((void**)&w.hdots, sizeof(double) * dev::kMaxBasis));
+    HIPCHK(hipHostMalloc((void**)&w.hflag, sizeof(int)));
+    w.n = n;
+    w.restart = restart;
+    return CHNS_OK;
+  }
+
+  template <class TV>
+  int dots(const TV* V, int64_t stride, int k, const TV* x, int64_t N, double* out) {
+    hipLaunchKernelGGL(dev::k_multidot<TV>, dim3(w.nb_part), dim3(256), 0, s, V, stride, k, x, N, w.part);
+    hipLaunchKernelGGL(dev::k_finish_sum, dim3(k), dim3(256), 0, s, w.part, w.nb_part, k, w.dots);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(w.hdots, w.dots, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int j = 0; j < k; ++j) out[j] = w.hdots[j];
+    return CHNS_OK;
+  }
+
+  template <class TV>
+  int apply(int block, const TV* x, TV* y, const double* U1, const double* U0) {
+    const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+    if (std::is_same<TV, double>::value)
+      return launch_jvp<double, double, TV>(m, pv, block, U1, U0, x, nf, 0, y, nf, 0, s);
+    return launch_jvp<float, float, TV>(m, pv, block, w.U1f, w.U0f, x, nf, 0, y, nf, 0, s);
+  }
+
+  template <class TV>
+  int precondition(int block, const TV* v, TV* z) {
+    if (block == CHNS_BLOCK_CH) {
+      if (std::is_same<TV, double>::value)
+        hipLaunchKernelGGL((dev::k_precond<2, TV, double>), dim3(grid_stride(n)), dim3(256), 0, s, w.Di, v, z, n);
+      else
+        hipLaunchKernelGGL((dev::k_precond<2, TV, float>), dim3(grid_stride(n)), dim3(256), 0, s, w.Di32, v, z, n);
+    } else {
+      if (std::is_same<TV, double>::value)
+        hipLaunchKernelGGL((dev::k_precond<4, TV, double>), dim3(grid_stride(n)), dim3(256), 0, s, w.Di, v, z, n);
+      else
+        hipLaunchKernelGGL((dev::k_precond<4, TV, float>), dim3(grid_stride(n)), dim3(256), 0, s, w.Di32, v, z, n);
+    }
+    HIPCHK(hipGetLastError());
+    return CHNS_OK;
+  }
+
+  // Right-preconditioned restarted GMRES(m) for J x = b (b in bvec), x0 = 0;
+  // x returned in w.x (FP64).
+  template <class TV>
+  int gmres(int block, TV* V, TV* Z, TV* wv, TV* bvec, const double* U1, const double* U0,
+            int* its) {
+    const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+    const int64_t N = n * nf;
+    const int mres = std::min(o.gmres_restart, dev::kMaxBasis - 1);
+    hipLaunchKernelGGL(dev::k_fill<double>, dim3(grid_stride(N)), dim3(256), 0, s, w.x, N, 0.0);
+    double bn;
+    int rc;
+    if ((rc = dots<TV>(bvec, 0, 1, bvec, N, &bn))) return rc;
+    bn = std::sqrt(bn);
+    *its = 0;
+    if (bn == 0.0) return CHNS_OK;
+    if (!std::isfinite(bn)) return fail(CHNS_ENONFINITE, "non-finite GMRES right-hand side");
+    double beta = bn;
+    hipLaunchKernelGGL((dev::k_scale<TV, TV>), dim3(grid_stride(N)), dim3(256), 0, s, V, bvec, 1.0 / beta, N);
+    std::vector<double> H((mres + 1) * mres), cs(mres), sn(mres), g(mres + 1), h(mres + 1), h2(mres + 1);
+    auto Hat = [&](int i, int j) -> double& { return H[i * mres + j]; };
+    bool done = false;
+    while (!done && *its < o.gmres_max_it) {
+      std::fill(H.begin(), H.end(), 0.0);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int k = 0;
+      for (; k < mres && *its < o.gmres_max_it; ++k) {
+        TV* Vk = V + (int64_t)k * N;
+        TV* Zk = Z + (int64_t)k * N;
+        if ((rc = precondition<TV>(block, Vk, Zk))) return rc;
+        if ((rc = apply<TV>(block, Zk, wv, U1, U0))) return rc;
+        ++*its;
+        for (int pass = 0; pass < 2; ++pass) {
+          if ((rc = dots<TV>(V, N, k + 1, wv, N, h.data()))) return rc;
+          dev::Coef c;
+          for (int j = 0; j <= k; ++j) {
+            c.c[j] = h[j];
+            Hat(j, k) += h[j];
+          }
+          hipLaunchKernelGGL(dev::k_multi_axpy<TV>, dim3(grid_stride(N)), dim3(256), 0, s, wv, V, N, k + 1, c, N);
+        }
+        double hn;
+        if ((rc = dots<TV>(wv, 0, 1, wv, N, &hn))) return rc;
+        hn = std::sqrt(hn);
+        if (!std::isfinite(hn)) return fail(CHNS_ENONFINITE, "non-finite value in GMRES");
+        Hat(k + 1, k) = hn;
+        if (hn > 0)
+          hipLaunchKernelGGL((dev::k_scale<TV, TV>), dim3(grid_stride(N)), dim3(256), 0, s,
+                             V + (int64_t)(k + 1) * N, wv, 1.0 / hn, N);
+        for (int j = 0; j < k; ++j) {
+          const double t = cs[j] * Hat(j, k) + sn[j] * Hat(j + 1, k);
+          Hat(j + 1, k) = -sn[j] * Hat(j, k) + cs[j] * Hat(j + 1, k);
+          Hat(j, k) = t;
+        }
+        const double den = std::hypot(Hat(k, k), Hat(k + 1, k));
+        cs[k] = den > 0 ? Hat(k, k) / den : 1.0;
+        sn[k] = den > 0 ? Hat(k + 1, k) / den : 0.0;
+        Hat(k, k) = den;
+        Hat(k + 1, k) = 0.0;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        if (std::fabs(g[k + 1]) <= o.gmres_rtol * bn || den == 0.0 || hn == 0.0) {
+          ++k;
+          done = true;
+          break;
+        }
+      }
+      std::vector<double> y(k, 0.0);
+      for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int j = i + 1; j < k; ++j) t -= Hat(i, j) * y[j];
+        y[i] = Hat(i, i) != 0 ? t / Hat(i, i) : 0.0;
+      }
+      dev::Coef c;
+      for (int j = 0; j < k; ++j) c.c[j] = y[j];
+      hipLaunchKernelGGL(dev::k_multi_update<TV>, dim3(grid_stride(N)), dim3(256), 0, s, w.x, Z, N, k, c, N);
+      if (done || *its >= o.gmres_max_it) break;
+      // restart from the true residual b - J x
+      hipLaunchKernelGGL((dev::k_convert<double, TV>), dim3(grid_stride(N)), dim3(256), 0, s, w.x, Z, N);
+      if ((rc = apply<TV>(block, Z, wv, U1, U0))) return rc;
+      hipLaunchKernelGGL(dev::k_rsub<TV>, dim3(grid_stride(N)), dim3(256), 0, s, wv, bvec, N);
+      if ((rc = dots<TV>(wv, 0, 1, wv, N, &beta))) return rc;
+      beta = std::sqrt(beta);
+      if (!std::isfinite(beta)) return fail(CHNS_ENONFINITE, "non-finite GMRES residual");
+      if (beta <= o.gmres_rtol * bn) break;
+      hipLaunchKernelGGL((dev::k_scale<TV, TV>), dim3(grid_stride(N)), dim3(256), 0, s, V, wv, 1.0 / beta, N);
+    }
+    HIPCHK(hipGetLastError());
+    return CHNS_OK;
+  }
+
+  int residual_norm(int block, double* U, double* rn) {
+    const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+    int rc = launch_residual(m, pv, block, U, w.Uk, w.r, nf, 0, s, block == CHNS_BLOCK_NS);
+    if (rc) return rc;
+    double d;
+    if ((rc = dots<double>(w.r, 0, 1, w.r, n * nf, &d))) return rc;
+    *rn = std::sqrt(d);
+    return CHNS_OK;
+  }
+
+  int newton(int block, double* U, int* nits, int* gits, double* relres, bool* conv) {
+    const int nf = block == CHNS_BLOCK_CH ? 2 : 4, f0 = block == CHNS_BLOCK_CH ? 0 : 2;
+    const int max_it = block == CHNS_BLOCK_CH ? o.newton_max_it_ch : o.newton_max_it_ns;
+    const int64_t N = n * nf;
+    double r0, rn;
+    int rc = residual_norm(block, U, &r0);
+    if (rc) return rc;
+    rn = r0;
+    *conv = false;
+    for (;;) {
+      if (!std::isfinite(rn)) return fail(CHNS_ENONFINITE, "non-finite Newton residual");
+      if (rn <= std::max(o.newton_rtol * r0, o.newton_atol)) {
+        *conv = true;
+        break;
+      }
+      if (*nits >= max_it) break;
+      if ((rc = launch_diag(m, pv, block, U, w.Uk, w.D, s))) return rc;
+      hipLaunchKernelGGL(dev::k_fill<int>, dim3(1), dim3(64), 0, s, w.flag, (int64_t)1, 0);
+      if (nf == 2)
+        hipLaunchKernelGGL(dev::k_invert_blocks<2>, dim3(grid_for(n)), dim3(256), 0, s, w.D, w.Di, w.Di32,
+                           n, o.precond == 0 ? 1 : 0, w.flag);
+      else
+        hipLaunchKernelGGL(dev::k_invert_blocks<4>, dim3(grid_for(n)), dim3(256), 0, s, w.D, w.Di, w.Di32,
+                           n, o.precond == 0 ? 1 : 0, w.flag);
+      HIPCHK(hipGetLastError());
+      int its = 0;
+      if (o.precision == 0) {
+        hipLaunchKernelGGL((dev::k_scale<double, double>), dim3(grid_stride(N)), dim3(256), 0, s, w.b64,
+                           w.r, -1.0, N);
+        rc = gmres<double>(block, w.V64, w.Z64, w.w64, w.b64, U, w.Uk, &its);
+      } else {
+        hipLaunchKernelGGL((dev::k_convert<double, float>), dim3(grid_stride(n * 6)), dim3(256), 0, s, U,
+                           w.U1f, n * 6);
+        hipLaunchKernelGGL((dev::k_convert<double, float>), dim3(grid_stride(n * 6)), dim3(256), 0, s,
+                           w.Uk, w.U0f, n * 6);
+        hipLaunchKernelGGL((dev::k_scale<double, float>), dim3(grid_stride(N)), dim3(256), 0, s, w.b32,
+                           w.r, -1.0, N);
+        rc = gmres<float>(block, w.V32, w.Z32, w.w32, w.b32, U, w.Uk, &its);
+      }
+      if (rc) return rc;
+      *gits += its;
+      hipLaunchKernelGGL(dev::k_add_block<double>, dim3(grid_stride(N)), dim3(256), 0, s, U, w.x, n, f0, nf, 1.0);
+      ++*nits;
+      if ((rc = residual_norm(block, U, &rn))) return rc;
+    }
+    *relres = r0 > 0 ? rn / r0 : 0.0;
+    return CHNS_OK;
+  }
+
+  int max_change(const double* a, const double* b, double* out) {
+    const int64_t N = n * 6;
+    hipLaunchKernelGGL(dev::k_maxabs_diff, dim3(w.nb_part), dim3(256), 0, s, a, b, N, w.part);
+    hipLaunchKernelGGL(dev::k_finish_max, dim3(1), dim3(256), 0, s, w.part, w.nb_part, w.dots);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(w.hdots, w.dots, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = w.hdots[0];
+    return CHNS_OK;
+  }
+
+  int step(double* U, chns_step_stats* st) {
+    int rc = ensure_workspace();
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(w.Uk, U, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
+    bool all_conv = true, block_conv = false;
+    for (int l = 0; l < o.block_max_it; ++l) {
+      HIPCHK(hipMemcpyAsync(w.Uprev, U, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
+      for (int b : {CHNS_BLOCK_NS, CHNS_BLOCK_CH}) {
+        int nits = 0, gits = 0;
+        double rr = 0;
+        bool conv = false;
+        if ((rc = newton(b, U, &nits, &gits, &rr, &conv))) return rc;
+        st->newton_its[b] += nits;
+        st->gmres_its[b] += gits;
+        st->rel_res[b] = rr;
+        all_conv = all_conv && conv;
+      }
+      st->block_its = l + 1;
+      if (l >= o.block_min_it) {
+        double ch;
+        if ((rc = max_change(U, w.Uprev, &ch))) return rc;
+        if (!std::isfinite(ch)) return fail(CHNS_ENONFINITE, "non-finite block change");
+        if (ch <= o.block_tol) {
+          block_conv = true;
+          break;
+        }
+      }
+    }
+    if ((rc = launch_diagnostics(m, pv, U, &st->mass, &st->energy, s))) return rc;
+    st->converged = (all_conv && block_conv) ? 1 : 0;
+    return st->converged ? CHNS_OK : CHNS_NOT_CONVERGED;
+  }
+};
+
+}  // namespace
+
+// =================================================================== ABI ==
+extern "C" {
+
+const char* chns_last_error(void) { return g_err.c_str(); }
+
+int chns_mesh_build(const chns_mesh_spec* spec, chns_mesh** out) {
+  if (!spec || !out) return fail(CHNS_EINVAL, "spec and out must not be NULL");
+  *out = nullptr;
+  chns_mesh* m = new (std::nothrow) chns_mesh();
+  if (!m) return fail(CHNS_ENOMEM, "out of host memory");
+  std::string err;
+  try {
+    err = build_host_mesh(*spec, m->h);
+  } catch (const std::bad_alloc&) {
+    err = "out of host memory while building the mesh";
+  }
+  if (!err.empty()) {
+    delete m;
+    return fail(err.find("memory") != std::string::npos ? CHNS_ENOMEM : CHNS_EINVAL, err);
+  }
+  *out = m;
+  return CHNS_OK;
+}
+
+int chns_mesh_info(const chns_mesh* m, chns_mesh_stats* out) {
+  if (!m || !out) return fail(CHNS_EINVAL, "mesh and out must not be NULL");
+  out->n_leaves = (int64_t)m->h.leaf_key.size();
+  out->n_nodes = (int64_t)m->h.node_key.size();
+  out->n_hanging = (int64_t)m->h.hang_key.size();
+  out->n_constraint = (int64_t)m->h.hang_ids.size();
+  out->level_max = m->h.D;
+  out->max_fanin = m->h.max_fanin;
+  out->device_bytes = m->device_bytes + m->ws.bytes;
+  return CHNS_OK;
+}
+
+int chns_mesh_arrays(const chns_mesh* m, int32_t* leaves, int32_t* elem, int32_t* nodes,
+                     uint8_t* bflags, int32_t* hang_xyz, int64_t* hang_off, int32_t* hang_ids,
+                     double* hang_w) {
+  if (!m) return fail(CHNS_EINVAL, "mesh is NULL");
+  const HostMesh& h = m->h;
+  const size_t E = h.leaf_key.size();
+  for (size_t e = 0; e < E; ++e) {
+    uint32_t x, y, z;
+    unkey(h.leaf_key[e], x, y, z);
+    if (leaves) {
+      leaves[4 * e] = (int32_t)x;
+      leaves[4 * e + 1] = (int32_t)y;
+      leaves[4 * e + 2] = (int32_t)z;
+      leaves[4 * e + 3] = h.leaf_level[e];
+    }
+  }
+  if (elem) std::memcpy(elem, h.elem.data(), h.elem.size() * sizeof(int32_t));
+  for (size_t i = 0; i < h.node_key.size(); ++i) {
+    uint32_t x, y, z;
+    unkey(h.node_key[i], x, y, z);
+    if (nodes) {
+      nodes[3 * i] = (int32_t)x;
+      nodes[3 * i + 1] = (int32_t)y;
+      nodes[3 * i + 2] = (int32_t)z;
+    }
+    if (bflags) bflags[i] = h.bflags[i];
+  }
+  for (size_t i = 0; i < h.hang_key.size(); ++i) {
+    uint32_t x, y, z;
+    unkey(h.hang_key[i], x, y, z);
+    if (hang_xyz) {
+      hang_xyz[3 * i] = (int32_t)x;
+      hang_xyz[3 * i + 1] = (int32_t)y;
+      hang_xyz[3 * i + 2] = (int32_t)z;
+    }
+  }
+  if (hang_off)
+    for (size_t i = 0; i < h.hang_off.size(); ++i) hang_off[i] = h.hang_off[i];
+  if (hang_ids) std::memcpy(hang_ids, h.hang_ids.data(), h.hang_ids.size() * sizeof(int32_t));
+  if (hang_w) std::memcpy(hang_w, h.hang_w.data(), h.hang_w.size() * sizeof(double));
+  return CHNS_OK;
+}
+
+int chns_mesh_nodes(const chns_mesh* m, double* xyz, uint8_t* bflags) {
+  if (!m) return fail(CHNS_EINVAL, "mesh is NULL");
+  const double unit = std::ldexp(1.0, -m->h.D);
+  for (size_t i = 0; i < m->h.node_key.size(); ++i) {
+    uint32_t x, y, z;
+    unkey(m->h.node_key[i], x, y, z);
+    if (xyz) {
+      xyz[3 * i] = x * unit;
+      xyz[3 * i + 1] = y * unit;
+      xyz[3 * i + 2] = z * unit;
+    }
+    if (bflags) bflags[i] = m->h.bflags[i];
+  }
+  return CHNS_OK;
+}
+
+int chns_mesh_upload(chns_mesh* m, void* stream) {
+  if (!m) return fail(CHNS_EINVAL, "mesh is NULL");
+  return upload(m, (hipStream_t)stream);
+}
+
+int chns_mesh_free(chns_mesh* m) {
+  if (!m) return CHNS_OK;
+  void* ptrs[] = {m->d_elem, m->d_hoff, m->d_hids, m->d_bnodes, m->d_anchor, m->d_level,
+                  m->d_hw, m->d_hw32, m->d_flag, m->d_part, m->d_sum,
+                  m->ws.Uk, m->ws.Uprev, m->ws.r, m->ws.x, m->ws.D, m->ws.Di, m->ws.Di32,
+                  m->ws.U1f, m->ws.U0f, m->ws.V64, m->ws.Z64, m->ws.w64, m->ws.b64, m->ws.V32,
+                  m->ws.Z32, m->ws.w32, m->ws.b32, m->ws.part, m->ws.dots, m->ws.flag};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (m->h_flag) (void)hipHostFree(m->h_flag);
+  if (m->h_sum) (void)hipHostFree(m->h_sum);
+  if (m->ws.hdots) (void)hipHostFree(m->ws.hdots);
+  if (m->ws.hflag) (void)hipHostFree(m->ws.hflag);
+  delete m;
+  return CHNS_OK;
+}
+
+int chns_residual(chns_mesh* m, const chns_params* params, int block, const double* U_new,
+                  const double* U_old, double* R, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int rc = check_mesh(m, s);
+  if (rc) return rc;
+  dev::PhysView pv;
+  if ((rc = phys_view(params, pv))) return rc;
+  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "unknown block");
+  if (!U_new || !U_old || !R) return fail(CHNS_EINVAL, "state and output pointers must not be NULL");
+  return launch_residual(m, pv, block, U_new, U_old, R, 6, block == CHNS_BLOCK_CH ? 0 : 2, s, true);
+}
+
+int chns_jvp(chns_mesh* m, const chns_params* params, int block, const double* U_new,
+             const double* U_old, const void* dU, void* JdU, int prec, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int rc = check_mesh(m, s);
+  if (rc) return rc;
+  dev::PhysView pv;
+  if ((rc = phys_view(params, pv))) return rc;
+  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "unknown block");
+  if (!U_new || !U_old || !dU || !JdU) return fail(CHNS_EINVAL, "pointers must not be NULL");
+  const int off = block == CHNS_BLOCK_CH ? 0 : 2;
+  if (prec == CHNS_F64)
+    return launch_jvp<double, double, double>(m, pv, block, U_new, U_old, (const double*)dU, 6, off,
+                                              (double*)JdU, 6, off, s);
+  if (prec == CHNS_F32)
+    return launch_jvp<float, double, float>(m, pv, block, U_new, U_old, (const float*)dU, 6, off,
+                                            (float*)JdU, 6, off, s);
+  return fail(CHNS_EINVAL, "prec must be CHNS_F64 or CHNS_F32");
+}
+
+int chns_diag_blocks(chns_mesh* m, const chns_params* params, int block, const double* U_new,
+                     const double* U_old, double* D, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int rc = check_mesh(m, s);
+  if (rc) return rc;
+  dev::PhysView pv;
+  if ((rc = phys_view(params, pv))) return rc;
+  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "unknown block");
+  if (!U_new || !U_old || !D) return fail(CHNS_EINVAL, "pointers must not be NULL");
+  return launch_diag(m, pv, block, U_new, U_old, D, s);
+}
+
+int chns_diagnostics(chns_mesh* m, const chns_params* params, const double* U, double* mass,
+                     double* energy, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int rc = check_mesh(m, s);
+  if (rc) return rc;
+  dev::PhysView pv;
+  if ((rc = phys_view(params, pv))) return rc;
+  if (!U || !mass || !energy) return fail(CHNS_EINVAL, "pointers must not be NULL");
+  return launch_diagnostics(m, pv, U, mass, energy, s);
+}
+
+int chns_step(chns_mesh* m, const chns_params* params, const chns_solver_opts* opts, double* U,
+              chns_step_stats* out, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int rc = check_mesh(m, s);
+  if (rc) return rc;
+  dev::PhysView pv;
+  if ((rc = phys_view(params, pv))) return rc;
+  if (!opts || !U || !out) return fail(CHNS_EINVAL, "opts, U and out must not be NULL");
+  if (opts->gmres_restart < 1 || opts->gmres_restart > dev::kMaxBasis - 1)
+    return fail(CHNS_EINVAL, "gmres_restart must be in [1, 31]");
+  if (opts->precision != 0 && opts->precision != 1) return fail(CHNS_EINVAL, "precision must be 0 or 1");
+  if (opts->precond != 0 && opts->precond != 1) return fail(CHNS_EINVAL, "precond must be 0 or 1");
+  if (opts->block_max_it < 1 || opts->gmres_max_it < 1) return fail(CHNS_EINVAL, "iteration limits must be positive");
+  std::memset(out, 0, sizeof(*out));
+  const auto t0 = std::chrono::steady_clock::now();
+  Solver S(m, pv, *opts, s);
+  rc = S.step(U, out);
+  out->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}
+
+}  // extern "C"

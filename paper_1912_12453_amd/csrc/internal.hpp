@@ -1,0 +1,61 @@
+// Internal declarations of libchns (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/chns.h"
+
+namespace chns {
+
+// ------------------------------------------------------------ Morton ------
+// 3 x 21-bit interleave, x in the lowest bit of each triple.
+inline uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffULL;
+  v = (v | (v << 32)) & 0x1f00000000ffffULL;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
+  v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+  v = (v | (v << 2)) & 0x1249249249249249ULL;
+  return v;
+}
+inline uint32_t compact3(uint64_t v) {
+  v &= 0x1249249249249249ULL;
+  v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ULL;
+  v = (v ^ (v >> 4)) & 0x100f00f00f00f00fULL;
+  v = (v ^ (v >> 8)) & 0x1f0000ff0000ffULL;
+  v = (v ^ (v >> 16)) & 0x1f00000000ffffULL;
+  v = (v ^ (v >> 32)) & 0x1fffffULL;
+  return (uint32_t)v;
+}
+inline uint64_t mkey(uint32_t x, uint32_t y, uint32_t z) {
+  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+inline void unkey(uint64_t k, uint32_t& x, uint32_t& y, uint32_t& z) {
+  x = compact3(k);
+  y = compact3(k >> 1);
+  z = compact3(k >> 2);
+}
+
+// --------------------------------------------------------- host mesh ------
+struct HostMesh {
+  int T[3] = {1, 1, 1};
+  int D = 0;                         // level_max
+  std::vector<uint64_t> leaf_key;    // anchor keys, Morton order
+  std::vector<uint8_t> leaf_level;
+  std::vector<uint64_t> node_key;    // independent nodes, Morton order
+  std::vector<uint64_t> hang_key;    // hanging nodes, Morton order
+  std::vector<int32_t> hang_off;     // CSR over hang_ids / hang_w
+  std::vector<int32_t> hang_ids;
+  std::vector<double> hang_w;
+  std::vector<int32_t> elem;         // 8 per leaf
+  std::vector<uint8_t> bflags;
+  int max_fanin = 0;
+};
+
+// Returns "" or an error message.
+std::string build_host_mesh(const chns_mesh_spec& spec, HostMesh& out);
+
+}  // namespace chns

@@ -1,0 +1,549 @@
+// HIP kernels of the CHNS element loop for gfx950.
+//
+// Cahn-Hilliard block (Def. 1 of Sec. 3 with the Crank-Nicolson averages,
+// cG(1) form of Def. 2): for test function q = N_a
+//   R_phi,a = (q, (phi^{k+1}-phi^k)/dt) - (dq/dx_i, v~_i phi~) + 1/(Pe Cn) (dq/dx_i, dmu~/dx_i)
+//   R_mu,a  = -(q, mu~) + (q, phi~^3 - phi~) + Cn^2 (dq/dx_i, dphi~/dx_i)
+// Navier-Stokes block (Def. 2 of Sec. 3.4, residual-based VMS with tau_m,
+// tau_c and the strong residuals R_m, R_c), coarse velocity and pressure at the
+// midpoint, rho and eta from phi^{k+1} pulled back to [-1,1].
+//
+// Every element integral is evaluated at the 2x2x2 Gauss points; the
+// pointwise integrand is written as a pair (c, F) such that the contribution to
+// row a is sum_q wdet (N_a c + grad N_a . F), which test_contract performs.
+#include <hip/hip_runtime.h>
+
+#include "element.hpp"
+
+namespace chns {
+namespace dev {
+
+// ------------------------------------------------------------- helpers ----
+template <class TS, class T, int NF>
+__device__ __forceinline__ void gather(const MeshView& m, int ref, const TS* __restrict__ X,
+                                       int ld, int f0, T (&out)[NF]) {
+  if (ref >= 0) {
+    const TS* p = X + (int64_t)ref * ld + f0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) out[f] = (T)p[f];
+    return;
+  }
+  const int h = -1 - ref;
+  const int t0 = m.hoff[h], t1 = m.hoff[h + 1];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) out[f] = (T)0;
+  const auto* w = weights<T>(m);
+  for (int t = t0; t < t1; ++t) {
+    const T wt = w[t];
+    const TS* p = X + (int64_t)m.hids[t] * ld + f0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) out[f] += wt * (T)p[f];
+  }
+}
+
+template <class TO, class T, int NF>
+__device__ __forceinline__ void scatter(const MeshView& m, int ref, TO* __restrict__ Y, int ld,
+                                        int f0, const T (&r)[NF]) {
+  if (ref >= 0) {
+    TO* p = Y + (int64_t)ref * ld + f0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) unsafeAtomicAdd(p + f, (TO)r[f]);
+    return;
+  }
+  const int h = -1 - ref;
+  const int t0 = m.hoff[h], t1 = m.hoff[h + 1];
+  const auto* w = weights<T>(m);
+  for (int t = t0; t < t1; ++t) {
+    const T wt = w[t];
+    TO* p = Y + (int64_t)m.hids[t] * ld + f0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) unsafeAtomicAdd(p + f, (TO)(wt * r[f]));
+  }
+}
+
+template <class T>
+__device__ __forceinline__ T clamp1(T x) {
+  return x > (T)1 ? (T)1 : (x < (T)-1 ? (T)-1 : x);
+}
+
+// ------------------------------------------------------------ CH block ----
+template <class T>
+__global__ __launch_bounds__(256) void k_ch_residual(MeshView m, PhysView p,
+                                                     const double* __restrict__ U1,
+                                                     const double* __restrict__ U0,
+                                                     double* __restrict__ R, int ldR, int offR) {
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const bool valid = e0 < m.E;
+  const int64_t e = valid ? e0 : m.E - 1;
+  Lane<T> L;
+  L.init(threadIdx.x & 7, m.level[e]);
+  const int ref = m.elem[e * 8 + L.c];
+  T a[5], b[5];  // phi, mu, u, v, w at k+1 and k
+  gather<double, T, 5>(m, ref, U1, 6, 0, a);
+  gather<double, T, 5>(m, ref, U0, 6, 0, b);
+  const VG<T> ph = eval_vg<T>((T)0.5 * (a[0] + b[0]), L);
+  const VG<T> mu = eval_vg<T>((T)0.5 * (a[1] + b[1]), L);
+  const T dphi = eval_v<T>(a[0] - b[0]);
+  const T vx = eval_v<T>((T)0.5 * (a[2] + b[2]));
+  const T vy = eval_v<T>((T)0.5 * (a[3] + b[3]));
+  const T vz = eval_v<T>((T)0.5 * (a[4] + b[4]));
+  const T w = L.wdet, kd = (T)p.inv_PeCn, cn2 = (T)p.Cn2;
+  T r[2];
+  r[0] = test_contract<T>(w * dphi * (T)p.inv_dt, w * (kd * mu.dx - vx * ph.v),
+                          w * (kd * mu.dy - vy * ph.v), w * (kd * mu.dz - vz * ph.v), L);
+  r[1] = test_contract<T>(w * (ph.v * ph.v * ph.v - ph.v - mu.v), w * cn2 * ph.dx,
+                          w * cn2 * ph.dy, w * cn2 * ph.dz, L);
+  if (valid) scatter<double, T, 2>(m, ref, R, ldR, offR, r);
+}
+
+template <class T, class TS, class TD>
+__global__ __launch_bounds__(256) void k_ch_jvp(MeshView m, PhysView p, const TS* __restrict__ U1,
+                                                const TS* __restrict__ U0,
+                                                const TD* __restrict__ dU, int ldD, int offD,
+                                                TD* __restrict__ out, int ldO, int offO) {
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const bool valid = e0 < m.E;
+  const int64_t e = valid ? e0 : m.E - 1;
+  Lane<T> L;
+  L.init(threadIdx.x & 7, m.level[e]);
+  const int ref = m.elem[e * 8 + L.c];
+  T a[5], b[5], d[2];
+  gather<TS, T, 5>(m, ref, U1, 6, 0, a);
+  gather<TS, T, 5>(m, ref, U0, 6, 0, b);
+  gather<TD, T, 2>(m, ref, dU, ldD, offD, d);
+  const T pt = eval_v<T>((T)0.5 * (a[0] + b[0]));
+  const T vx = eval_v<T>((T)0.5 * (a[2] + b[2]));
+  const T vy = eval_v<T>((T)0.5 * (a[3] + b[3]));
+  const T vz = eval_v<T>((T)0.5 * (a[4] + b[4]));
+  const VG<T> dp = eval_vg<T>(d[0], L);  // d phi^{k+1}; d phi~ = dp/2
+  const VG<T> dm = eval_vg<T>(d[1], L);  // d mu^{k+1};  d mu~  = dm/2
+  const T w = L.wdet, hk = (T)0.5 * (T)p.inv_PeCn, hc = (T)0.5 * (T)p.Cn2, hp = (T)0.5 * dp.v;
+  T r[2];
+  r[0] = test_contract<T>(w * dp.v * (T)p.inv_dt, w * (hk * dm.dx - vx * hp),
+                          w * (hk * dm.dy - vy * hp), w * (hk * dm.dz - vz * hp), L);
+  r[1] = test_contract<T>(w * ((T)3 * pt * pt - (T)1) * hp - w * (T)0.5 * dm.v, w * hc * dp.dx,
+                          w * hc * dp.dy, w * hc * dp.dz, L);
+  if (valid) scatter<TD, T, 2>(m, ref, out, ldO, offO, r);
+}
+
+// ------------------------------------------------------------ NS block ----
+// Quantities of the linearisation point at one Gauss point.
+template <class T>
+struct NSPoint {
+  T rho, eta, inv_rho;
+  T vt[3], G[3][3];  // v~ and its gradient G[i][j] = dv~_i/dx_j
+  T J[3];            // mass flux kappa grad mu~
+  T adv[3];          // rho v~_j + J_j/Pe - (deta/dx_j)/Re: transport velocity of R_m
+  T tg[3];           // rho (v^{k+1}-v^k)_i/dt - rho g_i/Fr
+  T Rm[3], Rc;       // strong residuals
+  T tau_m, tau_c, Gh;  // Gh = 4/h^2 (G_ij = Gh delta_ij)
+  T gpht[3];         // grad phi~
+  T pt;              // p~
+  bool ok;           // tau_m bracket positive
+};
+
+// Linearisation point from the lane's corner values of U^{k+1} (a) and U^k (b),
+// 6 fields each (phi, mu, u, v, w, p).
+template <class T>
+__device__ __forceinline__ void ns_point(const PhysView& p, const Lane<T>& L, const T (&a)[6],
+                                         const T (&b)[6], NSPoint<T>& P) {
+  const VG<T> ph1 = eval_vg<T>(a[0], L);
+  const VGH<T> pht = eval_vgh<T>((T)0.5 * (a[0] + b[0]), L);
+  const VG<T> mut = eval_vg<T>((T)0.5 * (a[1] + b[1]), L);
+  const VG<T> pt = eval_vg<T>((T)0.5 * (a[5] + b[5]), L);
+  T dv[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const VG<T> v = eval_vg<T>((T)0.5 * (a[2 + i] + b[2 + i]), L);
+    P.vt[i] = v.v;
+    P.G[i][0] = v.dx;
+    P.G[i][1] = v.dy;
+    P.G[i][2] = v.dz;
+    dv[i] = eval_v<T>(a[2 + i] - b[2 + i]);
+  }
+  const T ps = clamp1(ph1.v);
+  P.rho = (T)p.alpha * ps + (T)p.beta;
+  P.eta = (T)p.gamma * ps + (T)p.xi;
+  P.inv_rho = (T)1 / P.rho;
+  const bool inside = ph1.v <= (T)1 && ph1.v >= (T)-1;
+  const T gg = inside ? (T)p.gamma : (T)0;  // grad eta, zero where phi* is pulled back
+  const T kap = (T)p.kappa;
+  P.J[0] = kap * mut.dx;
+  P.J[1] = kap * mut.dy;
+  P.J[2] = kap * mut.dz;
+  const T iPe = (T)p.inv_Pe, iRe = (T)p.inv_Re, iWe = (T)p.inv_We;
+  P.adv[0] = P.rho * P.vt[0] + iPe * P.J[0] - iRe * gg * ph1.dx;
+  P.adv[1] = P.rho * P.vt[1] + iPe * P.J[1] - iRe * gg * ph1.dy;
+  P.adv[2] = P.rho * P.vt[2] + iPe * P.J[2] - iRe * gg * ph1.dz;
+  P.gpht[0] = pht.dx;
+  P.gpht[1] = pht.dy;
+  P.gpht[2] = pht.dz;
+  P.pt = pt.v;
+  // capillary divergence (Cn/We) d/dx_j (dphi~/dx_i dphi~/dx_j): on trilinear
+  // cells the Laplacian vanishes and only the mixed derivatives remain
+  const T cw = (T)p.CnWe;
+  const T cap[3] = {cw * (pht.dy * pht.dxy + pht.dz * pht.dxz),
+                    cw * (pht.dx * pht.dxy + pht.dz * pht.dyz),
+                    cw * (pht.dx * pht.dxz + pht.dy * pht.dyz)};
+  const T gpt[3] = {pt.dx, pt.dy, pt.dz};
+  const T ifr = (T)p.inv_Fr, idt = (T)p.inv_dt;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    P.tg[i] = P.rho * (dv[i] * idt - (T)p.g[i] * ifr);
+    P.Rm[i] = P.tg[i] + P.adv[0] * P.G[i][0] + P.adv[1] * P.G[i][1] + P.adv[2] * P.G[i][2] +
+              cap[i] + iWe * gpt[i];
+  }
+  P.Rc = P.G[0][0] + P.G[1][1] + P.G[2][2];
+  P.Gh = (T)4 / (L.h * L.h);
+  const T vv = P.vt[0] * P.vt[0] + P.vt[1] * P.vt[1] + P.vt[2] * P.vt[2];
+  const T vJ = P.vt[0] * P.J[0] + P.vt[1] * P.J[1] + P.vt[2] * P.J[2];
+  const T nu = P.eta * P.inv_rho * iRe;
+  const T br = (T)4 * idt * idt + P.Gh * vv + P.Gh * vJ * P.inv_rho * iPe +
+               (T)p.C_I * nu * nu * (T)3 * P.Gh * P.Gh;
+  P.ok = br > (T)0;
+  P.tau_m = (T)1 / sqrt(br);
+  P.tau_c = (T)1 / ((T)3 * P.Gh * P.tau_m);
+}
+
+// Residual rows of the NS block (momentum i = 0..2, continuity 3) at the point,
+// contracted against the test functions of the lane's corner.
+template <class T>
+__device__ __forceinline__ void ns_residual_point(const PhysView& p, const Lane<T>& L,
+                                                  const NSPoint<T>& P, T (&r)[4]) {
+  const T w = L.wdet, iPe = (T)p.inv_Pe, iWe = (T)p.inv_We, tm = P.tau_m;
+  const T er = P.eta * (T)p.inv_Re, cw = (T)p.CnWe;
+  T W[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) W[j] = P.vt[j] + (P.J[j] * iPe - tm * P.Rm[j]) * P.inv_rho;
+  const T dgl = iWe * (P.rho * P.tau_c * P.Rc - P.pt);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T c = P.tg[i];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c += (P.rho * P.vt[j] + iPe * P.J[j] - tm * P.Rm[j]) * P.G[i][j];
+    T F[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      F[j] = P.Rm[i] * tm * W[j] - cw * P.gpht[i] * P.gpht[j] + er * P.G[i][j];
+    F[i] += dgl;
+    r[i] = test_contract<T>(w * c, w * F[0], w * F[1], w * F[2], L);
+  }
+  const T q = tm * P.inv_rho * w;
+  r[3] = test_contract<T>(w * P.Rc, q * P.Rm[0], q * P.Rm[1], q * P.Rm[2], L);
+}
+
+// Derivative of the NS rows in the direction (dv, dp) of (v^{k+1}, p^{k+1}):
+// dvt = dv/2 (value and gradient), ddv = dv (value), dpt = dp/2.
+template <class T>
+__device__ __forceinline__ void ns_jvp_point(const PhysView& p, const Lane<T>& L,
+                                             const NSPoint<T>& P, const VG<T> (&dvt)[3],
+                                             const T (&ddv)[3], const VG<T>& dpt, T (&r)[4]) {
+  const T w = L.wdet, iPe = (T)p.inv_Pe, iWe = (T)p.inv_We, tm = P.tau_m, ir = P.inv_rho;
+  const T er = P.eta * (T)p.inv_Re, idt = (T)p.inv_dt;
+  T dG[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    dG[i][0] = dvt[i].dx;
+    dG[i][1] = dvt[i].dy;
+    dG[i][2] = dvt[i].dz;
+  }
+  const T dgp[3] = {dpt.dx, dpt.dy, dpt.dz};
+  T dRm[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T t = P.rho * ddv[i] * idt + iWe * dgp[i];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) t += P.adv[j] * dG[i][j] + P.rho * dvt[j].v * P.G[i][j];
+    dRm[i] = t;
+  }
+  const T dRc = dG[0][0] + dG[1][1] + dG[2][2];
+  const T vdv = P.vt[0] * dvt[0].v + P.vt[1] * dvt[1].v + P.vt[2] * dvt[2].v;
+  const T Jdv = P.J[0] * dvt[0].v + P.J[1] * dvt[1].v + P.J[2] * dvt[2].v;
+  const T dbr = (T)2 * P.Gh * vdv + P.Gh * Jdv * ir * iPe;
+  const T dtm = (T)-0.5 * tm * tm * tm * dbr;
+  const T dtc = -P.tau_c * dtm / tm;
+  T W[3], dW[3], dTR[3];  // dTR_j = d(tau_m R_m,j)
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    W[j] = P.vt[j] + (P.J[j] * iPe - tm * P.Rm[j]) * ir;
+    dTR[j] = dtm * P.Rm[j] + tm * dRm[j];
+    dW[j] = dvt[j].v - dTR[j] * ir;
+  }
+  const T dgl = iWe * (P.rho * (dtc * P.Rc + P.tau_c * dRc) - dpt.v);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T c = P.rho * ddv[i] * idt;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      c += (P.rho * P.vt[j] + iPe * P.J[j] - tm * P.Rm[j]) * dG[i][j] +
+           (P.rho * dvt[j].v - dTR[j]) * P.G[i][j];
+    T F[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) F[j] = dTR[i] * W[j] + P.Rm[i] * tm * dW[j] + er * dG[i][j];
+    F[i] += dgl;
+    r[i] = test_contract<T>(w * c, w * F[0], w * F[1], w * F[2], L);
+  }
+  const T q = w * ir;
+  r[3] = test_contract<T>(w * dRc, q * dTR[0], q * dTR[1], q * dTR[2], L);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_ns_residual(MeshView m, PhysView p,
+                                                     const double* __restrict__ U1,
+                                                     const double* __restrict__ U0,
+                                                     double* __restrict__ R, int ldR, int offR,
+                                                     int* __restrict__ flag) {
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const bool valid = e0 < m.E;
+  const int64_t e = valid ? e0 : m.E - 1;
+  Lane<T> L;
+  L.init(threadIdx.x & 7, m.level[e]);
+  const int ref = m.elem[e * 8 + L.c];
+  T a[6], b[6];
+  gather<double, T, 6>(m, ref, U1, 6, 0, a);
+  gather<double, T, 6>(m, ref, U0, 6, 0, b);
+  NSPoint<T> P;
+  ns_point<T>(p, L, a, b, P);
+  T r[4];
+  ns_residual_point<T>(p, L, P, r);
+  if (valid) {
+    if (!P.ok) atomicOr(flag, 1);
+    scatter<double, T, 4>(m, ref, R, ldR, offR, r);
+  }
+}
+
+template <class T, class TS, class TD>
+__global__ __launch_bounds__(256) void k_ns_jvp(MeshView m, PhysView p, const TS* __restrict__ U1,
+                                                const TS* __restrict__ U0,
+                                                const TD* __restrict__ dU, int ldD, int offD,
+                                                TD* __restrict__ out, int ldO, int offO) {
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const bool valid = e0 < m.E;
+  const int64_t e = valid ? e0 : m.E - 1;
+  Lane<T> L;
+  L.init(threadIdx.x & 7, m.level[e]);
+  const int ref = m.elem[e * 8 + L.c];
+  T a[6], b[6], d[4];
+  gather<TS, T, 6>(m, ref, U1, 6, 0, a);
+  gather<TS, T, 6>(m, ref, U0, 6, 0, b);
+  gather<TD, T, 4>(m, ref, dU, ldD, offD, d);
+  NSPoint<T> P;
+  ns_point<T>(p, L, a, b, P);
+  VG<T> dvt[3];
+  T ddv[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const VG<T> g = eval_vg<T>(d[i], L);
+    ddv[i] = g.v;
+    dvt[i].v = (T)0.5 * g.v;
+    dvt[i].dx = (T)0.5 * g.dx;
+    dvt[i].dy = (T)0.5 * g.dy;
+    dvt[i].dz = (T)0.5 * g.dz;
+  }
+  VG<T> dpt = eval_vg<T>((T)0.5 * d[3], L);
+  T r[4];
+  ns_jvp_point<T>(p, L, P, dvt, ddv, dpt, r);
+  if (valid) scatter<TD, T, 4>(m, ref, out, ldO, offO, r);
+}
+
+// ------------------------------------------------------ boundary rows ----
+// NS velocity rows of boundary nodes and the pressure row of the pinned node.
+__global__ void k_ns_bc_residual(const int32_t* __restrict__ bnodes, int64_t nb,
+                                 const double* __restrict__ U1, const double* __restrict__ U0,
+                                 double* __restrict__ R, int ldR, int offR) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) {
+    const int64_t n = bnodes[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) R[n * ldR + offR + d] = U1[n * 6 + 2 + d] - U0[n * 6 + 2 + d];
+  }
+  if (i == 0) R[offR + 3] = U1[5] - U0[5];
+}
+
+template <class TD>
+__global__ void k_ns_bc_jvp(const int32_t* __restrict__ bnodes, int64_t nb,
+                            const TD* __restrict__ dU, int ldD, int offD, TD* __restrict__ out,
+                            int ldO, int offO) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) {
+    const int64_t n = bnodes[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[n * ldO + offO + d] = dU[n * ldD + offD + d];
+  }
+  if (i == 0) out[offO + 3] = dU[offD + 3];
+}
+
+// ------------------------------------------------- node-block diagonal ----
+// Diagonal block of node n: sum over elements of sum_{c,c'} P_cn P_c'n J_e[c][c'],
+// where P_cn is 1 when corner c is node n, the constraint weight of n when c
+// hangs on n, and 0 otherwise.  Each element visits the nodes it touches (its
+// own corners, then the parents of its hanging corners not seen before); for
+// each node and each block field the seed P_.n e_f goes through the same
+// linearised integrand as the JVP.
+template <class T>
+__device__ __forceinline__ T seed_weight(const MeshView& m, int ref, int n) {
+  if (ref >= 0) return ref == n ? (T)1 : (T)0;
+  const int h = -1 - ref;
+  const auto* w = weights<T>(m);
+  for (int t = m.hoff[h]; t < m.hoff[h + 1]; ++t)
+    if (m.hids[t] == n) return w[t];
+  return (T)0;
+}
+
+__device__ __forceinline__ int lane_of_corner(int c) {
+  const int bx = c & 1, by = (c >> 1) & 1, bz = c >> 2;
+  return bx ^ (by ? 2 : 0) ^ (bz ? 7 : 0);
+}
+
+template <class T, int BLOCK>
+__global__ __launch_bounds__(256) void k_diag(MeshView m, PhysView p, const double* __restrict__ U1,
+                                              const double* __restrict__ U0,
+                                              double* __restrict__ Dg) {
+  constexpr int NF = BLOCK == 0 ? 2 : 4;
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const bool valid = e0 < m.E;
+  const int64_t e = valid ? e0 : m.E - 1;
+  const int lane8 = threadIdx.x & 7;
+  const int base = threadIdx.x & ~7;
+  Lane<T> L;
+  L.init(lane8, m.level[e]);
+  const int ref = m.elem[e * 8 + L.c];
+  T a[6], b[6];
+  gather<double, T, 6>(m, ref, U1, 6, 0, a);
+  gather<double, T, 6>(m, ref, U0, 6, 0, b);
+  NSPoint<T> P;
+  T ch_pt = 0, ch_v[3] = {0, 0, 0};
+  if (BLOCK == 1) {
+    ns_point<T>(p, L, a, b, P);
+  } else {
+    ch_pt = eval_v<T>((T)0.5 * (a[0] + b[0]));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ch_v[d] = eval_v<T>((T)0.5 * (a[2 + d] + b[2 + d]));
+  }
+  // candidate nodes: slot k < 8 is corner k's node when direct; slot 8 + 8*k + t
+  // is parent t of hanging corner k
+  const int max_t = 8;
+  for (int slot = 0; slot < 8 + 8 * max_t; ++slot) {
+    int n = -1;
+    if (slot < 8) {
+      const int r = __shfl(ref, base + lane_of_corner(slot), 64);
+      n = r >= 0 ? r : -1;
+    } else {
+      const int k = (slot - 8) / max_t, t = (slot - 8) % max_t;
+      const int r = __shfl(ref, base + lane_of_corner(k), 64);
+      if (r < 0) {
+        const int h = -1 - r;
+        if (m.hoff[h] + t < m.hoff[h + 1]) n = m.hids[m.hoff[h] + t];
+      }
+      if (n >= 0) {
+        // skip nodes already visited: a direct corner, or a parent of an earlier
+        // hanging corner
+        int seen = 0;
+        if (ref >= 0 && ref == n) seen = 1;
+        if (ref < 0 && L.c < k) {
+          const int h2 = -1 - ref;
+          for (int t2 = m.hoff[h2]; t2 < m.hoff[h2 + 1]; ++t2)
+            if (m.hids[t2] == n) seen = 1;
+        }
+        if (ref < 0 && L.c == k) {
+          const int h2 = -1 - ref;
+          for (int t2 = m.hoff[h2]; t2 < m.hoff[h2] + t; ++t2)
+            if (m.hids[t2] == n) seen = 1;
+        }
+        seen = (int)group_sum<float>((float)seen);
+        if (seen) n = -1;
+      }
+    }
+    if (n < 0) continue;  // uniform across the 8 lanes of the element
+    const T s = seed_weight<T>(m, ref, n);
+    for (int f = 0; f < NF; ++f) {
+      T r[NF];
+      if (BLOCK == 1) {
+        VG<T> dvt[3];
+        T ddv[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const VG<T> g = eval_vg<T>(f == i ? s : (T)0, L);
+          ddv[i] = g.v;
+          dvt[i].v = (T)0.5 * g.v;
+          dvt[i].dx = (T)0.5 * g.dx;
+          dvt[i].dy = (T)0.5 * g.dy;
+          dvt[i].dz = (T)0.5 * g.dz;
+        }
+        const VG<T> dpt = eval_vg<T>(f == 3 ? (T)0.5 * s : (T)0, L);
+        T rr[4];
+        ns_jvp_point<T>(p, L, P, dvt, ddv, dpt, rr);
+#pragma unroll
+        for (int q = 0; q < NF; ++q) r[q] = rr[q];
+      } else {
+        const VG<T> dp = eval_vg<T>(f == 0 ? s : (T)0, L);
+        const VG<T> dm = eval_vg<T>(f == 1 ? s : (T)0, L);
+        const T w = L.wdet, hk = (T)0.5 * (T)p.inv_PeCn, hc = (T)0.5 * (T)p.Cn2,
+                hp = (T)0.5 * dp.v;
+        r[0] = test_contract<T>(w * dp.v * (T)p.inv_dt, w * (hk * dm.dx - ch_v[0] * hp),
+                                w * (hk * dm.dy - ch_v[1] * hp), w * (hk * dm.dz - ch_v[2] * hp), L);
+        r[1] = test_contract<T>(w * ((T)3 * ch_pt * ch_pt - (T)1) * hp - w * (T)0.5 * dm.v,
+                                w * hc * dp.dx, w * hc * dp.dy, w * hc * dp.dz, L);
+      }
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        const T col = group_sum<T>(s * r[q]);
+        if (valid && lane8 == 0) unsafeAtomicAdd(Dg + (int64_t)n * NF * NF + q * NF + f, (double)col);
+      }
+    }
+  }
+}
+
+// identity rows for the NS boundary rows of the diagonal blocks
+__global__ void k_diag_bc(const int32_t* __restrict__ bnodes, int64_t nb, double* __restrict__ Dg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) {
+    double* B = Dg + (int64_t)bnodes[i] * 16;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) B[r * 4 + c] = r == c ? 1.0 : 0.0;
+  }
+  if (i == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Dg[12 + c] = c == 3 ? 1.0 : 0.0;
+  }
+}
+
+// ------------------------------------------------------- diagnostics ----
+// Per-element sums of phi and of the energy density at the Gauss points;
+// the element totals are reduced by k_reduce_sum in a fixed order.
+__global__ __launch_bounds__(256) void k_diagnostics(MeshView m, PhysView p,
+                                                     const int32_t* __restrict__ anchor,
+                                                     double unit, const double* __restrict__ U,
+                                                     double* __restrict__ part) {
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const bool valid = e0 < m.E;
+  const int64_t e = valid ? e0 : m.E - 1;
+  Lane<double> L;
+  L.init(threadIdx.x & 7, m.level[e]);
+  const int ref = m.elem[e * 8 + L.c];
+  double a[5];
+  gather<double, double, 5>(m, ref, U, 6, 0, a);
+  const VG<double> ph = eval_vg<double>(a[0], L);
+  const double vx = eval_v<double>(a[2]), vy = eval_v<double>(a[3]), vz = eval_v<double>(a[4]);
+  // Gauss point position: anchor + h (1 + s g)/2 per axis
+  const double x = anchor[e * 3 + 0] * unit + 0.5 * L.h * (1.0 + (L.sxh > 0 ? kGauss : -kGauss));
+  const double y = anchor[e * 3 + 1] * unit + 0.5 * L.h * (1.0 + (L.syh > 0 ? kGauss : -kGauss));
+  const double z = anchor[e * 3 + 2] * unit + 0.5 * L.h * (1.0 + (L.szh > 0 ? kGauss : -kGauss));
+  const double rho = p.alpha * clamp1(ph.v) + p.beta;
+  const double psi = 0.25 * (ph.v * ph.v - 1.0) * (ph.v * ph.v - 1.0);
+  const double g2 = ph.dx * ph.dx + ph.dy * ph.dy + ph.dz * ph.dz;
+  const double en = 0.5 * rho * (vx * vx + vy * vy + vz * vz) +
+                    p.inv_Fr * rho * -(p.g[0] * x + p.g[1] * y + p.g[2] * z);
+  const double fe = (psi + 0.5 * p.Cn2 * g2) * p.inv_We / p.Cn;
+  const double mass = group_sum<double>(L.wdet * ph.v);
+  const double energy = group_sum<double>(L.wdet * (en + fe));
+  if (valid && (threadIdx.x & 7) == 0) {
+    part[e0] = mass;
+    part[m.E + e0] = energy;
+  }
+}
+
+}  // namespace dev
+}  // namespace chns

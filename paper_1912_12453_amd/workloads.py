@@ -242,3 +242,35 @@ def serving_stream(n_requests=64, rate_hz=20.0, seed=4, level_range=(6, 9), step
 
 def with_physics(w: Workload, **kw):
     return replace(w, physics=replace(w.physics, **kw))
+
+
+def random_state(n, seed, phi_range=1.1, mu_sigma=0.5, v_sigma=0.3, p_sigma=1.0, step=0.05):
+    """A generic non-converged pair (U^{k+1}, U^k) for parity checks: phi ~
+    U(-phi_range, phi_range) (so some values need the pull-back), mu, v, p
+    normal; U^{k+1} = U^k + N(0, step^2)."""
+    rng = np.random.default_rng(seed)
+    U0 = np.zeros((n, 6))
+    U0[:, 0] = rng.uniform(-phi_range, phi_range, n)
+    U0[:, 1] = rng.normal(0, mu_sigma, n)
+    U0[:, 2:5] = rng.normal(0, v_sigma, (n, 3))
+    U0[:, 5] = rng.normal(0, p_sigma, n)
+    U1 = U0 + rng.normal(0, step, U0.shape)
+    return U1, U0
+
+
+def moderate_physics(**kw):
+    """Parameters of order one for parity checks on random states."""
+    base = dict(Cn=0.3, Pe=2.0, Re=7.0, We=3.0, Fr=1.5, rho_minus=0.25, eta_minus=0.4, dt=0.05,
+                g=(0.0, -1.0, 0.0))
+    base.update(kw)
+    return Physics(**base)
+
+
+def bubble_state(xyz, bflags, w, seeds=None):
+    """The bubble workload's fields: phi0 profile, mu = phi^3 - phi, v ~ N(0, 0.01^2)
+    (zero on the boundary), p = 0 as U^k; U^{k+1} = U^k + N(0, 1e-3^2)."""
+    seeds = seeds or w.seeds
+    U0 = initial_state(xyz, w.mesh.phi0, bflags, velocity_sigma=0.01,
+                       velocity_seed=seeds.get("velocity", 1))
+    U1 = perturbed(U0, 1e-3, seeds.get("perturb", 2))
+    return U1, U0

@@ -1,0 +1,168 @@
+"""GPU parity: the HIP element loop against the CPU oracle, through the C ABI.
+
+FP64 residuals, JVPs and node-block diagonals must agree with the oracle to
+1e-12 relative (2-norm over the block's rows, and entry-wise against the
+largest entry); FP32 JVPs are compared at 1e-4 and their error is printed.
+Meshes span several workgroups with a ragged tail, the single-leaf and
+all-boundary degenerate cases, multi-tree bricks and every hanging-node case
+of random 2:1 trees."""
+import numpy as np
+import pytest
+
+from paper_1912_12453_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CH, NS = 0, 1
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "a GPU is required"
+    return t
+
+
+@pytest.fixture(scope="module")
+def chns():
+    from paper_1912_12453_amd import chns as c
+    c.lib()
+    return c
+
+
+def mesh_pair(chns, orc, kind):
+    if kind == "single":
+        args = ((1, 1, 1), 0, 0)
+        return chns.Mesh(*args), orc.Mesh(*args)
+    if kind == "uniform2":
+        args = ((1, 1, 1), 2, 2)
+        return chns.Mesh(*args), orc.Mesh(*args)
+    if kind == "drop16":
+        args = ((1, 1, 1), 4, 4)
+        return chns.Mesh(*args), orc.Mesh(*args)
+    if kind == "adaptive":
+        lv = W.random_leaves((1, 1, 1), 4, 7, p_split=0.3, level_min=2)
+        return chns.Mesh((1, 1, 1), 0, 4, leaves=lv), orc.Mesh((1, 1, 1), 0, 4, leaves=lv)
+    if kind == "brick":
+        lv = W.random_leaves((1, 1, 3), 3, 9, p_split=0.35, level_min=1)
+        return chns.Mesh((1, 1, 3), 0, 3, leaves=lv), orc.Mesh((1, 1, 3), 0, 3, leaves=lv)
+    if kind == "bubble6":
+        w = W.bubble(level_max=6, level_min=3)
+        ms = w.mesh
+        return chns.Mesh.from_spec(ms), orc.Mesh(ms.trees, ms.level_min, ms.level_max, ms.phi0, ms.band)
+    raise KeyError(kind)
+
+
+KINDS = ["single", "uniform2", "adaptive", "brick", "drop16", "bubble6"]
+
+
+def relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+
+
+def compare(gpu, ref, fields, tol=TOL, label=""):
+    g, r = gpu[:, fields], ref[:, fields]
+    e = relerr(g, r)
+    emax = np.abs(g - r).max() / max(np.abs(r).max(), 1e-300)
+    print(f"{label}: rel2 {e:.2e} relmax {emax:.2e}", flush=True)
+    assert e <= tol and emax <= tol * 10, (e, emax)
+    return e
+
+
+def to_dev(torch, a, dtype=None):
+    import torch as t
+    return t.tensor(a, dtype=dtype or t.float64, device="cuda:0").contiguous()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("block", [CH, NS])
+def test_residual_parity(torch, chns, orc, kind, block):
+    pm, om = mesh_pair(chns, orc, kind)
+    print(f"case residual {kind} block {block} E={pm.n_leaves}", flush=True)
+    ph = W.moderate_physics()
+    U1, U0 = W.random_state(pm.n_nodes, 100 + block)
+    ref = om.residual(orc.Params.make(**vars(ph)), block, U1, U0)
+    R = pm.residual(chns.make_params(ph), block, to_dev(torch, U1), to_dev(torch, U0)).cpu().numpy()
+    fs = slice(0, 2) if block == CH else slice(2, 6)
+    compare(R, ref, fs, label=f"residual {kind} {block}")
+    other = slice(2, 6) if block == CH else slice(0, 2)
+    assert np.abs(R[:, other]).max() == 0.0
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("block", [CH, NS])
+def test_jvp_parity(torch, chns, orc, kind, block):
+    pm, om = mesh_pair(chns, orc, kind)
+    print(f"case jvp {kind} block {block} E={pm.n_leaves}", flush=True)
+    ph = W.moderate_physics()
+    U1, U0 = W.random_state(pm.n_nodes, 200 + block)
+    dU = W.direction(pm.n_nodes, 300 + block)
+    ref = om.jvp(orc.Params.make(**vars(ph)), block, U1, U0, dU)
+    p = chns.make_params(ph)
+    d1, d0 = to_dev(torch, U1), to_dev(torch, U0)
+    J64 = pm.jvp(p, block, d1, d0, to_dev(torch, dU)).cpu().numpy()
+    fs = slice(0, 2) if block == CH else slice(2, 6)
+    compare(J64, ref, fs, label=f"jvp64 {kind} {block}")
+    J32 = pm.jvp(p, block, d1, d0, to_dev(torch, dU, torch.float32), prec=chns.CHNS_F32)
+    J32 = J32.cpu().numpy().astype(np.float64)
+    e32 = compare(J32, ref, fs, tol=1e-4, label=f"jvp32 {kind} {block}")
+    assert e32 > 0
+
+
+@pytest.mark.parametrize("kind", ["single", "adaptive", "brick", "drop16"])
+@pytest.mark.parametrize("block", [CH, NS])
+def test_diag_blocks_parity(torch, chns, orc, kind, block):
+    pm, om = mesh_pair(chns, orc, kind)
+    print(f"case diag {kind} block {block}", flush=True)
+    ph = W.moderate_physics()
+    U1, U0 = W.random_state(pm.n_nodes, 400 + block)
+    ref = om.diag_blocks(orc.Params.make(**vars(ph)), block, U1, U0)
+    D = pm.diag_blocks(chns.make_params(ph), block, to_dev(torch, U1), to_dev(torch, U0)).cpu().numpy()
+    nf = 2 if block == CH else 4
+    compare(D.reshape(-1, nf * nf), ref.reshape(-1, nf * nf), slice(0, nf * nf), label=f"diag {kind}")
+
+
+@pytest.mark.parametrize("kind", ["adaptive", "brick", "bubble6"])
+def test_diagnostics_parity(torch, chns, orc, kind):
+    pm, om = mesh_pair(chns, orc, kind)
+    ph = W.moderate_physics(g=(0.3, -0.8, 0.52))
+    U1, _ = W.random_state(pm.n_nodes, 500)
+    m_ref, e_ref = om.diagnostics(orc.Params.make(**vars(ph)), U1)
+    m, e = pm.diagnostics(chns.make_params(ph), to_dev(torch, U1))
+    assert m == pytest.approx(m_ref, rel=1e-12, abs=1e-14)
+    assert e == pytest.approx(e_ref, rel=1e-12)
+
+
+def test_flux_mode_as_printed(torch, chns, orc):
+    pm, om = mesh_pair(chns, orc, "adaptive")
+    ph = W.moderate_physics(flux_mode=1)
+    U1, U0 = W.random_state(pm.n_nodes, 600)
+    ref = om.residual(orc.Params.make(**vars(ph)), NS, U1, U0)
+    R = pm.residual(chns.make_params(ph), NS, to_dev(torch, U1), to_dev(torch, U0)).cpu().numpy()
+    compare(R, ref, slice(2, 6), label="flux_mode=1")
+
+
+def test_tau_bracket_error_reported(torch, chns):
+    m = chns.Mesh((1, 1, 1), 3, 3)
+    xyz, _ = m.nodes()
+    U = np.zeros((m.n_nodes, 6))
+    U[:, 1] = 50.0 * xyz[:, 0]
+    U[:, 2] = 1.0
+    ph = W.moderate_physics(dt=10.0, Re=1e6)
+    d = to_dev(torch, U)
+    with pytest.raises(chns.ChnsError) as ei:
+        m.residual(chns.make_params(ph), NS, d, d)
+    assert ei.value.code == chns.CHNS_ETAU
+
+
+def test_invalid_arguments(torch, chns):
+    m = chns.Mesh((1, 1, 1), 1, 1)
+    d = to_dev(torch, np.zeros((m.n_nodes, 6)))
+    bad = chns.make_params(W.moderate_physics(dt=-1.0))
+    with pytest.raises(chns.ChnsError) as ei:
+        m.residual(bad, NS, d, d)
+    assert ei.value.code == chns.CHNS_EINVAL
+    with pytest.raises(chns.ChnsError):
+        m.residual(chns.make_params(W.moderate_physics()), 7, d, d)
