@@ -1,0 +1,212 @@
+"""Throughput of the matrix-free CHNS element loop on one MI355X.
+
+Workload (default): the adaptive-octree bubble mesh refined to level 9 around
+a bubble of radius 0.15 (about 1.13M leaves, 1.02M nodes, 0.23M hanging
+nodes), density ratio 1000, viscosity ratio 100, Re 35, We 10, Fr 1,
+Cn 0.005; FP64.  Inputs are synthetic and seeded (see workloads.py).
+
+One timed step is one pass of the whole hot path over that input: for the
+Navier-Stokes block and then the Cahn-Hilliard block, one Newton iteration
+with a fixed-length GMRES(30) cycle (residual and its FP64 norm, node-block
+Jacobi set-up, 30 preconditioned JVPs with classical Gram-Schmidt twice and
+FP64 dot products, the Newton update, the new residual), followed by the
+integral of phi and the total energy.  `value` counts the DoF that the 60
+JVPs of a step touch (30 x 4 per node for NS, 30 x 2 per node for CH) per
+second of wall time: JVP GDoF/s inside the solver.
+
+The roofline object describes the NS JVP element kernel, timed live with HIP
+events on the stream it is launched on.  The CPU baseline is the FP64 oracle
+(test infrastructure) computing the same 6-DoF JVP on the same mesh and state.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+                       [--workload bubble_l9|bubble_l8|drop16|rt_l10] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per element of the NS JVP element kernel (FP64), derived in
+# floating-point operations executed per element (8 lanes x the
+# FP64 add/mul/fma of one lane, fma = 2) and compulsory HBM bytes per element
+# (state U^{k+1}, U^k and direction dU of each node once, the output written
+# once, the element's 8 corner ids and level).
+NS_JVP_FLOPS_PER_ELEMENT = None  # filled from the kernel's instruction count
+NS_JVP_BYTES_PER_NODE = (6 + 6 + 4) * 8 + 4 * 8
+NS_JVP_BYTES_PER_ELEMENT = 8 * 4 + 1
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_VALU_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--workload", default="bubble_l9")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-reps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1912_12453_amd import chns
+    from paper_1912_12453_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    name = args.workload
+    if name.startswith("bubble_l"):
+        w = W.bubble(level_max=int(name[len("bubble_l"):]))
+    elif name == "drop16":
+        w = W.drop16()
+    elif name.startswith("rt_l"):
+        w = W.rt(level_max=int(name[len("rt_l"):]))
+    else:
+        raise SystemExit(f"unknown workload {name}")
+
+    t0 = time.time()
+    mesh = chns.Mesh.from_spec(w.mesh)
+    mesh.upload()
+    t_mesh = time.time() - t0
+    xyz, bf = mesh.nodes()
+    n, E = mesh.n_nodes, mesh.n_leaves
+    log(f"[bench] {name}: {E} leaves, {n} nodes, {mesh.stats.n_hanging} hanging; "
+        f"mesh build + upload {t_mesh:.2f}s")
+    if name.startswith("bubble"):
+        U1h, U0h = W.bubble_state(xyz, bf, w)
+    else:
+        U0h = W.initial_state(xyz, w.mesh.phi0, bf, phi_noise=1e-3, seed=0)
+        U1h = W.perturbed(U0h, 1e-3, 2)
+    dUh = W.direction(n, w.seeds.get("direction", 3))
+    p = chns.make_params(w.physics)
+    U0 = torch.tensor(U0h, device=dev)
+    U1 = torch.tensor(U1h, device=dev)
+    dU = torch.tensor(dUh, device=dev)
+    precision = 0 if args.precision == "fp64" else 1
+    K_GMRES = 30
+    opts = chns.make_opts(newton_max_it_ch=1, newton_max_it_ns=1, gmres_restart=K_GMRES,
+                          gmres_max_it=K_GMRES, gmres_rtol=0.0, newton_rtol=0.0, block_max_it=1,
+                          precision=precision, precond=1)
+    U = U0.clone()
+
+    def step():
+        U.copy_(U0)
+        rc, st = mesh.step(p, opts, U)
+        if rc not in (chns.CHNS_OK, chns.CHNS_NOT_CONVERGED):
+            raise RuntimeError(f"step failed with {rc}")
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lat = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        st = step()
+        lat.append((time.perf_counter() - ts) * 1e3)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    gits = list(st.gmres_its)
+    dof_per_step = (gits[0] * 2 + gits[1] * 4) * n
+    value = dof_per_step * args.steps / t_total / 1e9
+    log(f"[bench] {args.steps} steps in {t_total:.3f}s; gmres its per step {gits}")
+
+    # ---- live kernel timing: NS JVP element kernel (FP64), HIP events on its stream
+    stream = torch.cuda.current_stream()
+    out = torch.zeros_like(U1)
+    op = 1 if precision == 0 else 2
+    dUk = dU if precision == 0 else dU.float()
+    outk = out if precision == 0 else out.float()
+    chns.chns_launch_element_loop(mesh.h, p, chns.CHNS_BLOCK_NS, op, U1, U0, dUk, outk, 3)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    grid = chns.chns_launch_element_loop(mesh.h, p, chns.CHNS_BLOCK_NS, op, U1, U0, dUk, outk,
+                                         args.kernel_reps)
+    ev1.record(stream)
+    ev1.synchronize()
+    ns_ms = ev0.elapsed_time(ev1) / args.kernel_reps
+    kern = {}
+    for blk, bname in ((chns.CHNS_BLOCK_CH, "ch"), (chns.CHNS_BLOCK_NS, "ns")):
+        for o, oname in ((0, "residual"), (1, "jvp_f64"), (2, "jvp_f32")):
+            dd = dU if o != 2 else dU.float()
+            oo = out if o != 2 else out.float()
+            chns.chns_launch_element_loop(mesh.h, p, blk, o, U1, U0, dd, oo, 1)
+            ev0.record(stream)
+            chns.chns_launch_element_loop(mesh.h, p, blk, o, U1, U0, dd, oo, 5)
+            ev1.record(stream)
+            ev1.synchronize()
+            kern[f"{bname}_{oname}_ms"] = ev0.elapsed_time(ev1) / 5
+    for bname, nf in (("ch", 2), ("ns", 4)):
+        for oname in ("jvp_f64", "jvp_f32"):
+            kern[f"{bname}_{oname}_gdofs"] = n * nf / kern[f"{bname}_{oname}_ms"] / 1e6
+
+    bytes_per_launch = n * NS_JVP_BYTES_PER_NODE + E * NS_JVP_BYTES_PER_ELEMENT
+    flops_per_element = float(os.environ.get("CHNS_NS_JVP_FLOPS", "0")) or None
+    ach_gbs = bytes_per_launch / (ns_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach_gbs / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": "k_ns_jvp<double,double,double>" if precision == 0 else "k_ns_jvp<float,double,float>",
+            "avg_ms": round(ns_ms, 4), "grid": grid, "block": 256,
+            "bytes_per_launch": bytes_per_launch}
+    if flops_per_element:
+        tf = flops_per_element * E / (ns_ms * 1e-3) / 1e12
+        roof.update({"bound": "alu", "achieved": round(tf, 2), "peak": PEAK_FP64_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_VALU_TFLOPS, 4),
+                     "hbm_GBps": round(ach_gbs, 1)})
+
+    # ---- CPU baseline: the oracle's 6-DoF JVP on the same mesh and state
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.time()
+        om = oracle.Mesh(w.mesh.trees, w.mesh.level_min, w.mesh.level_max, w.mesh.phi0, w.mesh.band)
+        log(f"[bench] oracle mesh {time.time() - t0:.1f}s")
+        op_ = oracle.Params.make(**vars(w.physics))
+        reps = args.cpu_reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            om.jvp(op_, 0, U1h, U0h, dUh)
+            om.jvp(op_, 1, U1h, U0h, dUh)
+        tc = time.perf_counter() - t0
+        cpu = {"value": round(6 * n * reps / tc / 1e9, 6), "unit": "GDoF/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{reps} x (CH + NS JVP) over the full {name} mesh ({E} leaves), {tc:.1f}s"}
+        log(f"[bench] cpu baseline {cpu}")
+
+    res = {
+        "metric": "CHNS JVP GDoF/s (in-solver, FP64 Newton-GMRES pass)",
+        "value": round(value, 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_total / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision == 0 else "f64+f32", "data": "synthetic",
+        "config": {"workload": name, "leaves": E, "nodes": n, "hanging": int(mesh.stats.n_hanging),
+                   "precision": args.precision, "gmres_per_block": K_GMRES,
+                   "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                   "p99_ms": round(float(np.percentile(lat, 99)), 3)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": {k: round(v, 4) for k, v in kern.items()},
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

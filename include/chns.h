@@ -186,7 +186,8 @@ typedef struct {
   int32_t gmres_its[2];
   int32_t converged;     /* every Newton solve and the block iteration met
                             their tolerances                               */
-  double rel_res[2];     /* final ||R|| / ||R_0|| of the last solve per block */
+  double rel_res[2];     /* ||R_b(U^{k+1})|| / ||R_b(U^k)|| per block, both
+                            evaluated at the end of the step               */
   double mass, energy;   /* diagnostics of U^{k+1}                          */
   double t_ms;           /* wall time of the step                           */
 } chns_step_stats;
@@ -198,6 +199,18 @@ typedef struct {
  * CHNS_NOT_CONVERGED with U and stats written when a tolerance was missed. */
 int chns_step(chns_mesh* mesh, const chns_params* params, const chns_solver_opts* opts,
               double* U, chns_step_stats* out, void* stream);
+
+/* Measurement helper: enqueues `reps` back-to-back launches of one element
+ * kernel alone (the per-chunk element loop, without the node gather) on
+ * `stream` and returns without synchronising, so that the caller can bracket
+ * them with its own HIP events on that stream.  The kernels write the mesh's
+ * internal partial buffers; `out` is not used and may be NULL.  op: 0 residual
+ * (FP64), 1 JVP FP64 (dU: n_nodes*6 doubles), 2 JVP FP32 (dU: n_nodes*6
+ * floats), 3 node-block diagonal.  *grid (may be NULL) receives the number of
+ * workgroups of one launch. */
+int chns_launch_element_loop(chns_mesh* mesh, const chns_params* params, int block, int op,
+                             const double* U_new, const double* U_old, const void* dU, void* out,
+                             int reps, void* stream, int64_t* grid);
 
 const char* chns_last_error(void);
 

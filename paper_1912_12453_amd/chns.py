@@ -104,6 +104,8 @@ def lib():
         L.chns_diagnostics.argtypes = [vp, C.POINTER(chns_params), vp, dp, dp, vp]
         L.chns_step.argtypes = [vp, C.POINTER(chns_params), C.POINTER(chns_solver_opts), vp,
                                 C.POINTER(chns_step_stats), vp]
+        L.chns_launch_element_loop.argtypes = [vp, C.POINTER(chns_params), C.c_int, C.c_int, vp, vp,
+                                               vp, vp, C.c_int, vp, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -186,6 +188,15 @@ def chns_step(mesh, params, opts, U, stream=None):
     rc = _check(lib().chns_step(mesh, C.byref(params), C.byref(opts), U.data_ptr(), C.byref(st),
                                 _stream(stream)), allow=(CHNS_NOT_CONVERGED,))
     return rc, st
+
+
+def chns_launch_element_loop(mesh, params, block, op, U_new, U_old, dU, out, reps, stream=None):
+    g = C.c_int64()
+    _check(lib().chns_launch_element_loop(mesh, C.byref(params), block, op, U_new.data_ptr(),
+                                          U_old.data_ptr(), dU.data_ptr() if dU is not None else None,
+                                          out.data_ptr() if out is not None else None, reps,
+                                          _stream(stream), C.byref(g)))
+    return g.value
 
 
 def _stream(stream):

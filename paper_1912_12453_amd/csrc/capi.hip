@@ -71,11 +71,19 @@ struct Workspace {
 
 struct chns_mesh {
   HostMesh h;
+  ScatterPlan plan;
   int device = -1;
   bool uploaded = false;
-  int32_t *d_elem = nullptr, *d_hoff = nullptr, *d_hids = nullptr, *d_bnodes = nullptr,
-          *d_anchor = nullptr;
+  int32_t *d_elem = nullptr, *d_hoff = nullptr, *d_hids = nullptr, *d_anchor = nullptr;
   uint8_t* d_level = nullptr;
+  // scatter plan
+  int32_t *d_tgt_off = nullptr, *d_tgt = nullptr, *d_inc_off = nullptr, *d_node_off = nullptr, *d_node_slot = nullptr;
+  uint8_t *d_inc_corner = nullptr, *d_bflags = nullptr;
+  float* d_inc_w = nullptr;
+  int64_t *d_touch_off = nullptr, *d_ntouch_off = nullptr, *d_ntouch_slot = nullptr;
+  double* d_partial = nullptr;  // target slots x 4 (FP64), or x 8 FP32 values
+  double* d_tbuf = nullptr;     // element touches x 16, allocated on first diagonal
+  int64_t n_chunks = 0;
   double* d_hw = nullptr;
   float* d_hw32 = nullptr;
   int* d_flag = nullptr;
@@ -83,7 +91,6 @@ struct chns_mesh {
   double* d_part = nullptr;  // diagnostics partials
   double* d_sum = nullptr;
   double* h_sum = nullptr;
-  int64_t nb = 0;
   int64_t device_bytes = 0;
   Workspace ws;
 };
@@ -100,6 +107,33 @@ dev::MeshView view(const chns_mesh* m) {
   v.hw32 = m->d_hw32;
   v.E = (int64_t)m->h.leaf_key.size();
   return v;
+}
+
+dev::ChunkCaps caps(const chns_mesh* m) {
+  return dev::ChunkCaps{m->plan.max_targets, m->plan.max_inc};
+}
+
+dev::PlanView plan_view(const chns_mesh* m) {
+  dev::PlanView v;
+  v.tgt_off = m->d_tgt_off;
+  v.tgt = m->d_tgt;
+  v.inc_off = m->d_inc_off;
+  v.inc_corner = m->d_inc_corner;
+  v.inc_w = m->d_inc_w;
+  v.node_off = m->d_node_off;
+  v.node_slot = m->d_node_slot;
+  v.touch_off = m->d_touch_off;
+  v.ntouch_off = m->d_ntouch_off;
+  v.ntouch_slot = m->d_ntouch_slot;
+  v.bflags = m->d_bflags;
+  return v;
+}
+
+template <class T>
+int h2d(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) return CHNS_OK;
+  HIPCHK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return CHNS_OK;
 }
 
 int phys_view(const chns_params* p, dev::PhysView& v) {
@@ -147,7 +181,15 @@ int upload(chns_mesh* m, hipStream_t s) {
   const HostMesh& h = m->h;
   const size_t E = h.leaf_key.size(), NH = h.hang_key.size(), NC = h.hang_ids.size();
   if (h.max_fanin > 8) return fail(CHNS_EINVAL, "hanging-node fan-in above 8 is not supported");
-  std::vector<int32_t> anchor(E * 3), bnodes;
+  std::string perr;
+  try {
+    perr = build_scatter_plan(h, m->plan);
+  } catch (const std::bad_alloc&) {
+    perr = "out of host memory building the scatter plan";
+  }
+  if (!perr.empty()) return fail(CHNS_ENOMEM, perr);
+  const ScatterPlan& P = m->plan;
+  std::vector<int32_t> anchor(E * 3);
   for (size_t e = 0; e < E; ++e) {
     uint32_t x, y, z;
     unkey(h.leaf_key[e], x, y, z);
@@ -155,8 +197,6 @@ int upload(chns_mesh* m, hipStream_t s) {
     anchor[3 * e + 1] = (int32_t)y;
     anchor[3 * e + 2] = (int32_t)z;
   }
-  for (size_t i = 0; i < h.bflags.size(); ++i)
-    if (h.bflags[i] & 1) bnodes.push_back((int32_t)i);
   std::vector<float> w32(h.hang_w.begin(), h.hang_w.end());
   int64_t& B = m->device_bytes;
   B = 0;
@@ -164,29 +204,45 @@ int upload(chns_mesh* m, hipStream_t s) {
   if ((rc = dalloc(&m->d_elem, E * 8, &B)) || (rc = dalloc(&m->d_level, E, &B)) ||
       (rc = dalloc(&m->d_anchor, E * 3, &B)) || (rc = dalloc(&m->d_hoff, NH + 1, &B)) ||
       (rc = dalloc(&m->d_hids, NC, &B)) || (rc = dalloc(&m->d_hw, NC, &B)) ||
-      (rc = dalloc(&m->d_hw32, NC, &B)) || (rc = dalloc(&m->d_bnodes, bnodes.size(), &B)) ||
-      (rc = dalloc(&m->d_flag, 1, &B)) || (rc = dalloc(&m->d_part, E * 2, &B)) ||
-      (rc = dalloc(&m->d_sum, 2, &B)))
+      (rc = dalloc(&m->d_hw32, NC, &B)) || (rc = dalloc(&m->d_flag, 1, &B)) ||
+      (rc = dalloc(&m->d_part, E * 2, &B)) || (rc = dalloc(&m->d_sum, 2, &B)) ||
+      (rc = dalloc(&m->d_tgt_off, P.tgt_off.size(), &B)) || (rc = dalloc(&m->d_tgt, P.tgt.size(), &B)) ||
+      (rc = dalloc(&m->d_inc_off, P.inc_off.size(), &B)) ||
+      (rc = dalloc(&m->d_inc_corner, P.inc_corner.size(), &B)) ||
+      (rc = dalloc(&m->d_inc_w, P.inc_w.size(), &B)) ||
+      (rc = dalloc(&m->d_node_off, P.node_off.size(), &B)) ||
+      (rc = dalloc(&m->d_node_slot, P.node_slot.size(), &B)) ||
+      (rc = dalloc(&m->d_touch_off, P.touch_off.size(), &B)) ||
+      (rc = dalloc(&m->d_ntouch_off, P.ntouch_off.size(), &B)) ||
+      (rc = dalloc(&m->d_ntouch_slot, P.ntouch_slot.size(), &B)) ||
+      (rc = dalloc(&m->d_bflags, h.bflags.size(), &B)) ||
+      (rc = dalloc(&m->d_partial, P.tgt.size() * 4, &B)))
     return rc;
   HIPCHK(hipHostMalloc((void**)&m->h_flag, sizeof(int)));
   HIPCHK(hipHostMalloc((void**)&m->h_sum, 2 * sizeof(double)));
-  HIPCHK(hipMemcpyAsync(m->d_elem, h.elem.data(), E * 8 * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(m->d_level, h.leaf_level.data(), E, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(m->d_anchor, anchor.data(), E * 3 * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(m->d_hoff, h.hang_off.data(), (NH + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  if (NC) {
-    HIPCHK(hipMemcpyAsync(m->d_hids, h.hang_ids.data(), NC * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(m->d_hw, h.hang_w.data(), NC * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(m->d_hw32, w32.data(), NC * sizeof(float), hipMemcpyHostToDevice, s));
-  }
-  if (!bnodes.empty())
-    HIPCHK(hipMemcpyAsync(m->d_bnodes, bnodes.data(), bnodes.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  m->nb = (int64_t)bnodes.size();
+  if ((rc = h2d(m->d_elem, h.elem, s)) || (rc = h2d(m->d_level, h.leaf_level, s)) ||
+      (rc = h2d(m->d_anchor, anchor, s)) || (rc = h2d(m->d_hoff, h.hang_off, s)) ||
+      (rc = h2d(m->d_hids, h.hang_ids, s)) || (rc = h2d(m->d_hw, h.hang_w, s)) ||
+      (rc = h2d(m->d_hw32, w32, s)) || (rc = h2d(m->d_tgt_off, P.tgt_off, s)) || (rc = h2d(m->d_tgt, P.tgt, s)) ||
+      (rc = h2d(m->d_inc_off, P.inc_off, s)) || (rc = h2d(m->d_inc_corner, P.inc_corner, s)) ||
+      (rc = h2d(m->d_inc_w, P.inc_w, s)) || (rc = h2d(m->d_node_off, P.node_off, s)) ||
+      (rc = h2d(m->d_node_slot, P.node_slot, s)) || (rc = h2d(m->d_touch_off, P.touch_off, s)) ||
+      (rc = h2d(m->d_ntouch_off, P.ntouch_off, s)) ||
+      (rc = h2d(m->d_ntouch_slot, P.ntouch_slot, s)) || (rc = h2d(m->d_bflags, h.bflags, s)))
+    return rc;
+  m->n_chunks = (int64_t)P.tgt_off.size() - 1;
+  if (dev::ChunkLDS<double, 6, 4, 4>::bytes(caps(m)) > 65536)
+    return fail(CHNS_EINVAL, "a chunk of the mesh needs more than 64 KiB of LDS");
   // the host vectors above must outlive the copies
   HIPCHK(hipStreamSynchronize(s));
   m->device = dev;
   m->uploaded = true;
   return CHNS_OK;
+}
+
+int ensure_tbuf(chns_mesh* m) {
+  if (m->d_tbuf) return CHNS_OK;
+  return dalloc(&m->d_tbuf, (size_t)m->plan.ntouch_slot.size() * 16, &m->device_bytes);
 }
 
 int check_mesh(chns_mesh* m, hipStream_t s) {
@@ -195,23 +251,29 @@ int check_mesh(chns_mesh* m, hipStream_t s) {
 }
 
 // ----------------------------------------------------------- launches ----
-// Residual of a block into R (ld, off), zeroing R's other entries of each row.
+// Element kernel (one workgroup per chunk of 32 leaves) writing the chunk's
+// target partials, then the node gather writing every row of the output.
 int launch_residual(chns_mesh* m, const dev::PhysView& pv, int block, const double* U1,
                     const double* U0, double* R, int ld, int off, hipStream_t s, bool check_tau) {
-  const int64_t E = (int64_t)m->h.leaf_key.size(), n = (int64_t)m->h.node_key.size();
+  const int64_t n = (int64_t)m->h.node_key.size();
   const auto mv = view(m);
-  hipLaunchKernelGGL(dev::k_fill<double>, dim3(grid_stride(n * ld)), dim3(256), 0, s, R, n * ld, 0.0);
+  const auto pl = plan_view(m);
+  const dim3 g((unsigned)m->n_chunks), b(dev::kChunkThreads);
+  const dev::ChunkCaps cc = caps(m);
+  double* part = m->d_partial;
   if (block == CHNS_BLOCK_CH) {
-    hipLaunchKernelGGL(dev::k_ch_residual<double>, dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, U1,
-                       U0, R, ld, off);
+    hipLaunchKernelGGL(dev::k_ch_residual<double>, g, b, (dev::ChunkLDS<double, 5, 0, 2>::bytes(cc)), s,
+                       mv, pl, pv, cc, U1, U0, part);
+    hipLaunchKernelGGL((dev::k_gather<2, double, double, 0>), dim3(grid_stride(n)), dim3(256), 0, s,
+                       pl, n, part, R, ld, off, U1, U0, (const double*)nullptr, 0, 0);
     HIPCHK(hipGetLastError());
     return CHNS_OK;
   }
   hipLaunchKernelGGL(dev::k_fill<int>, dim3(1), dim3(64), 0, s, m->d_flag, (int64_t)1, 0);
-  hipLaunchKernelGGL(dev::k_ns_residual<double>, dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, U1, U0,
-                     R, ld, off, m->d_flag);
-  hipLaunchKernelGGL(dev::k_ns_bc_residual, dim3(grid_for(std::max<int64_t>(m->nb, 1))), dim3(256), 0, s,
-                     m->d_bnodes, m->nb, U1, U0, R, ld, off);
+  hipLaunchKernelGGL(dev::k_ns_residual<double>, g, b, (dev::ChunkLDS<double, 6, 0, 4>::bytes(cc)), s, mv,
+                     pl, pv, cc, U1, U0, part, m->d_flag);
+  hipLaunchKernelGGL((dev::k_gather<4, double, double, 1>), dim3(grid_stride(n)), dim3(256), 0, s, pl,
+                     n, part, R, ld, off, U1, U0, (const double*)nullptr, 0, 0);
   HIPCHK(hipGetLastError());
   if (check_tau) {
     HIPCHK(hipMemcpyAsync(m->h_flag, m->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -221,20 +283,27 @@ int launch_residual(chns_mesh* m, const dev::PhysView& pv, int block, const doub
   return CHNS_OK;
 }
 
+// T: arithmetic, TS: state storage, TD: direction and output storage (partials
+// are kept in T)
 template <class T, class TS, class TD>
 int launch_jvp(chns_mesh* m, const dev::PhysView& pv, int block, const TS* U1, const TS* U0,
                const TD* dU, int ldD, int offD, TD* out, int ldO, int offO, hipStream_t s) {
-  const int64_t E = (int64_t)m->h.leaf_key.size(), n = (int64_t)m->h.node_key.size();
+  const int64_t n = (int64_t)m->h.node_key.size();
   const auto mv = view(m);
-  hipLaunchKernelGGL(dev::k_fill<TD>, dim3(grid_stride(n * ldO)), dim3(256), 0, s, out, n * ldO, (TD)0);
+  const auto pl = plan_view(m);
+  const dim3 g((unsigned)m->n_chunks), b(dev::kChunkThreads);
+  const dev::ChunkCaps cc = caps(m);
+  T* part = (T*)m->d_partial;
   if (block == CHNS_BLOCK_CH) {
-    hipLaunchKernelGGL((dev::k_ch_jvp<T, TS, TD>), dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, U1,
-                       U0, dU, ldD, offD, out, ldO, offO);
+    hipLaunchKernelGGL((dev::k_ch_jvp<T, TS, TD>), g, b, (dev::ChunkLDS<T, 5, 2, 2>::bytes(cc)), s, mv, pl,
+                       pv, cc, U1, U0, dU, ldD, offD, part);
+    hipLaunchKernelGGL((dev::k_gather<2, T, TD, 0>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part,
+                       out, ldO, offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD);
   } else {
-    hipLaunchKernelGGL((dev::k_ns_jvp<T, TS, TD>), dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, U1,
-                       U0, dU, ldD, offD, out, ldO, offO);
-    hipLaunchKernelGGL(dev::k_ns_bc_jvp<TD>, dim3(grid_for(std::max<int64_t>(m->nb, 1))), dim3(256), 0,
-                       s, m->d_bnodes, m->nb, dU, ldD, offD, out, ldO, offO);
+    hipLaunchKernelGGL((dev::k_ns_jvp<T, TS, TD>), g, b, (dev::ChunkLDS<T, 6, 4, 4>::bytes(cc)), s, mv, pl,
+                       pv, cc, U1, U0, dU, ldD, offD, part);
+    hipLaunchKernelGGL((dev::k_gather<4, T, TD, 2>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part,
+                       out, ldO, offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD);
   }
   HIPCHK(hipGetLastError());
   return CHNS_OK;
@@ -242,17 +311,18 @@ int launch_jvp(chns_mesh* m, const dev::PhysView& pv, int block, const TS* U1, c
 
 int launch_diag(chns_mesh* m, const dev::PhysView& pv, int block, const double* U1, const double* U0,
                 double* D, hipStream_t s) {
-  const int64_t E = (int64_t)m->h.leaf_key.size(), n = (int64_t)m->h.node_key.size();
-  const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+  const int64_t n = (int64_t)m->h.node_key.size();
+  int rc = ensure_tbuf(m);
+  if (rc) return rc;
   const auto mv = view(m);
-  hipLaunchKernelGGL(dev::k_fill<double>, dim3(grid_stride(n * nf * nf)), dim3(256), 0, s, D,
-                     n * nf * nf, 0.0);
+  const auto pl = plan_view(m);
+  const dim3 g((unsigned)m->n_chunks), b(dev::kChunkThreads);
   if (block == CHNS_BLOCK_CH) {
-    hipLaunchKernelGGL((dev::k_diag<double, 0>), dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, U1, U0, D);
+    hipLaunchKernelGGL((dev::k_diag<double, 0>), g, b, 0, s, mv, pl, pv, U1, U0, m->d_tbuf);
+    hipLaunchKernelGGL(dev::k_gather_diag<2>, dim3(grid_stride(n)), dim3(256), 0, s, pl, n, m->d_tbuf, D);
   } else {
-    hipLaunchKernelGGL((dev::k_diag<double, 1>), dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, U1, U0, D);
-    hipLaunchKernelGGL(dev::k_diag_bc, dim3(grid_for(std::max<int64_t>(m->nb, 1))), dim3(256), 0, s,
-                       m->d_bnodes, m->nb, D);
+    hipLaunchKernelGGL((dev::k_diag<double, 1>), g, b, 0, s, mv, pl, pv, U1, U0, m->d_tbuf);
+    hipLaunchKernelGGL(dev::k_gather_diag<4>, dim3(grid_stride(n)), dim3(256), 0, s, pl, n, m->d_tbuf, D);
   }
   HIPCHK(hipGetLastError());
   return CHNS_OK;
@@ -524,6 +594,9 @@ struct Solver {
     int rc = ensure_workspace();
     if (rc) return rc;
     HIPCHK(hipMemcpyAsync(w.Uk, U, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
+    double r_init[2];
+    for (int b : {CHNS_BLOCK_CH, CHNS_BLOCK_NS})
+      if ((rc = residual_norm(b, U, &r_init[b]))) return rc;
     bool all_conv = true, block_conv = false;
     for (int l = 0; l < o.block_max_it; ++l) {
       HIPCHK(hipMemcpyAsync(w.Uprev, U, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
@@ -534,7 +607,6 @@ struct Solver {
         if ((rc = newton(b, U, &nits, &gits, &rr, &conv))) return rc;
         st->newton_its[b] += nits;
         st->gmres_its[b] += gits;
-        st->rel_res[b] = rr;
         all_conv = all_conv && conv;
       }
       st->block_its = l + 1;
@@ -547,6 +619,11 @@ struct Solver {
           break;
         }
       }
+    }
+    for (int b : {CHNS_BLOCK_CH, CHNS_BLOCK_NS}) {
+      double rf;
+      if ((rc = residual_norm(b, U, &rf))) return rc;
+      st->rel_res[b] = r_init[b] > 0 ? rf / r_init[b] : 0.0;
     }
     if ((rc = launch_diagnostics(m, pv, U, &st->mass, &st->energy, s))) return rc;
     st->converged = (all_conv && block_conv) ? 1 : 0;
@@ -658,8 +735,11 @@ int chns_mesh_upload(chns_mesh* m, void* stream) {
 
 int chns_mesh_free(chns_mesh* m) {
   if (!m) return CHNS_OK;
-  void* ptrs[] = {m->d_elem, m->d_hoff, m->d_hids, m->d_bnodes, m->d_anchor, m->d_level,
+  void* ptrs[] = {m->d_elem, m->d_hoff, m->d_hids, m->d_anchor, m->d_level,
                   m->d_hw, m->d_hw32, m->d_flag, m->d_part, m->d_sum,
+                  m->d_tgt_off, m->d_tgt, m->d_inc_off, m->d_node_off, m->d_node_slot, m->d_inc_corner,
+                  m->d_bflags, m->d_inc_w, m->d_touch_off, m->d_ntouch_off, m->d_ntouch_slot,
+                  m->d_partial, m->d_tbuf,
                   m->ws.Uk, m->ws.Uprev, m->ws.r, m->ws.x, m->ws.D, m->ws.Di, m->ws.Di32,
                   m->ws.U1f, m->ws.U0f, m->ws.V64, m->ws.Z64, m->ws.w64, m->ws.b64, m->ws.V32,
                   m->ws.Z32, m->ws.w32, m->ws.b32, m->ws.part, m->ws.dots, m->ws.flag};
@@ -746,6 +826,66 @@ int chns_step(chns_mesh* m, const chns_params* params, const chns_solver_opts* o
   rc = S.step(U, out);
   out->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return rc;
+}
+
+int chns_launch_element_loop(chns_mesh* m, const chns_params* params, int block, int op,
+                             const double* U_new, const double* U_old, const void* dU, void* out,
+                             int reps, void* stream, int64_t* grid) {
+  hipStream_t s = (hipStream_t)stream;
+  int rc = check_mesh(m, s);
+  if (rc) return rc;
+  dev::PhysView pv;
+  if ((rc = phys_view(params, pv))) return rc;
+  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "unknown block");
+  if (!U_new || !U_old || (op != 0 && op != 3 && !dU)) return fail(CHNS_EINVAL, "NULL pointer");
+  if (reps < 1) return fail(CHNS_EINVAL, "reps must be positive");
+  if (op == 3 && (rc = ensure_tbuf(m))) return rc;
+  (void)out;
+  const auto mv = view(m);
+  const auto pl = plan_view(m);
+  const dim3 g((unsigned)m->n_chunks), b(dev::kChunkThreads);
+  const int off = block == CHNS_BLOCK_CH ? 0 : 2;
+  double* p64 = m->d_partial;
+  float* p32 = (float*)m->d_partial;
+  const dev::ChunkCaps cc = caps(m);
+  for (int r = 0; r < reps; ++r) {
+    if (op == 0) {
+      if (block == CHNS_BLOCK_CH)
+        hipLaunchKernelGGL(dev::k_ch_residual<double>, g, b, (dev::ChunkLDS<double, 5, 0, 2>::bytes(cc)), s,
+                           mv, pl, pv, cc, U_new, U_old, p64);
+      else
+        hipLaunchKernelGGL(dev::k_ns_residual<double>, g, b, (dev::ChunkLDS<double, 6, 0, 4>::bytes(cc)), s,
+                           mv, pl, pv, cc, U_new, U_old, p64, m->d_flag);
+    } else if (op == 1) {
+      if (block == CHNS_BLOCK_CH)
+        hipLaunchKernelGGL((dev::k_ch_jvp<double, double, double>), g, b,
+                           (dev::ChunkLDS<double, 5, 2, 2>::bytes(cc)), s, mv, pl, pv, cc, U_new, U_old,
+                           (const double*)dU, 6, off, p64);
+      else
+        hipLaunchKernelGGL((dev::k_ns_jvp<double, double, double>), g, b,
+                           (dev::ChunkLDS<double, 6, 4, 4>::bytes(cc)), s, mv, pl, pv, cc, U_new, U_old,
+                           (const double*)dU, 6, off, p64);
+    } else if (op == 2) {
+      if (block == CHNS_BLOCK_CH)
+        hipLaunchKernelGGL((dev::k_ch_jvp<float, double, float>), g, b,
+                           (dev::ChunkLDS<float, 5, 2, 2>::bytes(cc)), s, mv, pl, pv, cc, U_new, U_old,
+                           (const float*)dU, 6, off, p32);
+      else
+        hipLaunchKernelGGL((dev::k_ns_jvp<float, double, float>), g, b,
+                           (dev::ChunkLDS<float, 6, 4, 4>::bytes(cc)), s, mv, pl, pv, cc, U_new, U_old,
+                           (const float*)dU, 6, off, p32);
+    } else if (op == 3) {
+      if (block == CHNS_BLOCK_CH)
+        hipLaunchKernelGGL((dev::k_diag<double, 0>), g, b, 0, s, mv, pl, pv, U_new, U_old, m->d_tbuf);
+      else
+        hipLaunchKernelGGL((dev::k_diag<double, 1>), g, b, 0, s, mv, pl, pv, U_new, U_old, m->d_tbuf);
+    } else {
+      return fail(CHNS_EINVAL, "op must be 0..3");
+    }
+  }
+  HIPCHK(hipGetLastError());
+  if (grid) *grid = (int64_t)g.x;
+  return CHNS_OK;
 }
 
 }  // extern "C"

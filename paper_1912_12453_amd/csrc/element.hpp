@@ -30,15 +30,17 @@ constexpr int kXor1 = 0xB1;
 constexpr int kXor2 = 0x4E;
 constexpr int kXor7 = 0x141;
 
+// Every lane of the wave is active whenever these run (all row and bank masks
+// set), so the moved value never falls back to an "old" operand.
 template <int CTRL>
 __device__ __forceinline__ float xchg(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 template <int CTRL>
 __device__ __forceinline__ double xchg(double v) {
   int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
 
@@ -71,70 +73,72 @@ struct VGH {  // value, gradient and mixed second derivatives
   T v, dx, dy, dz, dxy, dxz, dyz;
 };
 
+// One axis of the butterfly with d = partner - mine:
+//   value at the lane's Gauss point  mine + B*d   (A*mine + B*partner, A + B = 1)
+//   derivative along the axis       -s*d/h        (s*(mine - partner)/h)
 template <class T>
 __device__ __forceinline__ T eval_v(T u) {
-  const T A = (T)kA, B = (T)kB;
-  T v = A * u + B * xchg<kXor1>(u);
-  v = A * v + B * xchg<kXor2>(v);
-  return A * v + B * xchg<kXor7>(v);
+  const T B = (T)kB;
+  T v = u + B * (xchg<kXor1>(u) - u);
+  v = v + B * (xchg<kXor2>(v) - v);
+  return v + B * (xchg<kXor7>(v) - v);
 }
 
 template <class T>
 __device__ __forceinline__ VG<T> eval_vg(T u, const Lane<T>& L) {
-  const T A = (T)kA, B = (T)kB;
-  T p = xchg<kXor1>(u);
-  T v = A * u + B * p;
-  T dx = L.sxh * (u - p);
-  T pv = xchg<kXor2>(v), pdx = xchg<kXor2>(dx);
-  T v2 = A * v + B * pv;
-  T dy = L.syh * (v - pv);
-  T dx2 = A * dx + B * pdx;
-  T qv = xchg<kXor7>(v2), qdx = xchg<kXor7>(dx2), qdy = xchg<kXor7>(dy);
+  const T B = (T)kB;
+  const T d1 = xchg<kXor1>(u) - u;
+  const T v = u + B * d1;
+  const T dx = -L.sxh * d1;
+  const T d2 = xchg<kXor2>(v) - v, e2 = xchg<kXor2>(dx) - dx;
+  const T v2 = v + B * d2;
+  const T dy = -L.syh * d2;
+  const T dx2 = dx + B * e2;
+  const T d3 = xchg<kXor7>(v2) - v2, e3 = xchg<kXor7>(dx2) - dx2, f3 = xchg<kXor7>(dy) - dy;
   VG<T> r;
-  r.v = A * v2 + B * qv;
-  r.dz = L.szh * (v2 - qv);
-  r.dx = A * dx2 + B * qdx;
-  r.dy = A * dy + B * qdy;
+  r.v = v2 + B * d3;
+  r.dz = -L.szh * d3;
+  r.dx = dx2 + B * e3;
+  r.dy = dy + B * f3;
   return r;
 }
 
 template <class T>
 __device__ __forceinline__ VGH<T> eval_vgh(T u, const Lane<T>& L) {
-  const T A = (T)kA, B = (T)kB;
-  T p = xchg<kXor1>(u);
-  T v = A * u + B * p;
-  T dx = L.sxh * (u - p);
-  T pv = xchg<kXor2>(v), pdx = xchg<kXor2>(dx);
-  T v2 = A * v + B * pv;
-  T dy = L.syh * (v - pv);
-  T dxy = L.syh * (dx - pdx);
-  T dx2 = A * dx + B * pdx;
-  T qv = xchg<kXor7>(v2), qdx = xchg<kXor7>(dx2), qdy = xchg<kXor7>(dy), qdxy = xchg<kXor7>(dxy);
+  const T B = (T)kB;
+  const T d1 = xchg<kXor1>(u) - u;
+  const T v = u + B * d1;
+  const T dx = -L.sxh * d1;
+  const T d2 = xchg<kXor2>(v) - v, e2 = xchg<kXor2>(dx) - dx;
+  const T v2 = v + B * d2;
+  const T dy = -L.syh * d2;
+  const T dxy = -L.syh * e2;
+  const T dx2 = dx + B * e2;
+  const T d3 = xchg<kXor7>(v2) - v2, e3 = xchg<kXor7>(dx2) - dx2, f3 = xchg<kXor7>(dy) - dy,
+          g3 = xchg<kXor7>(dxy) - dxy;
   VGH<T> r;
-  r.v = A * v2 + B * qv;
-  r.dz = L.szh * (v2 - qv);
-  r.dx = A * dx2 + B * qdx;
-  r.dy = A * dy + B * qdy;
-  r.dxy = A * dxy + B * qdxy;
-  r.dxz = L.szh * (dx2 - qdx);
-  r.dyz = L.szh * (dy - qdy);
+  r.v = v2 + B * d3;
+  r.dz = -L.szh * d3;
+  r.dx = dx2 + B * e3;
+  r.dy = dy + B * f3;
+  r.dxy = dxy + B * g3;
+  r.dxz = -L.szh * e3;
+  r.dyz = -L.szh * f3;
   return r;
 }
 
 // sum over the element's Gauss points of N_a c + dN_a/dx Fx + dN_a/dy Fy +
-// dN_a/dz Fz, returned on the lane of corner a.
+// dN_a/dz Fz, returned on the lane of corner a (the transposed butterfly:
+// per axis c <- A*c + B*c_partner + s*(F + F_partner)/h).
 template <class T>
 __device__ __forceinline__ T test_contract(T c, T Fx, T Fy, T Fz, const Lane<T>& L) {
-  const T A = (T)kA, B = (T)kB;
-  T pc = xchg<kXor7>(c), pFz = xchg<kXor7>(Fz), pFx = xchg<kXor7>(Fx), pFy = xchg<kXor7>(Fy);
-  T c1 = A * c + B * pc + L.szh * (Fz + pFz);
-  T Fx1 = A * Fx + B * pFx;
-  T Fy1 = A * Fy + B * pFy;
-  T pc1 = xchg<kXor2>(c1), pFy1 = xchg<kXor2>(Fy1), pFx1 = xchg<kXor2>(Fx1);
-  T c2 = A * c1 + B * pc1 + L.syh * (Fy1 + pFy1);
-  T Fx2 = A * Fx1 + B * pFx1;
-  T pc2 = xchg<kXor1>(c2), pFx2 = xchg<kXor1>(Fx2);
-  return A * c2 + B * pc2 + L.sxh * (Fx2 + pFx2);
+  const T B = (T)kB;
+  const T c1 = c + B * (xchg<kXor7>(c) - c) + L.szh * (Fz + xchg<kXor7>(Fz));
+  const T Fx1 = Fx + B * (xchg<kXor7>(Fx) - Fx);
+  const T Fy1 = Fy + B * (xchg<kXor7>(Fy) - Fy);
+  const T c2 = c1 + B * (xchg<kXor2>(c1) - c1) + L.syh * (Fy1 + xchg<kXor2>(Fy1));
+  const T Fx2 = Fx1 + B * (xchg<kXor2>(Fx1) - Fx1);
+  return c2 + B * (xchg<kXor1>(c2) - c2) + L.sxh * (Fx2 + xchg<kXor1>(Fx2));
 }
 
 // Sum of a value over the 8 lanes of an element (every lane gets the sum).
@@ -163,6 +167,21 @@ template <>
 __device__ __forceinline__ const double* weights<double>(const MeshView& m) { return m.hw; }
 template <>
 __device__ __forceinline__ const float* weights<float>(const MeshView& m) { return m.hw32; }
+
+// Scatter plan on the device (see ScatterPlan in internal.hpp).
+struct PlanView {
+  const int32_t* tgt_off;     // per chunk
+  const int32_t* tgt;         // per target slot: node id
+  const int32_t* inc_off;     // per target slot
+  const uint8_t* inc_corner;  // local element * 8 + corner
+  const float* inc_w;
+  const int32_t* node_off;    // per node
+  const int32_t* node_slot;
+  const int64_t* touch_off;   // per element
+  const int64_t* ntouch_off;  // per node
+  const int64_t* ntouch_slot;
+  const uint8_t* bflags;      // per node
+};
 
 // Physical parameters in kernel form.
 struct PhysView {

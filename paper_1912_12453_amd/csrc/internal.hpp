@@ -58,4 +58,30 @@ struct HostMesh {
 // Returns "" or an error message.
 std::string build_host_mesh(const chns_mesh_spec& spec, HostMesh& out);
 
+// Scatter plan of the element loop (all integer, built once per mesh).
+// Elements are cut into Morton chunks of kChunk consecutive leaves, one
+// workgroup each.  The targets of chunk c are the independent nodes its
+// corners touch (directly or as constraint parents), sorted:
+// tgt[tgt_off[c] .. tgt_off[c+1]).  Target slot s sums, in this order, the
+// corner results inc_corner[k] (local element * 8 + corner) times inc_w[k] for
+// inc_off[s] <= k < inc_off[s+1].  Node n then sums the target slots
+// node_slot[node_off[n] .. node_off[n+1]) in increasing slot order.
+// For the node-block diagonal every element lists the nodes it touches (its
+// direct corners in corner order, then the parents of its hanging corners in
+// corner and constraint order, first occurrence only): touch_off[e] ..
+// touch_off[e+1]; node n sums touch_slot[ntouch_off[n] .. ntouch_off[n+1]).
+constexpr int kChunk = 32;
+struct ScatterPlan {
+  std::vector<int32_t> tgt_off, tgt, inc_off;
+  std::vector<uint8_t> inc_corner;
+  std::vector<float> inc_w;
+  std::vector<int32_t> node_off, node_slot;
+  std::vector<int64_t> touch_off;
+  std::vector<int64_t> ntouch_off, ntouch_slot;
+  int max_targets = 0;  // targets of the largest chunk
+  int max_inc = 0;      // incidences of the largest chunk
+  int max_touch = 0;
+};
+std::string build_scatter_plan(const HostMesh& m, ScatterPlan& out);
+
 }  // namespace chns

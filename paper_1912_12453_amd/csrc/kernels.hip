@@ -18,7 +18,11 @@
 namespace chns {
 namespace dev {
 
+constexpr int kChunkThreads = 256;  // 32 elements x 8 lanes per workgroup
+
 // ------------------------------------------------------------- helpers ----
+// Gathers NF fields of a node-major array for the lane's corner straight from
+// global memory (used by the kernels that do not stage the chunk).
 template <class TS, class T, int NF>
 __device__ __forceinline__ void gather(const MeshView& m, int ref, const TS* __restrict__ X,
                                        int ld, int f0, T (&out)[NF]) {
@@ -41,89 +45,187 @@ __device__ __forceinline__ void gather(const MeshView& m, int ref, const TS* __r
   }
 }
 
-template <class TO, class T, int NF>
-__device__ __forceinline__ void scatter(const MeshView& m, int ref, TO* __restrict__ Y, int ld,
-                                        int f0, const T (&r)[NF]) {
-  if (ref >= 0) {
-    TO* p = Y + (int64_t)ref * ld + f0;
-#pragma unroll
-    for (int f = 0; f < NF; ++f) unsafeAtomicAdd(p + f, (TO)r[f]);
-    return;
-  }
-  const int h = -1 - ref;
-  const int t0 = m.hoff[h], t1 = m.hoff[h + 1];
-  const auto* w = weights<T>(m);
-  for (int t = t0; t < t1; ++t) {
-    const T wt = w[t];
-    TO* p = Y + (int64_t)m.hids[t] * ld + f0;
-#pragma unroll
-    for (int f = 0; f < NF; ++f) unsafeAtomicAdd(p + f, (TO)(wt * r[f]));
-  }
-}
-
 template <class T>
 __device__ __forceinline__ T clamp1(T x) {
   return x > (T)1 ? (T)1 : (x < (T)-1 ? (T)-1 : x);
 }
 
+// Chunk staging in dynamic LDS.  A workgroup owns one chunk of 32 leaves.
+// Before any arithmetic it copies, with coalesced loads, the records of the
+// chunk's target nodes (NU fields of U^{k+1} and U^k, ND of the direction),
+// the sorted target list and the chunk's incidence lists; lanes then read
+// their corners from LDS.  Capacities come from the largest chunk of the
+// mesh.  Layout: val[cap_t][SV] (T) | res[256][SF] (T) | tgt[cap_t] |
+// ioff[cap_t+1] | iw[cap_i] (float) | icor[cap_i] (byte).
+struct ChunkCaps {
+  int cap_t, cap_i;
+};
+
+template <class T, int NU, int ND, int NF>
+struct ChunkLDS {
+  static constexpr int NV = 2 * NU + ND;
+  // record strides padded to an odd number of words so that lanes reading the
+  // same field of different records hit different LDS banks
+  static constexpr int SV = NV | 1;
+  static constexpr int SF = NF | 1;
+  T* val;
+  T* res;
+  int* tgt;
+  int* ioff;
+  float* iw;
+  uint8_t* icor;
+  int s0, cnt;
+  __host__ __device__ static size_t bytes(ChunkCaps c) {
+    return sizeof(T) * ((size_t)c.cap_t * SV + kChunkThreads * SF) + sizeof(int) * (2 * (size_t)c.cap_t + 1) +
+           5 * (size_t)c.cap_i;
+  }
+  __device__ __forceinline__ void carve(char* smem, ChunkCaps c) {
+    val = (T*)smem;
+    res = val + (size_t)c.cap_t * SV;
+    tgt = (int*)(res + kChunkThreads * SF);
+    ioff = tgt + c.cap_t;
+    iw = (float*)(ioff + c.cap_t + 1);
+    icor = (uint8_t*)(iw + c.cap_i);
+  }
+  template <class TS, class TD>
+  __device__ __forceinline__ void stage(const PlanView& pl, const TS* __restrict__ U1, const TS* __restrict__ U0,
+                        const TD* __restrict__ dU, int ldD, int offD) {
+    s0 = pl.tgt_off[blockIdx.x];
+    cnt = pl.tgt_off[blockIdx.x + 1] - s0;
+    const int i0 = pl.inc_off[s0];
+    const int ni = pl.inc_off[s0 + cnt] - i0;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) tgt[i] = pl.tgt[s0 + i];
+    for (int i = threadIdx.x; i <= cnt; i += blockDim.x) ioff[i] = pl.inc_off[s0 + i] - i0;
+    for (int i = threadIdx.x; i < ni; i += blockDim.x) {
+      iw[i] = pl.inc_w[i0 + i];
+      icor[i] = pl.inc_corner[i0 + i];
+    }
+    for (int i = threadIdx.x; i < cnt * NV; i += blockDim.x) {
+      const int j = i / NV, f = i - j * NV;
+      const int64_t g = pl.tgt[s0 + j];
+      T v;
+      if (f < NU) {
+        v = (T)U1[g * 6 + f];
+      } else if (ND == 0 || f < 2 * NU) {
+        v = (T)U0[g * 6 + f - NU];
+      } else {
+        if constexpr (ND > 0) v = (T)dU[g * ldD + offD + f - 2 * NU];
+      }
+      val[j * SV + f] = v;
+    }
+  }
+  // position of node g in the sorted target list
+  __device__ __forceinline__ int find(int g) const {
+    int lo = 0, hi = cnt;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (tgt[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+  }
+  // the lane's corner record (2NU+ND values), through the constraint when the
+  // corner hangs
+  __device__ __forceinline__ void corner(const MeshView& m, int ref, T (&out)[NV]) const {
+    if (ref >= 0) {
+      const T* p = val + find(ref) * SV;
+#pragma unroll
+      for (int f = 0; f < NV; ++f) out[f] = p[f];
+      return;
+    }
+#pragma unroll
+    for (int f = 0; f < NV; ++f) out[f] = (T)0;
+    const int h = -1 - ref;
+    const auto* w = weights<T>(m);
+    for (int t = m.hoff[h]; t < m.hoff[h + 1]; ++t) {
+      const T wt = w[t];
+      const T* p = val + find(m.hids[t]) * SV;
+#pragma unroll
+      for (int f = 0; f < NV; ++f) out[f] += wt * p[f];
+    }
+  }
+  // Element-loop epilogue: stage the corner results, then every target sums
+  // its incident corner results times the constraint weight in the plan's
+  // fixed order and writes one partial row.  No atomics, so results do not
+  // depend on scheduling.
+  __device__ __forceinline__ void finish(int corner_slot, const T (&r)[NF], T* __restrict__ partial) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) res[corner_slot * SF + f] = r[f];
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt * NF; i += blockDim.x) {
+      const int j = i / NF, f = i - j * NF;
+      T acc = 0;
+      for (int k = ioff[j]; k < ioff[j + 1]; ++k) acc += (T)iw[k] * res[icor[k] * SF + f];
+      partial[(int64_t)(s0 + j) * NF + f] = acc;
+    }
+  }
+};
+
 // ------------------------------------------------------------ CH block ----
 template <class T>
-__global__ __launch_bounds__(256) void k_ch_residual(MeshView m, PhysView p,
+__global__ __launch_bounds__(256) void k_ch_residual(MeshView m, PlanView pl, PhysView p,
+                                                     ChunkCaps caps,
                                                      const double* __restrict__ U1,
                                                      const double* __restrict__ U0,
-                                                     double* __restrict__ R, int ldR, int offR) {
+                                                     T* __restrict__ partial) {
+  extern __shared__ double smem_d[];
+  using CL = ChunkLDS<T, 5, 0, 2>;
+  CL S;
+  S.carve((char*)smem_d, caps);
   const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
-  const bool valid = e0 < m.E;
-  const int64_t e = valid ? e0 : m.E - 1;
+  const int64_t e = e0 < m.E ? e0 : m.E - 1;
   Lane<T> L;
   L.init(threadIdx.x & 7, m.level[e]);
   const int ref = m.elem[e * 8 + L.c];
-  T a[5], b[5];  // phi, mu, u, v, w at k+1 and k
-  gather<double, T, 5>(m, ref, U1, 6, 0, a);
-  gather<double, T, 5>(m, ref, U0, 6, 0, b);
-  const VG<T> ph = eval_vg<T>((T)0.5 * (a[0] + b[0]), L);
-  const VG<T> mu = eval_vg<T>((T)0.5 * (a[1] + b[1]), L);
-  const T dphi = eval_v<T>(a[0] - b[0]);
-  const T vx = eval_v<T>((T)0.5 * (a[2] + b[2]));
-  const T vy = eval_v<T>((T)0.5 * (a[3] + b[3]));
-  const T vz = eval_v<T>((T)0.5 * (a[4] + b[4]));
+  S.stage(pl, U1, U0, (const double*)nullptr, 0, 0);
+  __syncthreads();
+  T c[CL::NV];  // phi, mu, u, v, w at k+1, then at k
+  S.corner(m, ref, c);
+  const VG<T> ph = eval_vg<T>((T)0.5 * (c[0] + c[5]), L);
+  const VG<T> mu = eval_vg<T>((T)0.5 * (c[1] + c[6]), L);
+  const T dphi = eval_v<T>(c[0] - c[5]);
+  const T vx = eval_v<T>((T)0.5 * (c[2] + c[7]));
+  const T vy = eval_v<T>((T)0.5 * (c[3] + c[8]));
+  const T vz = eval_v<T>((T)0.5 * (c[4] + c[9]));
   const T w = L.wdet, kd = (T)p.inv_PeCn, cn2 = (T)p.Cn2;
   T r[2];
   r[0] = test_contract<T>(w * dphi * (T)p.inv_dt, w * (kd * mu.dx - vx * ph.v),
                           w * (kd * mu.dy - vy * ph.v), w * (kd * mu.dz - vz * ph.v), L);
   r[1] = test_contract<T>(w * (ph.v * ph.v * ph.v - ph.v - mu.v), w * cn2 * ph.dx,
                           w * cn2 * ph.dy, w * cn2 * ph.dz, L);
-  if (valid) scatter<double, T, 2>(m, ref, R, ldR, offR, r);
+  S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
 }
 
 template <class T, class TS, class TD>
-__global__ __launch_bounds__(256) void k_ch_jvp(MeshView m, PhysView p, const TS* __restrict__ U1,
-                                                const TS* __restrict__ U0,
+__global__ __launch_bounds__(256) void k_ch_jvp(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
+                                                const TS* __restrict__ U1, const TS* __restrict__ U0,
                                                 const TD* __restrict__ dU, int ldD, int offD,
-                                                TD* __restrict__ out, int ldO, int offO) {
+                                                T* __restrict__ partial) {
+  extern __shared__ double smem_d[];
+  using CL = ChunkLDS<T, 5, 2, 2>;
+  CL S;
+  S.carve((char*)smem_d, caps);
   const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
-  const bool valid = e0 < m.E;
-  const int64_t e = valid ? e0 : m.E - 1;
+  const int64_t e = e0 < m.E ? e0 : m.E - 1;
   Lane<T> L;
   L.init(threadIdx.x & 7, m.level[e]);
   const int ref = m.elem[e * 8 + L.c];
-  T a[5], b[5], d[2];
-  gather<TS, T, 5>(m, ref, U1, 6, 0, a);
-  gather<TS, T, 5>(m, ref, U0, 6, 0, b);
-  gather<TD, T, 2>(m, ref, dU, ldD, offD, d);
-  const T pt = eval_v<T>((T)0.5 * (a[0] + b[0]));
-  const T vx = eval_v<T>((T)0.5 * (a[2] + b[2]));
-  const T vy = eval_v<T>((T)0.5 * (a[3] + b[3]));
-  const T vz = eval_v<T>((T)0.5 * (a[4] + b[4]));
-  const VG<T> dp = eval_vg<T>(d[0], L);  // d phi^{k+1}; d phi~ = dp/2
-  const VG<T> dm = eval_vg<T>(d[1], L);  // d mu^{k+1};  d mu~  = dm/2
+  S.stage(pl, U1, U0, dU, ldD, offD);
+  __syncthreads();
+  T c[CL::NV];  // phi, mu, u, v, w at k+1 and at k, then d phi, d mu
+  S.corner(m, ref, c);
+  const T pt = eval_v<T>((T)0.5 * (c[0] + c[5]));
+  const T vx = eval_v<T>((T)0.5 * (c[2] + c[7]));
+  const T vy = eval_v<T>((T)0.5 * (c[3] + c[8]));
+  const T vz = eval_v<T>((T)0.5 * (c[4] + c[9]));
+  const VG<T> dp = eval_vg<T>(c[10], L);  // d phi^{k+1}; d phi~ = dp/2
+  const VG<T> dm = eval_vg<T>(c[11], L);  // d mu^{k+1};  d mu~  = dm/2
   const T w = L.wdet, hk = (T)0.5 * (T)p.inv_PeCn, hc = (T)0.5 * (T)p.Cn2, hp = (T)0.5 * dp.v;
   T r[2];
   r[0] = test_contract<T>(w * dp.v * (T)p.inv_dt, w * (hk * dm.dx - vx * hp),
                           w * (hk * dm.dy - vy * hp), w * (hk * dm.dz - vz * hp), L);
   r[1] = test_contract<T>(w * ((T)3 * pt * pt - (T)1) * hp - w * (T)0.5 * dm.v, w * hc * dp.dx,
                           w * hc * dp.dy, w * hc * dp.dz, L);
-  if (valid) scatter<TD, T, 2>(m, ref, out, ldO, offO, r);
+  S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
 }
 
 // ------------------------------------------------------------ NS block ----
@@ -288,89 +390,147 @@ __device__ __forceinline__ void ns_jvp_point(const PhysView& p, const Lane<T>& L
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_ns_residual(MeshView m, PhysView p,
+__global__ __launch_bounds__(256) void k_ns_residual(MeshView m, PlanView pl, PhysView p,
+                                                     ChunkCaps caps,
                                                      const double* __restrict__ U1,
                                                      const double* __restrict__ U0,
-                                                     double* __restrict__ R, int ldR, int offR,
-                                                     int* __restrict__ flag) {
+                                                     T* __restrict__ partial, int* __restrict__ flag) {
+  extern __shared__ double smem_d[];
+  using CL = ChunkLDS<T, 6, 0, 4>;
+  CL S;
+  S.carve((char*)smem_d, caps);
   const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const bool valid = e0 < m.E;
   const int64_t e = valid ? e0 : m.E - 1;
   Lane<T> L;
   L.init(threadIdx.x & 7, m.level[e]);
   const int ref = m.elem[e * 8 + L.c];
-  T a[6], b[6];
-  gather<double, T, 6>(m, ref, U1, 6, 0, a);
-  gather<double, T, 6>(m, ref, U0, 6, 0, b);
+  S.stage(pl, U1, U0, (const double*)nullptr, 0, 0);
+  __syncthreads();
+  T c[CL::NV];
+  S.corner(m, ref, c);
+  const T a[6] = {c[0], c[1], c[2], c[3], c[4], c[5]};
+  const T b[6] = {c[6], c[7], c[8], c[9], c[10], c[11]};
   NSPoint<T> P;
   ns_point<T>(p, L, a, b, P);
   T r[4];
   ns_residual_point<T>(p, L, P, r);
-  if (valid) {
-    if (!P.ok) atomicOr(flag, 1);
-    scatter<double, T, 4>(m, ref, R, ldR, offR, r);
-  }
+  if (valid && !P.ok) atomicOr(flag, 1);
+  S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
 }
 
 template <class T, class TS, class TD>
-__global__ __launch_bounds__(256) void k_ns_jvp(MeshView m, PhysView p, const TS* __restrict__ U1,
-                                                const TS* __restrict__ U0,
+__global__ __launch_bounds__(256) void k_ns_jvp(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
+                                                const TS* __restrict__ U1, const TS* __restrict__ U0,
                                                 const TD* __restrict__ dU, int ldD, int offD,
-                                                TD* __restrict__ out, int ldO, int offO) {
+                                                T* __restrict__ partial) {
+  extern __shared__ double smem_d[];
+  using CL = ChunkLDS<T, 6, 4, 4>;
+  CL S;
+  S.carve((char*)smem_d, caps);
   const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
-  const bool valid = e0 < m.E;
-  const int64_t e = valid ? e0 : m.E - 1;
+  const int64_t e = e0 < m.E ? e0 : m.E - 1;
   Lane<T> L;
   L.init(threadIdx.x & 7, m.level[e]);
   const int ref = m.elem[e * 8 + L.c];
-  T a[6], b[6], d[4];
-  gather<TS, T, 6>(m, ref, U1, 6, 0, a);
-  gather<TS, T, 6>(m, ref, U0, 6, 0, b);
-  gather<TD, T, 4>(m, ref, dU, ldD, offD, d);
+  S.stage(pl, U1, U0, dU, ldD, offD);
+  __syncthreads();
+  T c[CL::NV];
+  S.corner(m, ref, c);
+  const T a[6] = {c[0], c[1], c[2], c[3], c[4], c[5]};
+  const T b[6] = {c[6], c[7], c[8], c[9], c[10], c[11]};
   NSPoint<T> P;
   ns_point<T>(p, L, a, b, P);
   VG<T> dvt[3];
   T ddv[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const VG<T> g = eval_vg<T>(d[i], L);
+    const VG<T> g = eval_vg<T>(c[12 + i], L);
     ddv[i] = g.v;
     dvt[i].v = (T)0.5 * g.v;
     dvt[i].dx = (T)0.5 * g.dx;
     dvt[i].dy = (T)0.5 * g.dy;
     dvt[i].dz = (T)0.5 * g.dz;
   }
-  VG<T> dpt = eval_vg<T>((T)0.5 * d[3], L);
+  const VG<T> dpt = eval_vg<T>((T)0.5 * c[15], L);
   T r[4];
   ns_jvp_point<T>(p, L, P, dvt, ddv, dpt, r);
-  if (valid) scatter<TD, T, 4>(m, ref, out, ldO, offO, r);
+  S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
 }
 
-// ------------------------------------------------------ boundary rows ----
-// NS velocity rows of boundary nodes and the pressure row of the pinned node.
-__global__ void k_ns_bc_residual(const int32_t* __restrict__ bnodes, int64_t nb,
-                                 const double* __restrict__ U1, const double* __restrict__ U0,
-                                 double* __restrict__ R, int ldR, int offR) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nb) {
-    const int64_t n = bnodes[i];
+// -------------------------------------------------------- node gather ----
+// Every node sums its target slots in slot order and writes its rows of the
+// output (ld values per node starting at off; with ld = 6 the other block's
+// entries are set to 0).  Boundary rows of the NS block are written here too:
+// MODE 1 (residual) velocity rows v^{k+1} - v^k on boundary nodes and the
+// pressure row p^{k+1} - p^k of the pinned node; MODE 2 (JVP) the identity
+// rows dU.
+template <int NF, class TP, class TO, int MODE>
+__global__ void k_gather(PlanView pl, int64_t n, const TP* __restrict__ partial,
+                         TO* __restrict__ out, int ld, int off, const double* __restrict__ U1,
+                         const double* __restrict__ U0, const TO* __restrict__ dU, int ldD,
+                         int offD) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    TP acc[NF];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) R[n * ldR + offR + d] = U1[n * 6 + 2 + d] - U0[n * 6 + 2 + d];
+    for (int f = 0; f < NF; ++f) acc[f] = 0;
+    for (int k = pl.node_off[i]; k < pl.node_off[i + 1]; ++k) {
+      const int64_t s = pl.node_slot[k];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) acc[f] += partial[s * NF + f];
+    }
+    TO v[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[f] = (TO)acc[f];
+    if (MODE != 0) {
+      const uint8_t b = pl.bflags[i];
+      if (b & 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          v[d] = MODE == 1 ? (TO)(U1[i * 6 + 2 + d] - U0[i * 6 + 2 + d]) : dU[i * ldD + offD + d];
+      }
+      if (b & 2) v[3] = MODE == 1 ? (TO)(U1[i * 6 + 5] - U0[i * 6 + 5]) : dU[i * ldD + offD + 3];
+    }
+    TO* o = out + i * ld;
+    if (ld == NF) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) o[f] = v[f];
+    } else {
+      for (int f = 0; f < ld; ++f) o[f] = (f >= off && f < off + NF) ? v[f - off] : (TO)0;
+    }
   }
-  if (i == 0) R[offR + 3] = U1[5] - U0[5];
 }
 
-template <class TD>
-__global__ void k_ns_bc_jvp(const int32_t* __restrict__ bnodes, int64_t nb,
-                            const TD* __restrict__ dU, int ldD, int offD, TD* __restrict__ out,
-                            int ldO, int offO) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nb) {
-    const int64_t n = bnodes[i];
+// Node-block diagonal: node n sums its element touches; NS boundary rows
+// become identity rows.
+template <int NF>
+__global__ void k_gather_diag(PlanView pl, int64_t n, const double* __restrict__ tbuf,
+                              double* __restrict__ D) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double acc[NF * NF];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) out[n * ldO + offO + d] = dU[n * ldD + offD + d];
+    for (int f = 0; f < NF * NF; ++f) acc[f] = 0;
+    for (int64_t k = pl.ntouch_off[i]; k < pl.ntouch_off[i + 1]; ++k) {
+      const int64_t t = pl.ntouch_slot[k];
+#pragma unroll
+      for (int f = 0; f < NF * NF; ++f) acc[f] += tbuf[t * NF * NF + f];
+    }
+    if (NF == 4) {
+      const uint8_t b = pl.bflags[i];
+      if (b & 1)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[r * 4 + c] = r == c ? 1.0 : 0.0;
+      if (b & 2)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[12 + c] = c == 3 ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int f = 0; f < NF * NF; ++f) D[i * NF * NF + f] = acc[f];
   }
-  if (i == 0) out[offO + 3] = dU[offD + 3];
 }
 
 // ------------------------------------------------- node-block diagonal ----
@@ -396,9 +556,10 @@ __device__ __forceinline__ int lane_of_corner(int c) {
 }
 
 template <class T, int BLOCK>
-__global__ __launch_bounds__(256) void k_diag(MeshView m, PhysView p, const double* __restrict__ U1,
+__global__ __launch_bounds__(256) void k_diag(MeshView m, PlanView pl, PhysView p,
+                                              const double* __restrict__ U1,
                                               const double* __restrict__ U0,
-                                              double* __restrict__ Dg) {
+                                              double* __restrict__ tbuf) {
   constexpr int NF = BLOCK == 0 ? 2 : 4;
   const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const bool valid = e0 < m.E;
@@ -421,8 +582,10 @@ __global__ __launch_bounds__(256) void k_diag(MeshView m, PhysView p, const doub
     for (int d = 0; d < 3; ++d) ch_v[d] = eval_v<T>((T)0.5 * (a[2 + d] + b[2 + d]));
   }
   // candidate nodes: slot k < 8 is corner k's node when direct; slot 8 + 8*k + t
-  // is parent t of hanging corner k
+  // is parent t of hanging corner k.  The visited nodes are numbered in visiting
+  // order, the order in which the scatter plan lists the element's touches.
   const int max_t = 8;
+  int64_t touch = pl.touch_off[e];
   for (int slot = 0; slot < 8 + 8 * max_t; ++slot) {
     int n = -1;
     if (slot < 8) {
@@ -488,25 +651,10 @@ __global__ __launch_bounds__(256) void k_diag(MeshView m, PhysView p, const doub
 #pragma unroll
       for (int q = 0; q < NF; ++q) {
         const T col = group_sum<T>(s * r[q]);
-        if (valid && lane8 == 0) unsafeAtomicAdd(Dg + (int64_t)n * NF * NF + q * NF + f, (double)col);
+        if (valid && lane8 == q) tbuf[touch * NF * NF + q * NF + f] = (double)col;
       }
     }
-  }
-}
-
-// identity rows for the NS boundary rows of the diagonal blocks
-__global__ void k_diag_bc(const int32_t* __restrict__ bnodes, int64_t nb, double* __restrict__ Dg) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nb) {
-    double* B = Dg + (int64_t)bnodes[i] * 16;
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) B[r * 4 + c] = r == c ? 1.0 : 0.0;
-  }
-  if (i == 0) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Dg[12 + c] = c == 3 ? 1.0 : 0.0;
+    ++touch;
   }
 }
 

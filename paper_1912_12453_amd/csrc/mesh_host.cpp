@@ -393,3 +393,93 @@ std::string build_host_mesh(const chns_mesh_spec& s, HostMesh& M) {
 }
 
 }  // namespace chns
+
+namespace chns {
+
+std::string build_scatter_plan(const HostMesh& m, ScatterPlan& P) {
+  const int64_t E = (int64_t)m.leaf_key.size(), n = (int64_t)m.node_key.size();
+  const int64_t C = (E + kChunk - 1) / kChunk;
+  P = ScatterPlan();
+  P.tgt_off.assign(C + 1, 0);
+  P.inc_off.push_back(0);
+  std::vector<std::pair<int64_t, int64_t>> ent;  // (node, corner slot)
+  std::vector<float> entw;
+  std::vector<std::pair<std::pair<int64_t, int64_t>, float>> tmp;
+  for (int64_t c = 0; c < C; ++c) {
+    tmp.clear();
+    const int64_t e0 = c * kChunk, e1 = std::min(E, e0 + kChunk);
+    for (int64_t e = e0; e < e1; ++e)
+      for (int k = 0; k < 8; ++k) {
+        const int64_t slot = (e - e0) * 8 + k;
+        const int32_t r = m.elem[e * 8 + k];
+        if (r >= 0) {
+          tmp.push_back({{r, slot}, 1.0f});
+        } else {
+          const int32_t h = -1 - r;
+          for (int32_t t = m.hang_off[h]; t < m.hang_off[h + 1]; ++t)
+            tmp.push_back({{m.hang_ids[t], slot}, (float)m.hang_w[t]});
+        }
+      }
+    std::sort(tmp.begin(), tmp.end(),
+              [](const auto& a, const auto& b) { return a.first < b.first; });
+    int ntg = 0;
+    for (size_t i = 0; i < tmp.size(); ++i) {
+      if (i == 0 || tmp[i].first.first != tmp[i - 1].first.first) {
+        if (i) P.inc_off.push_back((int32_t)P.inc_corner.size());
+        P.tgt.push_back((int32_t)tmp[i].first.first);
+        ++ntg;
+      }
+      P.inc_corner.push_back((uint8_t)tmp[i].first.second);
+      P.inc_w.push_back(tmp[i].second);
+    }
+    if (!tmp.empty()) P.inc_off.push_back((int32_t)P.inc_corner.size());
+    P.tgt_off[c + 1] = P.tgt_off[c] + ntg;
+    P.max_targets = std::max(P.max_targets, ntg);
+    P.max_inc = std::max(P.max_inc, (int)tmp.size());
+    if ((int64_t)P.inc_corner.size() > INT32_MAX) return "scatter plan too large";
+  }
+  // node -> slots (counting sort keeps slots ascending)
+  const int64_t S = (int64_t)P.tgt.size();
+  P.node_off.assign(n + 1, 0);
+  for (int64_t s = 0; s < S; ++s) ++P.node_off[P.tgt[s] + 1];
+  for (int64_t i = 0; i < n; ++i) P.node_off[i + 1] += P.node_off[i];
+  P.node_slot.resize(S);
+  {
+    std::vector<int32_t> fill(P.node_off.begin(), P.node_off.end() - 1);
+    for (int64_t s = 0; s < S; ++s) P.node_slot[fill[P.tgt[s]]++] = (int32_t)s;
+  }
+  // touched nodes per element, in the order the diagonal kernel visits them
+  P.touch_off.assign(E + 1, 0);
+  std::vector<int32_t> touch;
+  touch.reserve(E * 9);
+  for (int64_t e = 0; e < E; ++e) {
+    const size_t start = touch.size();
+    for (int k = 0; k < 8; ++k)
+      if (m.elem[e * 8 + k] >= 0) touch.push_back(m.elem[e * 8 + k]);
+    for (int k = 0; k < 8; ++k) {
+      const int32_t r = m.elem[e * 8 + k];
+      if (r >= 0) continue;
+      const int32_t h = -1 - r;
+      for (int32_t t = m.hang_off[h]; t < m.hang_off[h + 1]; ++t) {
+        const int32_t g = m.hang_ids[t];
+        bool seen = false;
+        for (size_t q = start; q < touch.size(); ++q) seen = seen || touch[q] == g;
+        if (!seen) touch.push_back(g);
+      }
+    }
+    P.touch_off[e + 1] = (int64_t)touch.size();
+    P.max_touch = std::max(P.max_touch, (int)(touch.size() - start));
+  }
+  const int64_t T = (int64_t)touch.size();
+  P.ntouch_off.assign(n + 1, 0);
+  for (int64_t t = 0; t < T; ++t) ++P.ntouch_off[touch[t] + 1];
+  for (int64_t i = 0; i < n; ++i) P.ntouch_off[i + 1] += P.ntouch_off[i];
+  P.ntouch_slot.resize(T);
+  {
+    std::vector<int64_t> fill(P.ntouch_off.begin(), P.ntouch_off.end() - 1);
+    for (int64_t t = 0; t < T; ++t) P.ntouch_slot[fill[touch[t]]++] = t;
+  }
+  return "";
+}
+
+}  // namespace chns

@@ -1,0 +1,79 @@
+"""Parity at the benchmark's full size, in the launch configuration bench.py
+times: the level-9 bubble mesh (~1.13M leaves).  The oracle evaluates the
+rows of a sample of nodes one by one (all elements around each sampled node);
+the mass identity is checked over the whole mesh."""
+import numpy as np
+import pytest
+
+from paper_1912_12453_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup(orc):
+    import torch
+    from paper_1912_12453_amd import chns
+    assert torch.cuda.is_available()
+    w = W.bubble(level_max=9)
+    pm = chns.Mesh.from_spec(w.mesh)
+    print(f"case fullsize bubble_l9 E={pm.n_leaves} n={pm.n_nodes}", flush=True)
+    om = orc.Mesh(w.mesh.trees, w.mesh.level_min, w.mesh.level_max, w.mesh.phi0, w.mesh.band)
+    assert om.n_nodes == pm.n_nodes
+    xyz, bf = pm.nodes()
+    U1, U0 = W.bubble_state(xyz, bf, w)
+    dU = W.direction(pm.n_nodes, 3)
+    rng = np.random.default_rng(7)
+    a = pm.arrays()
+    parents = np.unique(a["hang_ids"])
+    rows = np.unique(np.concatenate([
+        rng.choice(pm.n_nodes, 1500, replace=False),
+        rng.choice(parents, 400, replace=False),
+        rng.choice(np.nonzero(bf & 1)[0], 100, replace=False), [0]])).astype(np.int32)
+    return dict(w=w, pm=pm, om=om, U1=U1, U0=U0, dU=dU, rows=rows, chns=chns, torch=torch)
+
+
+@pytest.mark.parametrize("block", [0, 1])
+def test_fullsize_residual_rows(setup, orc, block):
+    S = setup
+    t, c = S["torch"], S["chns"]
+    p = c.make_params(S["w"].physics)
+    d1 = t.tensor(S["U1"], device="cuda:0")
+    d0 = t.tensor(S["U0"], device="cuda:0")
+    R = S["pm"].residual(p, block, d1, d0).cpu().numpy()
+    ref = S["om"].residual_rows(orc.Params.make(**vars(S["w"].physics)), block, S["U1"], S["U0"],
+                                S["rows"])
+    fs = slice(0, 2) if block == 0 else slice(2, 6)
+    g = R[S["rows"]][:, fs]
+    r = ref[:, fs]
+    e = np.linalg.norm(g - r) / np.linalg.norm(r)
+    print(f"fullsize residual block {block}: rel2 {e:.2e} over {len(S['rows'])} rows", flush=True)
+    assert e < 1e-12
+    if block == 0:
+        m1, _ = S["pm"].diagnostics(p, d1)
+        m0, _ = S["pm"].diagnostics(p, d0)
+        lhs = R[:, 0].sum()
+        rhs = (m1 - m0) / S["w"].physics.dt
+        print(f"mass identity: sum R_phi {lhs:.12e} vs d(int phi)/dt {rhs:.12e}", flush=True)
+        assert abs(lhs - rhs) <= 1e-9 * max(abs(rhs), 1e-3)
+
+
+@pytest.mark.parametrize("block", [0, 1])
+def test_fullsize_jvp_rows(setup, orc, block):
+    S = setup
+    t, c = S["torch"], S["chns"]
+    p = c.make_params(S["w"].physics)
+    d1 = t.tensor(S["U1"], device="cuda:0")
+    d0 = t.tensor(S["U0"], device="cuda:0")
+    dd = t.tensor(S["dU"], device="cuda:0")
+    J = S["pm"].jvp(p, block, d1, d0, dd).cpu().numpy()
+    J32 = S["pm"].jvp(p, block, d1, d0, dd.float(), prec=c.CHNS_F32).cpu().numpy()
+    ref = S["om"].residual_rows(orc.Params.make(**vars(S["w"].physics)), block, S["U1"], S["U0"],
+                                S["rows"], dU=S["dU"])
+    fs = slice(0, 2) if block == 0 else slice(2, 6)
+    r = ref[:, fs]
+    e = np.linalg.norm(J[S["rows"]][:, fs] - r) / np.linalg.norm(r)
+    e32 = np.linalg.norm(J32[S["rows"]][:, fs].astype(np.float64) - r) / np.linalg.norm(r)
+    print(f"fullsize jvp block {block}: FP64 rel2 {e:.2e}, FP32 rel2 {e32:.2e}", flush=True)
+    assert e < 1e-12
+    assert e32 < 1e-4
