@@ -30,17 +30,18 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per element of the NS JVP element kernel (FP64), derived in
-# floating-point operations executed per element (8 lanes x the
-# FP64 add/mul/fma of one lane, fma = 2) and compulsory HBM bytes per element
-# (state U^{k+1}, U^k and direction dU of each node once, the output written
-# once, the element's 8 corner ids and level).
-NS_JVP_FLOPS_PER_ELEMENT = None  # filled from the kernel's instruction count
-NS_JVP_BYTES_PER_NODE = (6 + 6 + 4) * 8 + 4 * 8
+# Work per element of the NS JVP element kernel: floating-point operations
+# executed per element (8 lanes x the add/mul/fma of one lane in the kernel's
+# gfx950 code, fma = 2), and compulsory HBM bytes (per node: U^{k+1} and U^k,
+# 6 values each, the 4-value direction and the 4-value result; per element:
+# 8 corner ids and the level byte).
+NS_JVP_FLOPS_PER_ELEMENT = {"fp64": 7464, "mixed": 7392}
+NS_JVP_BYTES_PER_NODE = {"fp64": (6 + 6 + 4 + 4) * 8, "mixed": (6 + 6) * 8 + (4 + 4) * 4}
 NS_JVP_BYTES_PER_ELEMENT = 8 * 4 + 1
 
 PEAK_HBM_GBS = 8000.0
-PEAK_FP64_VALU_TFLOPS = 78.6
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # FP64 vector; FP32 vector
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def log(*a):
@@ -72,14 +73,7 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     name = args.workload
-    if name.startswith("bubble_l"):
-        w = W.bubble(level_max=int(name[len("bubble_l"):]))
-    elif name == "drop16":
-        w = W.drop16()
-    elif name.startswith("rt_l"):
-        w = W.rt(level_max=int(name[len("rt_l"):]))
-    else:
-        raise SystemExit(f"unknown workload {name}")
+    w = W.by_name(name)
 
     t0 = time.time()
     mesh = chns.Mesh.from_spec(w.mesh)
@@ -89,11 +83,7 @@ def main():
     n, E = mesh.n_nodes, mesh.n_leaves
     log(f"[bench] {name}: {E} leaves, {n} nodes, {mesh.stats.n_hanging} hanging; "
         f"mesh build + upload {t_mesh:.2f}s")
-    if name.startswith("bubble"):
-        U1h, U0h = W.bubble_state(xyz, bf, w)
-    else:
-        U0h = W.initial_state(xyz, w.mesh.phi0, bf, phi_noise=1e-3, seed=0)
-        U1h = W.perturbed(U0h, 1e-3, 2)
+    U1h, U0h = W.state_for(w, xyz, bf)
     dUh = W.direction(n, w.seeds.get("direction", 3))
     p = chns.make_params(w.physics)
     U0 = torch.tensor(U0h, device=dev)
@@ -158,19 +148,32 @@ def main():
         for oname in ("jvp_f64", "jvp_f32"):
             kern[f"{bname}_{oname}_gdofs"] = n * nf / kern[f"{bname}_{oname}_ms"] / 1e6
 
-    bytes_per_launch = n * NS_JVP_BYTES_PER_NODE + E * NS_JVP_BYTES_PER_ELEMENT
-    flops_per_element = float(os.environ.get("CHNS_NS_JVP_FLOPS", "0")) or None
+    # diagonal-block kernels (once per Newton iteration)
+    for blk, bname in ((chns.CHNS_BLOCK_CH, "ch"), (chns.CHNS_BLOCK_NS, "ns")):
+        chns.chns_launch_element_loop(mesh.h, p, blk, 3, U1, U0, None, None, 1)
+        ev0.record(stream)
+        chns.chns_launch_element_loop(mesh.h, p, blk, 3, U1, U0, None, None, 2)
+        ev1.record(stream)
+        ev1.synchronize()
+        kern[f"{bname}_diag_ms"] = ev0.elapsed_time(ev1) / 2
+
+    prec = args.precision
+    bytes_per_launch = n * NS_JVP_BYTES_PER_NODE[prec] + E * NS_JVP_BYTES_PER_ELEMENT
+    flops_per_launch = NS_JVP_FLOPS_PER_ELEMENT[prec] * E
     ach_gbs = bytes_per_launch / (ns_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(ach_gbs / PEAK_HBM_GBS, 4), "traffic": None,
-            "kernel": "k_ns_jvp<double,double,double>" if precision == 0 else "k_ns_jvp<float,double,float>",
-            "avg_ms": round(ns_ms, 4), "grid": grid, "block": 256,
-            "bytes_per_launch": bytes_per_launch}
-    if flops_per_element:
-        tf = flops_per_element * E / (ns_ms * 1e-3) / 1e12
-        roof.update({"bound": "alu", "achieved": round(tf, 2), "peak": PEAK_FP64_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_VALU_TFLOPS, 4),
-                     "hbm_GBps": round(ach_gbs, 1)})
+    tflops = flops_per_launch / (ns_ms * 1e-3) / 1e12
+    kname = "k_ns_jvp<double,double,double>" if precision == 0 else "k_ns_jvp<float,double,float>"
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        ent = tr.get("kernels", {}).get(kname)
+        if ent and ent.get("workload") == name and ent.get("leaves") == E:
+            traffic = ent["hbm_bytes_per_launch"]
+    roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_TFLOPS[prec],
+            "unit": "TFLOP/s", "frac": round(tflops / PEAK_TFLOPS[prec], 4), "traffic": traffic,
+            "kernel": kname, "avg_ms": round(ns_ms, 4), "grid": grid, "block": 256,
+            "flops_per_launch": flops_per_launch, "algorithmic_bytes_per_launch": bytes_per_launch,
+            "algorithmic_GBps": round(ach_gbs, 1), "hbm_frac": round(ach_gbs / PEAK_HBM_GBS, 4)}
 
     # ---- CPU baseline: the oracle's 6-DoF JVP on the same mesh and state
     cpu = None

@@ -373,8 +373,8 @@ struct Solver {
     if ((rc = dalloc(&w.Uk, n * 6, &B)) || (rc = dalloc(&w.Uprev, n * 6, &B)) ||
         (rc = dalloc(&w.r, N, &B)) || (rc = dalloc(&w.x, N, &B)) || (rc = dalloc(&w.D, n * 16, &B)) ||
         (rc = dalloc(&w.Di, n * 16, &B)) || (rc = dalloc(&w.Di32, n * 16, &B)) ||
-        (rc = dalloc(&w.part, (size_t)w.nb_part * dev::kMaxBasis, &B)) ||
-        (rc = dalloc(&w.dots, dev::kMaxBasis, &B)) || (rc = dalloc(&w.flag, 1, &B)))
+        (rc = dalloc(&w.part, (size_t)w.nb_part * (dev::kMaxBasis + 1), &B)) ||
+        (rc = dalloc(&w.dots, dev::kMaxBasis + 1, &B)) || (rc = dalloc(&w.flag, 1, &B)))
       return rc;
     if (o.precision == 0) {
       if ((rc = dalloc(&w.V64, N * (restart + 1), &B)) || (rc = dalloc(&w.Z64, N * restart, &B)) ||
@@ -386,22 +386,28 @@ struct Solver {
           (rc = dalloc(&w.U1f, n * 6, &B)) || (rc = dalloc(&w.U0f, n * 6, &B)))
         return rc;
     }
-    HIPCHK(hipHostMalloc((void**)&w.hdots, sizeof(double) * dev::kMaxBasis));
+    HIPCHK(hipHostMalloc((void**)&w.hdots, sizeof(double) * (dev::kMaxBasis + 1)));
     HIPCHK(hipHostMalloc((void**)&w.hflag, sizeof(int)));
     w.n = n;
     w.restart = restart;
     return CHNS_OK;
   }
 
-  template <class TV>
-  int dots(const TV* V, int64_t stride, int k, const TV* x, int64_t N, double* out) {
-    hipLaunchKernelGGL(dev::k_multidot<TV>, dim3(w.nb_part), dim3(256), 0, s, V, stride, k, x, N, w.part);
+  // sums the k partial rows left in w.part by a reduction kernel and copies
+  // them to the host
+  int finish_sums(int k, double* out) {
     hipLaunchKernelGGL(dev::k_finish_sum, dim3(k), dim3(256), 0, s, w.part, w.nb_part, k, w.dots);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(w.hdots, w.dots, sizeof(double) * k, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int j = 0; j < k; ++j) out[j] = w.hdots[j];
     return CHNS_OK;
+  }
+
+  template <class TV>
+  int dots(const TV* V, int64_t stride, int k, const TV* x, int64_t N, double* out) {
+    hipLaunchKernelGGL(dev::k_multidot<TV>, dim3(w.nb_part), dim3(256), 0, s, V, stride, k, x, N, w.part);
+    return finish_sums(k, out);
   }
 
   template <class TV>
@@ -461,17 +467,24 @@ struct Solver {
         if ((rc = precondition<TV>(block, Vk, Zk))) return rc;
         if ((rc = apply<TV>(block, Zk, wv, U1, U0))) return rc;
         ++*its;
-        for (int pass = 0; pass < 2; ++pass) {
-          if ((rc = dots<TV>(V, N, k + 1, wv, N, h.data()))) return rc;
-          dev::Coef c;
-          for (int j = 0; j <= k; ++j) {
-            c.c[j] = h[j];
-            Hat(j, k) += h[j];
-          }
-          hipLaunchKernelGGL(dev::k_multi_axpy<TV>, dim3(grid_stride(N)), dim3(256), 0, s, wv, V, N, k + 1, c, N);
+        // classical Gram-Schmidt twice (h = V^T w; w -= V h), the second update
+        // fused with ||w||^2
+        dev::Coef c;
+        if ((rc = dots<TV>(V, N, k + 1, wv, N, h.data()))) return rc;
+        for (int j = 0; j <= k; ++j) {
+          c.c[j] = h[j];
+          Hat(j, k) += h[j];
         }
+        hipLaunchKernelGGL(dev::k_multi_axpy<TV>, dim3(grid_stride(N)), dim3(256), 0, s, wv, V, N, k + 1, c, N);
+        if ((rc = dots<TV>(V, N, k + 1, wv, N, h2.data()))) return rc;
+        for (int j = 0; j <= k; ++j) {
+          c.c[j] = h2[j];
+          Hat(j, k) += h2[j];
+        }
+        hipLaunchKernelGGL(dev::k_axpy_norm<TV>, dim3(w.nb_part), dim3(256), 0, s, wv, V, N, k + 1, c, N,
+                           w.part);
         double hn;
-        if ((rc = dots<TV>(wv, 0, 1, wv, N, &hn))) return rc;
+        if ((rc = finish_sums(1, &hn))) return rc;
         hn = std::sqrt(hn);
         if (!std::isfinite(hn)) return fail(CHNS_ENONFINITE, "non-finite value in GMRES");
         Hat(k + 1, k) = hn;

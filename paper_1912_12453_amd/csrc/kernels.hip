@@ -334,13 +334,15 @@ __device__ __forceinline__ void ns_residual_point(const PhysView& p, const Lane<
   r[3] = test_contract<T>(w * P.Rc, q * P.Rm[0], q * P.Rm[1], q * P.Rm[2], L);
 }
 
-// Derivative of the NS rows in the direction (dv, dp) of (v^{k+1}, p^{k+1}):
-// dvt = dv/2 (value and gradient), ddv = dv (value), dpt = dp/2.
+// Derivative of the NS integrand in the direction (dv, dp) of (v^{k+1},
+// p^{k+1}) at the point: dvt = dv/2 (value and gradient), ddv = dv (value),
+// dpt = dp/2.  Returns the coefficients (c, F) of the momentum rows i = 0..2
+// and the continuity row 3, before the Gauss weight.
 template <class T>
-__device__ __forceinline__ void ns_jvp_point(const PhysView& p, const Lane<T>& L,
-                                             const NSPoint<T>& P, const VG<T> (&dvt)[3],
-                                             const T (&ddv)[3], const VG<T>& dpt, T (&r)[4]) {
-  const T w = L.wdet, iPe = (T)p.inv_Pe, iWe = (T)p.inv_We, tm = P.tau_m, ir = P.inv_rho;
+__device__ __forceinline__ void ns_jvp_coef(const PhysView& p, const NSPoint<T>& P,
+                                            const VG<T> (&dvt)[3], const T (&ddv)[3],
+                                            const VG<T>& dpt, T (&c)[4], T (&F)[4][3]) {
+  const T iPe = (T)p.inv_Pe, iWe = (T)p.inv_We, tm = P.tau_m, ir = P.inv_rho;
   const T er = P.eta * (T)p.inv_Re, idt = (T)p.inv_dt;
   T dG[3][3];
 #pragma unroll
@@ -374,19 +376,30 @@ __device__ __forceinline__ void ns_jvp_point(const PhysView& p, const Lane<T>& L
   const T dgl = iWe * (P.rho * (dtc * P.Rc + P.tau_c * dRc) - dpt.v);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    T c = P.rho * ddv[i] * idt;
+    T ci = P.rho * ddv[i] * idt;
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      c += (P.rho * P.vt[j] + iPe * P.J[j] - tm * P.Rm[j]) * dG[i][j] +
-           (P.rho * dvt[j].v - dTR[j]) * P.G[i][j];
-    T F[3];
+      ci += (P.rho * P.vt[j] + iPe * P.J[j] - tm * P.Rm[j]) * dG[i][j] +
+            (P.rho * dvt[j].v - dTR[j]) * P.G[i][j];
+    c[i] = ci;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) F[j] = dTR[i] * W[j] + P.Rm[i] * tm * dW[j] + er * dG[i][j];
-    F[i] += dgl;
-    r[i] = test_contract<T>(w * c, w * F[0], w * F[1], w * F[2], L);
+    for (int j = 0; j < 3; ++j) F[i][j] = dTR[i] * W[j] + P.Rm[i] * tm * dW[j] + er * dG[i][j];
+    F[i][i] += dgl;
   }
-  const T q = w * ir;
-  r[3] = test_contract<T>(w * dRc, q * dTR[0], q * dTR[1], q * dTR[2], L);
+  c[3] = dRc;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) F[3][j] = dTR[j] * ir;
+}
+
+template <class T>
+__device__ __forceinline__ void ns_jvp_point(const PhysView& p, const Lane<T>& L,
+                                             const NSPoint<T>& P, const VG<T> (&dvt)[3],
+                                             const T (&ddv)[3], const VG<T>& dpt, T (&r)[4]) {
+  T c[4], F[4][3];
+  ns_jvp_coef<T>(p, P, dvt, ddv, dpt, c, F);
+  const T w = L.wdet;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r[i] = test_contract<T>(w * c[i], w * F[i][0], w * F[i][1], w * F[i][2], L);
 }
 
 template <class T>
@@ -556,6 +569,74 @@ __device__ __forceinline__ int lane_of_corner(int c) {
 }
 
 template <class T, int BLOCK>
+__device__ __forceinline__ void diag_regular(const PhysView& p, const Lane<T>& L,
+                                             const NSPoint<T>& P, T ch_pt, const T (&ch_v)[3],
+                                             double* __restrict__ out, bool valid) {
+  constexpr int NF = BLOCK == 0 ? 2 : 4;
+  const T A = (T)kA, B = (T)kB;
+  const bool qx = L.sxh > (T)0, qy = L.syh > (T)0, qz = L.szh > (T)0;
+  const T ih = (T)1 / L.h, w = L.wdet;
+#pragma unroll 1
+  for (int a = 0; a < 8; ++a) {
+    // seed N_a at this Gauss point: shape factor A on an axis where the corner
+    // and the point share a side, B otherwise
+    const bool ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    const T mx = ax == qx ? A : B, my = ay == qy ? A : B, mz = az == qz ? A : B;
+    const T N = mx * my * mz;
+    const T gx = (ax ? ih : -ih) * my * mz, gy = (ay ? ih : -ih) * mx * mz,
+            gz = (az ? ih : -ih) * mx * my;
+#pragma unroll 1
+    for (int f = 0; f < NF; ++f) {
+      T c[NF], F[NF][3];
+      if (BLOCK == 1) {
+        VG<T> dvt[3];
+        T ddv[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const T sd = f == i ? (T)1 : (T)0;
+          ddv[i] = sd * N;
+          dvt[i].v = (T)0.5 * sd * N;
+          dvt[i].dx = (T)0.5 * sd * gx;
+          dvt[i].dy = (T)0.5 * sd * gy;
+          dvt[i].dz = (T)0.5 * sd * gz;
+        }
+        const T sp = f == 3 ? (T)0.5 : (T)0;
+        VG<T> dpt;
+        dpt.v = sp * N;
+        dpt.dx = sp * gx;
+        dpt.dy = sp * gy;
+        dpt.dz = sp * gz;
+        T c4[4], F4[4][3];
+        ns_jvp_coef<T>(p, P, dvt, ddv, dpt, c4, F4);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          c[i] = c4[i];
+          F[i][0] = F4[i][0];
+          F[i][1] = F4[i][1];
+          F[i][2] = F4[i][2];
+        }
+      } else {
+        const T dp = f == 0 ? (T)1 : (T)0, dm = f == 1 ? (T)1 : (T)0;
+        const T hk = (T)0.5 * (T)p.inv_PeCn, hc = (T)0.5 * (T)p.Cn2, hp = (T)0.5 * dp * N;
+        c[0] = dp * N * (T)p.inv_dt;
+        F[0][0] = hk * dm * gx - ch_v[0] * hp;
+        F[0][1] = hk * dm * gy - ch_v[1] * hp;
+        F[0][2] = hk * dm * gz - ch_v[2] * hp;
+        c[1] = ((T)3 * ch_pt * ch_pt - (T)1) * hp - (T)0.5 * dm * N;
+        F[1][0] = hc * dp * gx;
+        F[1][1] = hc * dp * gy;
+        F[1][2] = hc * dp * gz;
+      }
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        const T t = group_sum<T>(w * (N * c[i] + gx * F[i][0] + gy * F[i][1] + gz * F[i][2]));
+        if (valid && L.c == a) out[a * NF * NF + i * NF + f] = (double)t;
+      }
+    }
+  }
+}
+
+template <class T, int BLOCK>
 __global__ __launch_bounds__(256) void k_diag(MeshView m, PlanView pl, PhysView p,
                                               const double* __restrict__ U1,
                                               const double* __restrict__ U0,
@@ -581,9 +662,21 @@ __global__ __launch_bounds__(256) void k_diag(MeshView m, PlanView pl, PhysView 
 #pragma unroll
     for (int d = 0; d < 3; ++d) ch_v[d] = eval_v<T>((T)0.5 * (a[2 + d] + b[2 + d]));
   }
-  // candidate nodes: slot k < 8 is corner k's node when direct; slot 8 + 8*k + t
-  // is parent t of hanging corner k.  The visited nodes are numbered in visiting
-  // order, the order in which the scatter plan lists the element's touches.
+  // Elements without hanging corners: the diagonal block of corner a is
+  // sum_q wdet [N_a(q) dc(N_a) + grad N_a(q) . dF(N_a)], with the seed N_a e_f
+  // known in closed form at the lane's Gauss point.  Each lane evaluates the
+  // linearised integrand for all 8 corners and NF fields; sums over the
+  // element's lanes give corner a's block, which lane a writes to the element's
+  // touch slot a (direct corners come first, in corner order).
+  const bool hanging = group_sum<float>(ref < 0 ? 1.f : 0.f) > 0.f;
+  if (!hanging) {
+    diag_regular<T, BLOCK>(p, L, P, ch_pt, ch_v, tbuf + pl.touch_off[e] * NF * NF, valid);
+    return;
+  }
+  // General elements: slot k < 8 is corner k's node when direct; slot
+  // 8 + 8*k + t is parent t of hanging corner k.  The visited nodes are numbered
+  // in visiting order, the order in which the scatter plan lists the element's
+  // touches.
   const int max_t = 8;
   int64_t touch = pl.touch_off[e];
   for (int slot = 0; slot < 8 + 8 * max_t; ++slot) {

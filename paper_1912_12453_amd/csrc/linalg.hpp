@@ -54,14 +54,17 @@ __device__ __forceinline__ double block_reduce_sum(double v, double* sh) {
   return r;  // valid on thread 0
 }
 
+// max that lets a NaN through (fmax would drop it)
+__device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
 __device__ __forceinline__ double block_reduce_max(double v, double* sh) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  for (int o = 32; o > 0; o >>= 1) v = nan_max(v, __shfl_xor(v, o, 64));
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (l == 0) sh[w] = v;
   __syncthreads();
   double r = 0;
   if (threadIdx.x == 0)
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r = fmax(r, sh[i]);
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r = nan_max(r, sh[i]);
   __syncthreads();
   return r;
 }
@@ -102,7 +105,7 @@ __global__ void k_finish_sum(const double* __restrict__ part, int nb, int k, dou
 __global__ void k_finish_max(const double* __restrict__ part, int nb, double* __restrict__ out) {
   __shared__ double sh[4];
   double s = 0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) s = fmax(s, part[b]);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s = nan_max(s, part[b]);
   s = block_reduce_max(s, sh);
   if (threadIdx.x == 0) out[0] = s;
 }
@@ -119,6 +122,27 @@ __global__ void k_multi_axpy(TV* __restrict__ w, const TV* __restrict__ V, int64
       if (j < k) s -= c.c[j] * (double)V[j * stride + i];
     w[i] = (TV)s;
   }
+}
+
+// w -= sum_{j<k} c_j V_j and the partial sums of w . w (slot 0)
+template <class TV>
+__global__ __launch_bounds__(256) void k_axpy_norm(TV* __restrict__ w, const TV* __restrict__ V,
+                                                   int64_t stride, int k, Coef c, int64_t n,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[4];
+  double acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = (double)w[i];
+#pragma unroll
+    for (int j = 0; j < kMaxBasis; ++j)
+      if (j < k) s -= c.c[j] * (double)V[j * stride + i];
+    const TV st = (TV)s;
+    w[i] = st;
+    acc += (double)st * (double)st;
+  }
+  const double t = block_reduce_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // x += sum_{j<k} c_j Z_j  (x in FP64)
@@ -244,7 +268,7 @@ __global__ void k_maxabs_diff(const double* __restrict__ a, const double* __rest
   double m = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    m = fmax(m, fabs(a[i] - b[i]));
+    m = nan_max(m, fabs(a[i] - b[i]));
   m = block_reduce_max(m, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = m;
 }

@@ -274,3 +274,27 @@ def bubble_state(xyz, bflags, w, seeds=None):
                        velocity_seed=seeds.get("velocity", 1))
     U1 = perturbed(U0, 1e-3, seeds.get("perturb", 2))
     return U1, U0
+
+
+def by_name(name):
+    """The workload called bubble_l<L>, rt_l<L> or drop<2^L>."""
+    if name.startswith("bubble_l"):
+        return bubble(level_max=int(name[len("bubble_l"):]))
+    if name.startswith("rt_l"):
+        return rt(level_max=int(name[len("rt_l"):]))
+    if name.startswith("drop"):
+        side = int(name[len("drop"):])
+        level = side.bit_length() - 1
+        if side != 1 << level:
+            raise ValueError(f"drop side {side} is not a power of two")
+        return drop16(level)
+    raise ValueError(f"unknown workload {name}")
+
+
+def state_for(w, xyz, bflags):
+    """(U^{k+1}, U^k) of a named workload on the nodes xyz: the bubble fields for
+    bubble meshes, else phi0 with 1e-3 noise and a 1e-3 perturbation."""
+    if w.name.startswith("bubble"):
+        return bubble_state(xyz, bflags, w)
+    U0 = initial_state(xyz, w.mesh.phi0, bflags, phi_noise=1e-3, seed=0)
+    return perturbed(U0, 1e-3, w.seeds.get("perturb", 2)), U0
