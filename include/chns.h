@@ -170,7 +170,7 @@ typedef struct {
   double block_tol;    /* 1e-4: max change of all fields between two sweeps  */
   double gmres_rtol;   /* 1e-7 (FP64) / 1e-5 is typical for mixed precision  */
   int32_t newton_max_it_ch, newton_max_it_ns; /* 20, 40                      */
-  int32_t gmres_restart;                      /* 30                          */
+  int32_t gmres_restart;                      /* 1..127; 120: basis of (2m+3) block vectors */
   int32_t gmres_max_it;                       /* 1000 per linear solve       */
   int32_t block_max_it;                       /* 10                          */
   int32_t block_min_it;                       /* 1: sweeps 0 and 1 always run */
@@ -178,6 +178,11 @@ typedef struct {
                           preconditioner, basis) with FP64 dot products,
                           Hessenberg, update and Newton residual            */
   int32_t precond;     /* 0: point Jacobi; 1: node-block Jacobi             */
+  int32_t graphs;      /* 1: each GMRES restart cycle is captured once as a
+                          HIP graph (per mesh, block, precision, restart
+                          length and parameters) and replayed; 0: the same
+                          kernels are launched one by one.  Results are
+                          identical.                                        */
 } chns_solver_opts;
 
 typedef struct {
@@ -193,8 +198,10 @@ typedef struct {
 } chns_step_stats;
 
 /* One Crank-Nicolson step (Fig. 1): U (device, n_nodes*6) holds U^k on entry
- * and U^{k+1} on return.  Synchronises the stream (the Newton and GMRES
- * control decisions are taken on the host from device-computed FP64 norms).
+ * and U^{k+1} on return.  Synchronises the stream: Newton decisions are taken
+ * on the host from device-computed FP64 norms; GMRES runs its Arnoldi
+ * control (Hessenberg, Givens rotations, stopping test) on the device and
+ * the host waits once per restart cycle.
  * Work buffers are allocated on first use and kept with the mesh.  Returns
  * CHNS_NOT_CONVERGED with U and stats written when a tolerance was missed. */
 int chns_step(chns_mesh* mesh, const chns_params* params, const chns_solver_opts* opts,

@@ -63,7 +63,8 @@ class chns_solver_opts(C.Structure):
                 ("newton_max_it_ch", C.c_int32), ("newton_max_it_ns", C.c_int32),
                 ("gmres_restart", C.c_int32), ("gmres_max_it", C.c_int32),
                 ("block_max_it", C.c_int32), ("block_min_it", C.c_int32),
-                ("precision", C.c_int32), ("precond", C.c_int32)]
+                ("precision", C.c_int32), ("precond", C.c_int32),
+                ("graphs", C.c_int32)]
 
 
 class chns_step_stats(C.Structure):
@@ -127,11 +128,11 @@ def make_params(physics):
 
 
 def make_opts(newton_rtol=1e-8, newton_atol=1e-12, block_tol=1e-4, gmres_rtol=1e-7,
-              newton_max_it_ch=20, newton_max_it_ns=40, gmres_restart=30, gmres_max_it=1000,
-              block_max_it=10, block_min_it=1, precision=0, precond=1):
+              newton_max_it_ch=20, newton_max_it_ns=40, gmres_restart=120, gmres_max_it=1000,
+              block_max_it=10, block_min_it=1, precision=0, precond=1, graphs=1):
     return chns_solver_opts(newton_rtol, newton_atol, block_tol, gmres_rtol, newton_max_it_ch,
                             newton_max_it_ns, gmres_restart, gmres_max_it, block_max_it,
-                            block_min_it, precision, precond)
+                            block_min_it, precision, precond, graphs)
 
 
 # ------------------------------------------------ C ABI, same names ------

@@ -51,9 +51,19 @@ inline unsigned grid_stride(int64_t n, int block = 256, int cap = 2048) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap, (n + block - 1) / block));
 }
 
+// A part of a GMRES restart cycle captured as a HIP graph, valid for one
+// block, basis type, restart length and parameter set of the mesh it was
+// captured on.
+struct CycleGraph {
+  int block = 0, tv = 0, mres = 0, seg = 0;
+  dev::PhysView pv;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct Workspace {
   int64_t n = 0;
-  int restart = 0;
+  int restart64 = 0, restart32 = 0;  // basis length allocated per precision
+  double *U1 = nullptr;              // the step's iterate U^{k+1}
   double *Uk = nullptr, *Uprev = nullptr, *r = nullptr, *x = nullptr;
   double *D = nullptr, *Di = nullptr;
   float *Di32 = nullptr, *U1f = nullptr, *U0f = nullptr;
@@ -63,9 +73,53 @@ struct Workspace {
   double* hdots = nullptr;  // pinned host
   int* flag = nullptr;
   int* hflag = nullptr;     // pinned host
+  dev::GmresCtl* ctl = nullptr;
+  int* hctl = nullptr;      // pinned host: the first ints of *ctl
+  hipStream_t cap = nullptr;  // capture stream (graphs are launched on the caller's)
+  std::vector<CycleGraph> graphs;
   int nb_part = 0;
   int64_t bytes = 0;
 };
+
+void drop_graphs(Workspace& w) {
+  for (auto& g : w.graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  w.graphs.clear();
+}
+
+void free_basis(Workspace& w, int precision) {
+  drop_graphs(w);
+  const int64_t N = w.n * 4;
+  if (precision == 0) {
+    if (w.V64) w.bytes -= (N * (2 * w.restart64 + 3)) * (int64_t)sizeof(double);
+    void* ptrs[] = {w.V64, w.Z64, w.w64, w.b64};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    w.V64 = w.Z64 = w.w64 = w.b64 = nullptr;
+    w.restart64 = 0;
+  } else {
+    if (w.V32) w.bytes -= (N * (2 * w.restart32 + 3) + w.n * 12) * (int64_t)sizeof(float);
+    void* ptrs[] = {w.V32, w.Z32, w.w32, w.b32, w.U1f, w.U0f};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    w.V32 = w.Z32 = w.w32 = w.b32 = nullptr;
+    w.U1f = w.U0f = nullptr;
+    w.restart32 = 0;
+  }
+}
+
+void free_workspace(Workspace& w) {
+  free_basis(w, 0);
+  free_basis(w, 1);
+  void* ptrs[] = {w.U1, w.Uk, w.Uprev, w.r, w.x, w.D, w.Di, w.Di32, w.part, w.dots, w.flag, w.ctl};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (w.hdots) (void)hipHostFree(w.hdots);
+  if (w.hflag) (void)hipHostFree(w.hflag);
+  if (w.hctl) (void)hipHostFree(w.hctl);
+  if (w.cap) (void)hipStreamDestroy(w.cap);
+  w = Workspace();
+}
 
 }  // namespace
 
@@ -265,7 +319,7 @@ int launch_residual(chns_mesh* m, const dev::PhysView& pv, int block, const doub
     hipLaunchKernelGGL(dev::k_ch_residual<double>, g, b, (dev::ChunkLDS<double, 5, 0, 2>::bytes(cc)), s,
                        mv, pl, pv, cc, U1, U0, part);
     hipLaunchKernelGGL((dev::k_gather<2, double, double, 0>), dim3(grid_stride(n)), dim3(256), 0, s,
-                       pl, n, part, R, ld, off, U1, U0, (const double*)nullptr, 0, 0);
+                       pl, n, part, R, ld, off, U1, U0, (const double*)nullptr, 0, 0, (const int*)nullptr);
     HIPCHK(hipGetLastError());
     return CHNS_OK;
   }
@@ -273,7 +327,7 @@ int launch_residual(chns_mesh* m, const dev::PhysView& pv, int block, const doub
   hipLaunchKernelGGL(dev::k_ns_residual<double>, g, b, (dev::ChunkLDS<double, 6, 0, 4>::bytes(cc)), s, mv,
                      pl, pv, cc, U1, U0, part, m->d_flag);
   hipLaunchKernelGGL((dev::k_gather<4, double, double, 1>), dim3(grid_stride(n)), dim3(256), 0, s, pl,
-                     n, part, R, ld, off, U1, U0, (const double*)nullptr, 0, 0);
+                     n, part, R, ld, off, U1, U0, (const double*)nullptr, 0, 0, (const int*)nullptr);
   HIPCHK(hipGetLastError());
   if (check_tau) {
     HIPCHK(hipMemcpyAsync(m->h_flag, m->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -287,7 +341,8 @@ int launch_residual(chns_mesh* m, const dev::PhysView& pv, int block, const doub
 // are kept in T)
 template <class T, class TS, class TD>
 int launch_jvp(chns_mesh* m, const dev::PhysView& pv, int block, const TS* U1, const TS* U0,
-               const TD* dU, int ldD, int offD, TD* out, int ldO, int offO, hipStream_t s) {
+               const TD* dU, int ldD, int offD, TD* out, int ldO, int offO, hipStream_t s,
+               const int* skip = nullptr) {
   const int64_t n = (int64_t)m->h.node_key.size();
   const auto mv = view(m);
   const auto pl = plan_view(m);
@@ -296,14 +351,14 @@ int launch_jvp(chns_mesh* m, const dev::PhysView& pv, int block, const TS* U1, c
   T* part = (T*)m->d_partial;
   if (block == CHNS_BLOCK_CH) {
     hipLaunchKernelGGL((dev::k_ch_jvp<T, TS, TD>), g, b, (dev::ChunkLDS<T, 5, 2, 2>::bytes(cc)), s, mv, pl,
-                       pv, cc, U1, U0, dU, ldD, offD, part);
+                       pv, cc, U1, U0, dU, ldD, offD, part, skip);
     hipLaunchKernelGGL((dev::k_gather<2, T, TD, 0>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part,
-                       out, ldO, offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD);
+                       out, ldO, offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD, skip);
   } else {
     hipLaunchKernelGGL((dev::k_ns_jvp<T, TS, TD>), g, b, (dev::ChunkLDS<T, 6, 4, 4>::bytes(cc)), s, mv, pl,
-                       pv, cc, U1, U0, dU, ldD, offD, part);
+                       pv, cc, U1, U0, dU, ldD, offD, part, skip);
     hipLaunchKernelGGL((dev::k_gather<4, T, TD, 2>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part,
-                       out, ldO, offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD);
+                       out, ldO, offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD, skip);
   }
   HIPCHK(hipGetLastError());
   return CHNS_OK;
@@ -334,7 +389,8 @@ int launch_diagnostics(chns_mesh* m, const dev::PhysView& pv, const double* U, d
   const auto mv = view(m);
   hipLaunchKernelGGL(dev::k_diagnostics, dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, m->d_anchor,
                      std::ldexp(1.0, -m->h.D), U, m->d_part);
-  hipLaunchKernelGGL(dev::k_finish_sum, dim3(2), dim3(256), 0, s, m->d_part, (int)E, 2, m->d_sum);
+  hipLaunchKernelGGL(dev::k_finish_sum, dim3(2), dim3(256), 0, s, m->d_part, (int)E, 2, m->d_sum,
+                     (const int*)nullptr);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(m->h_sum, m->d_sum, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -355,48 +411,56 @@ struct Solver {
       : m(m_), pv(pv_), o(o_), s(s_), w(m_->ws), n((int64_t)m_->h.node_key.size()) {}
 
   int ensure_workspace() {
-    const int restart = o.gmres_restart;
-    if (w.n == n && w.restart >= restart) return CHNS_OK;
-    if (w.n) {
-      void* ptrs[] = {w.Uk, w.Uprev, w.r, w.x, w.D, w.Di, w.Di32, w.U1f, w.U0f, w.V64, w.Z64,
-                      w.w64, w.b64, w.V32, w.Z32, w.w32, w.b32, w.part, w.dots, w.flag};
-      for (void* p : ptrs)
-        if (p) (void)hipFree(p);
-      if (w.hdots) (void)hipHostFree(w.hdots);
-      if (w.hflag) (void)hipHostFree(w.hflag);
-      w = Workspace();
-    }
-    const size_t N = (size_t)n * 4;
-    w.nb_part = (int)grid_stride((int64_t)N, 256, 1024);
     int rc;
     int64_t& B = w.bytes;
-    if ((rc = dalloc(&w.Uk, n * 6, &B)) || (rc = dalloc(&w.Uprev, n * 6, &B)) ||
-        (rc = dalloc(&w.r, N, &B)) || (rc = dalloc(&w.x, N, &B)) || (rc = dalloc(&w.D, n * 16, &B)) ||
-        (rc = dalloc(&w.Di, n * 16, &B)) || (rc = dalloc(&w.Di32, n * 16, &B)) ||
-        (rc = dalloc(&w.part, (size_t)w.nb_part * (dev::kMaxBasis + 1), &B)) ||
-        (rc = dalloc(&w.dots, dev::kMaxBasis + 1, &B)) || (rc = dalloc(&w.flag, 1, &B)))
-      return rc;
-    if (o.precision == 0) {
-      if ((rc = dalloc(&w.V64, N * (restart + 1), &B)) || (rc = dalloc(&w.Z64, N * restart, &B)) ||
-          (rc = dalloc(&w.w64, N, &B)) || (rc = dalloc(&w.b64, N, &B)))
+    const size_t N = (size_t)n * 4;
+    if (w.n != n) {
+      free_workspace(w);
+      w.nb_part = (int)grid_stride((int64_t)N, 256, 1024);
+      if ((rc = dalloc(&w.U1, n * 6, &B)) || (rc = dalloc(&w.Uk, n * 6, &B)) ||
+          (rc = dalloc(&w.Uprev, n * 6, &B)) || (rc = dalloc(&w.r, N, &B)) || (rc = dalloc(&w.x, N, &B)) ||
+          (rc = dalloc(&w.D, n * 16, &B)) || (rc = dalloc(&w.Di, n * 16, &B)) ||
+          (rc = dalloc(&w.Di32, n * 16, &B)) ||
+          (rc = dalloc(&w.part, (size_t)w.nb_part * (dev::kMaxBasis + 1), &B)) ||
+          (rc = dalloc(&w.dots, dev::kMaxBasis + 1, &B)) || (rc = dalloc(&w.flag, 1, &B)) ||
+          (rc = dalloc(&w.ctl, 1, &B))) {
+        free_workspace(w);
         return rc;
-    } else {
+      }
+      HIPCHK(hipHostMalloc((void**)&w.hdots, sizeof(double) * (dev::kMaxBasis + 1)));
+      HIPCHK(hipHostMalloc((void**)&w.hflag, sizeof(int)));
+      HIPCHK(hipHostMalloc((void**)&w.hctl, sizeof(int) * 8));
+      HIPCHK(hipStreamCreateWithFlags(&w.cap, hipStreamNonBlocking));
+      w.n = n;
+    }
+    const int restart = o.gmres_restart;
+    if (o.precision == 0 && w.restart64 < restart) {
+      free_basis(w, 0);
+      if ((rc = dalloc(&w.V64, N * (restart + 1), &B)) || (rc = dalloc(&w.Z64, N * restart, &B)) ||
+          (rc = dalloc(&w.w64, N, &B)) || (rc = dalloc(&w.b64, N, &B))) {
+        free_basis(w, 0);
+        return rc;
+      }
+      w.restart64 = restart;
+    }
+    if (o.precision == 1 && w.restart32 < restart) {
+      free_basis(w, 1);
       if ((rc = dalloc(&w.V32, N * (restart + 1), &B)) || (rc = dalloc(&w.Z32, N * restart, &B)) ||
           (rc = dalloc(&w.w32, N, &B)) || (rc = dalloc(&w.b32, N, &B)) ||
-          (rc = dalloc(&w.U1f, n * 6, &B)) || (rc = dalloc(&w.U0f, n * 6, &B)))
+          (rc = dalloc(&w.U1f, n * 6, &B)) || (rc = dalloc(&w.U0f, n * 6, &B))) {
+        free_basis(w, 1);
         return rc;
+      }
+      w.restart32 = restart;
     }
-    HIPCHK(hipHostMalloc((void**)&w.hdots, sizeof(double) * (dev::kMaxBasis + 1)));
-    HIPCHK(hipHostMalloc((void**)&w.hflag, sizeof(int)));
-    w.n = n;
-    w.restart = restart;
     return CHNS_OK;
   }
 
   // sums the k partial rows left in w.part by a reduction kernel and copies
   // them to the host
   int finish_sums(int k, double* out) {
-    hipLaunchKernelGGL(dev::k_finish_sum, dim3(k), dim3(256), 0, s, w.part, w.nb_part, k, w.dots);
+    hipLaunchKernelGGL(dev::k_finish_sum, dim3(k), dim3(256), 0, s, w.part, w.nb_part, k, w.dots,
+                       (const int*)nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(w.hdots, w.dots, sizeof(double) * k, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -406,130 +470,185 @@ struct Solver {
 
   template <class TV>
   int dots(const TV* V, int64_t stride, int k, const TV* x, int64_t N, double* out) {
-    hipLaunchKernelGGL(dev::k_multidot<TV>, dim3(w.nb_part), dim3(256), 0, s, V, stride, k, x, N, w.part);
+    hipLaunchKernelGGL(dev::k_multidot<TV>, dim3(w.nb_part, (k + dev::kDotTile - 1) / dev::kDotTile),
+                       dim3(256), 0, s, V, stride, k, x, N, w.part,
+                       (const int*)nullptr);
     return finish_sums(k, out);
   }
 
   template <class TV>
-  int apply(int block, const TV* x, TV* y, const double* U1, const double* U0) {
+  int apply(int block, const TV* x, TV* y, const double* U1, const double* U0, const int* skip) {
     const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
     if (std::is_same<TV, double>::value)
-      return launch_jvp<double, double, TV>(m, pv, block, U1, U0, x, nf, 0, y, nf, 0, s);
-    return launch_jvp<float, float, TV>(m, pv, block, w.U1f, w.U0f, x, nf, 0, y, nf, 0, s);
+      return launch_jvp<double, double, TV>(m, pv, block, U1, U0, x, nf, 0, y, nf, 0, s, skip);
+    return launch_jvp<float, float, TV>(m, pv, block, w.U1f, w.U0f, x, nf, 0, y, nf, 0, s, skip);
   }
 
   template <class TV>
-  int precondition(int block, const TV* v, TV* z) {
+  void precondition(int block, const TV* v, TV* z, const int* skip) {
+    const dim3 g(grid_stride(n)), b(256);
     if (block == CHNS_BLOCK_CH) {
       if (std::is_same<TV, double>::value)
-        hipLaunchKernelGGL((dev::k_precond<2, TV, double>), dim3(grid_stride(n)), dim3(256), 0, s, w.Di, v, z, n);
+        hipLaunchKernelGGL((dev::k_precond<2, TV, double>), g, b, 0, s, w.Di, v, z, n, skip);
       else
-        hipLaunchKernelGGL((dev::k_precond<2, TV, float>), dim3(grid_stride(n)), dim3(256), 0, s, w.Di32, v, z, n);
+        hipLaunchKernelGGL((dev::k_precond<2, TV, float>), g, b, 0, s, w.Di32, v, z, n, skip);
     } else {
       if (std::is_same<TV, double>::value)
-        hipLaunchKernelGGL((dev::k_precond<4, TV, double>), dim3(grid_stride(n)), dim3(256), 0, s, w.Di, v, z, n);
+        hipLaunchKernelGGL((dev::k_precond<4, TV, double>), g, b, 0, s, w.Di, v, z, n, skip);
       else
-        hipLaunchKernelGGL((dev::k_precond<4, TV, float>), dim3(grid_stride(n)), dim3(256), 0, s, w.Di32, v, z, n);
+        hipLaunchKernelGGL((dev::k_precond<4, TV, float>), g, b, 0, s, w.Di32, v, z, n, skip);
+    }
+  }
+
+  // Right-preconditioned restarted GMRES(mres) with classical Gram-Schmidt
+  // twice, all control on the device (GmresCtl).  A cycle is enqueued in
+  // parts: Arnoldi steps [k0, k1), then the tail (least-squares update
+  // x += Z y, the true residual b - J x and the start of the next cycle).
+  // Steps after the stop test has fired return at once; nothing is read back
+  // here.
+  static constexpr int kSegment = 16;  // Arnoldi steps between host checks
+
+  template <class TV>
+  int enqueue_steps(int block, TV* V, TV* Z, TV* wv, const double* U1, const double* U0, int k0,
+                    int k1) {
+    const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+    const int64_t N = n * nf;
+    dev::GmresCtl* C = w.ctl;
+    const int* idle = &C->idle;
+    const dim3 gs(grid_stride(N)), b(256);
+    int rc;
+    for (int k = k0; k < k1; ++k) {
+      TV* Vk = V + (int64_t)k * N;
+      TV* Zk = Z + (int64_t)k * N;
+      const dim3 gp(w.nb_part, (k + dev::kDotTile) / dev::kDotTile);  // ceil((k + 1) / tile)
+      precondition<TV>(block, Vk, Zk, idle);
+      if ((rc = apply<TV>(block, Zk, wv, U1, U0, idle))) return rc;
+      hipLaunchKernelGGL(dev::k_multidot<TV>, gp, b, 0, s, V, N, k + 1, wv, N, w.part, idle);
+      hipLaunchKernelGGL(dev::k_finish_sum, dim3(k + 1), b, 0, s, w.part, w.nb_part, k + 1, C->h1, idle);
+      hipLaunchKernelGGL(dev::k_multi_axpy<TV>, gs, b, 0, s, wv, V, N, k + 1, C->h1, N, idle);
+      hipLaunchKernelGGL(dev::k_multidot<TV>, gp, b, 0, s, V, N, k + 1, wv, N, w.part, idle);
+      hipLaunchKernelGGL(dev::k_finish_sum, dim3(k + 1), b, 0, s, w.part, w.nb_part, k + 1, C->h2, idle);
+      hipLaunchKernelGGL(dev::k_axpy_norm<TV>, dim3(w.nb_part), b, 0, s, wv, V, N, k + 1, C->h2, N, w.part,
+                         idle);
+      hipLaunchKernelGGL(dev::k_arnoldi_close, dim3(1), b, 0, s, C, k, w.part, w.nb_part);
+      hipLaunchKernelGGL(dev::k_scale_dev<TV>, gs, b, 0, s, V + (int64_t)(k + 1) * N, wv, &C->inv_scale, N,
+                         idle);
     }
     HIPCHK(hipGetLastError());
     return CHNS_OK;
   }
 
-  // Right-preconditioned restarted GMRES(m) for J x = b (b in bvec), x0 = 0;
-  // x returned in w.x (FP64).
+  template <class TV>
+  int enqueue_tail(int block, TV* V, TV* Z, TV* wv, const TV* bvec, const double* U1, const double* U0) {
+    const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+    const int64_t N = n * nf;
+    dev::GmresCtl* C = w.ctl;
+    const int* fin = &C->finished;
+    const dim3 gs(grid_stride(N)), b(256);
+    int rc;
+    hipLaunchKernelGGL(dev::k_gmres_solve, dim3(1), b, 0, s, C);
+    hipLaunchKernelGGL(dev::k_multi_update<TV>, gs, b, 0, s, w.x, Z, N, &C->ncols, C->y, N);
+    hipLaunchKernelGGL((dev::k_convert<double, TV>), gs, b, 0, s, w.x, Z, N, fin);
+    if ((rc = apply<TV>(block, Z, wv, U1, U0, fin))) return rc;
+    hipLaunchKernelGGL(dev::k_rsub<TV>, gs, b, 0, s, wv, bvec, N, fin);
+    hipLaunchKernelGGL(dev::k_multidot<TV>, dim3(w.nb_part), b, 0, s, wv, 0, 1, wv, N, w.part, fin);
+    hipLaunchKernelGGL(dev::k_gmres_restart, dim3(1), b, 0, s, C, w.part, w.nb_part);
+    hipLaunchKernelGGL(dev::k_scale_dev<TV>, gs, b, 0, s, V, wv, &C->inv_scale, N, fin);
+    HIPCHK(hipGetLastError());
+    return CHNS_OK;
+  }
+
+  // Enqueues part `seg` of a cycle (seg < 0: the tail), directly or as a HIP
+  // graph captured on the workspace's own stream the first time this (block,
+  // basis type, restart length, parameters, part) is seen.  Every pointer in
+  // a graph belongs to the mesh or its workspace, so it stays valid until
+  // the workspace is reallocated (which drops the cache).
+  template <class TV>
+  int enqueue_part(int block, TV* V, TV* Z, TV* wv, const TV* bvec, const double* U1,
+                   const double* U0, int mres, int seg) {
+    auto direct = [&]() {
+      if (seg < 0) return enqueue_tail<TV>(block, V, Z, wv, bvec, U1, U0);
+      return enqueue_steps<TV>(block, V, Z, wv, U1, U0, seg * kSegment,
+                               std::min(mres, (seg + 1) * kSegment));
+    };
+    if (!o.graphs) return direct();
+    const int tv = std::is_same<TV, double>::value ? 0 : 1;
+    hipGraphExec_t ex = nullptr;
+    for (auto& g : w.graphs)
+      if (g.block == block && g.tv == tv && g.mres == mres && g.seg == seg &&
+          std::memcmp(&g.pv, &pv, sizeof(pv)) == 0) {
+        ex = g.exec;
+        break;
+      }
+    if (!ex) {
+      if (w.graphs.size() >= 64) drop_graphs(w);
+      hipGraph_t graph = nullptr;
+      hipStream_t caller = s;
+      s = w.cap;
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const int rc = direct();
+      const hipError_t e = hipStreamEndCapture(s, &graph);
+      s = caller;
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(CHNS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      CycleGraph g;
+      g.block = block;
+      g.tv = tv;
+      g.mres = mres;
+      g.seg = seg;
+      g.pv = pv;
+      const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) return fail(CHNS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+      w.graphs.push_back(g);
+      ex = g.exec;
+    }
+    HIPCHK(hipGraphLaunch(ex, s));
+    return CHNS_OK;
+  }
+
+  int read_ctl() {
+    HIPCHK(hipMemcpyAsync(w.hctl, w.ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (w.hctl[3]) return fail(CHNS_ENONFINITE, "non-finite value in GMRES");
+    return CHNS_OK;
+  }
+
+  // Solves J x = b (b in bvec) from x0 = 0; x returned in w.x (FP64).  The
+  // host checks the device's stop flags after every kSegment Arnoldi steps
+  // and after each cycle's tail.
   template <class TV>
   int gmres(int block, TV* V, TV* Z, TV* wv, TV* bvec, const double* U1, const double* U0,
             int* its) {
     const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
     const int64_t N = n * nf;
-    const int mres = std::min(o.gmres_restart, dev::kMaxBasis - 1);
-    hipLaunchKernelGGL(dev::k_fill<double>, dim3(grid_stride(N)), dim3(256), 0, s, w.x, N, 0.0);
-    double bn;
+    const int mres = std::max(1, std::min(o.gmres_restart, dev::kMaxBasis - 1));
+    const int nseg = (mres + kSegment - 1) / kSegment;
+    const dim3 gs(grid_stride(N)), b(256);
+    dev::GmresCtl* C = w.ctl;
+    hipLaunchKernelGGL(dev::k_fill<double>, gs, b, 0, s, w.x, N, 0.0);
+    hipLaunchKernelGGL(dev::k_multidot<TV>, dim3(w.nb_part), b, 0, s, bvec, 0, 1, bvec, N, w.part,
+                       (const int*)nullptr);
+    hipLaunchKernelGGL(dev::k_gmres_begin, dim3(1), b, 0, s, C, w.part, w.nb_part, o.gmres_max_it, mres,
+                       o.gmres_rtol);
+    hipLaunchKernelGGL(dev::k_scale_dev<TV>, gs, b, 0, s, V, bvec, &C->inv_scale, N, &C->finished);
     int rc;
-    if ((rc = dots<TV>(bvec, 0, 1, bvec, N, &bn))) return rc;
-    bn = std::sqrt(bn);
-    *its = 0;
-    if (bn == 0.0) return CHNS_OK;
-    if (!std::isfinite(bn)) return fail(CHNS_ENONFINITE, "non-finite GMRES right-hand side");
-    double beta = bn;
-    hipLaunchKernelGGL((dev::k_scale<TV, TV>), dim3(grid_stride(N)), dim3(256), 0, s, V, bvec, 1.0 / beta, N);
-    std::vector<double> H((mres + 1) * mres), cs(mres), sn(mres), g(mres + 1), h(mres + 1), h2(mres + 1);
-    auto Hat = [&](int i, int j) -> double& { return H[i * mres + j]; };
-    bool done = false;
-    while (!done && *its < o.gmres_max_it) {
-      std::fill(H.begin(), H.end(), 0.0);
-      std::fill(g.begin(), g.end(), 0.0);
-      g[0] = beta;
-      int k = 0;
-      for (; k < mres && *its < o.gmres_max_it; ++k) {
-        TV* Vk = V + (int64_t)k * N;
-        TV* Zk = Z + (int64_t)k * N;
-        if ((rc = precondition<TV>(block, Vk, Zk))) return rc;
-        if ((rc = apply<TV>(block, Zk, wv, U1, U0))) return rc;
-        ++*its;
-        // classical Gram-Schmidt twice (h = V^T w; w -= V h), the second update
-        // fused with ||w||^2
-        dev::Coef c;
-        if ((rc = dots<TV>(V, N, k + 1, wv, N, h.data()))) return rc;
-        for (int j = 0; j <= k; ++j) {
-          c.c[j] = h[j];
-          Hat(j, k) += h[j];
-        }
-        hipLaunchKernelGGL(dev::k_multi_axpy<TV>, dim3(grid_stride(N)), dim3(256), 0, s, wv, V, N, k + 1, c, N);
-        if ((rc = dots<TV>(V, N, k + 1, wv, N, h2.data()))) return rc;
-        for (int j = 0; j <= k; ++j) {
-          c.c[j] = h2[j];
-          Hat(j, k) += h2[j];
-        }
-        hipLaunchKernelGGL(dev::k_axpy_norm<TV>, dim3(w.nb_part), dim3(256), 0, s, wv, V, N, k + 1, c, N,
-                           w.part);
-        double hn;
-        if ((rc = finish_sums(1, &hn))) return rc;
-        hn = std::sqrt(hn);
-        if (!std::isfinite(hn)) return fail(CHNS_ENONFINITE, "non-finite value in GMRES");
-        Hat(k + 1, k) = hn;
-        if (hn > 0)
-          hipLaunchKernelGGL((dev::k_scale<TV, TV>), dim3(grid_stride(N)), dim3(256), 0, s,
-                             V + (int64_t)(k + 1) * N, wv, 1.0 / hn, N);
-        for (int j = 0; j < k; ++j) {
-          const double t = cs[j] * Hat(j, k) + sn[j] * Hat(j + 1, k);
-          Hat(j + 1, k) = -sn[j] * Hat(j, k) + cs[j] * Hat(j + 1, k);
-          Hat(j, k) = t;
-        }
-        const double den = std::hypot(Hat(k, k), Hat(k + 1, k));
-        cs[k] = den > 0 ? Hat(k, k) / den : 1.0;
-        sn[k] = den > 0 ? Hat(k + 1, k) / den : 0.0;
-        Hat(k, k) = den;
-        Hat(k + 1, k) = 0.0;
-        g[k + 1] = -sn[k] * g[k];
-        g[k] = cs[k] * g[k];
-        if (std::fabs(g[k + 1]) <= o.gmres_rtol * bn || den == 0.0 || hn == 0.0) {
-          ++k;
-          done = true;
-          break;
+    for (;;) {
+      for (int seg = 0; seg < nseg; ++seg) {
+        if ((rc = enqueue_part<TV>(block, V, Z, wv, bvec, U1, U0, mres, seg))) return rc;
+        if (seg + 1 < nseg) {
+          if ((rc = read_ctl())) return rc;
+          if (w.hctl[0]) break;  // idle: the cycle ended early
         }
       }
-      std::vector<double> y(k, 0.0);
-      for (int i = k - 1; i >= 0; --i) {
-        double t = g[i];
-        for (int j = i + 1; j < k; ++j) t -= Hat(i, j) * y[j];
-        y[i] = Hat(i, i) != 0 ? t / Hat(i, i) : 0.0;
-      }
-      dev::Coef c;
-      for (int j = 0; j < k; ++j) c.c[j] = y[j];
-      hipLaunchKernelGGL(dev::k_multi_update<TV>, dim3(grid_stride(N)), dim3(256), 0, s, w.x, Z, N, k, c, N);
-      if (done || *its >= o.gmres_max_it) break;
-      // restart from the true residual b - J x
-      hipLaunchKernelGGL((dev::k_convert<double, TV>), dim3(grid_stride(N)), dim3(256), 0, s, w.x, Z, N);
-      if ((rc = apply<TV>(block, Z, wv, U1, U0))) return rc;
-      hipLaunchKernelGGL(dev::k_rsub<TV>, dim3(grid_stride(N)), dim3(256), 0, s, wv, bvec, N);
-      if ((rc = dots<TV>(wv, 0, 1, wv, N, &beta))) return rc;
-      beta = std::sqrt(beta);
-      if (!std::isfinite(beta)) return fail(CHNS_ENONFINITE, "non-finite GMRES residual");
-      if (beta <= o.gmres_rtol * bn) break;
-      hipLaunchKernelGGL((dev::k_scale<TV, TV>), dim3(grid_stride(N)), dim3(256), 0, s, V, wv, 1.0 / beta, N);
+      if ((rc = enqueue_part<TV>(block, V, Z, wv, bvec, U1, U0, mres, -1))) return rc;
+      if ((rc = read_ctl())) return rc;
+      if (w.hctl[1]) break;
     }
-    HIPCHK(hipGetLastError());
+    *its = w.hctl[2];
     return CHNS_OK;
   }
 
@@ -575,9 +694,9 @@ struct Solver {
         rc = gmres<double>(block, w.V64, w.Z64, w.w64, w.b64, U, w.Uk, &its);
       } else {
         hipLaunchKernelGGL((dev::k_convert<double, float>), dim3(grid_stride(n * 6)), dim3(256), 0, s, U,
-                           w.U1f, n * 6);
+                           w.U1f, n * 6, (const int*)nullptr);
         hipLaunchKernelGGL((dev::k_convert<double, float>), dim3(grid_stride(n * 6)), dim3(256), 0, s,
-                           w.Uk, w.U0f, n * 6);
+                           w.Uk, w.U0f, n * 6, (const int*)nullptr);
         hipLaunchKernelGGL((dev::k_scale<double, float>), dim3(grid_stride(N)), dim3(256), 0, s, w.b32,
                            w.r, -1.0, N);
         rc = gmres<float>(block, w.V32, w.Z32, w.w32, w.b32, U, w.Uk, &its);
@@ -603,10 +722,14 @@ struct Solver {
     return CHNS_OK;
   }
 
-  int step(double* U, chns_step_stats* st) {
+  // The step works on the workspace copy w.U1 of the caller's U, so that the
+  // captured GMRES cycles only ever see workspace pointers.
+  int step(double* Uout, chns_step_stats* st) {
     int rc = ensure_workspace();
     if (rc) return rc;
-    HIPCHK(hipMemcpyAsync(w.Uk, U, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
+    double* U = w.U1;
+    HIPCHK(hipMemcpyAsync(U, Uout, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(w.Uk, Uout, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
     double r_init[2];
     for (int b : {CHNS_BLOCK_CH, CHNS_BLOCK_NS})
       if ((rc = residual_norm(b, U, &r_init[b]))) return rc;
@@ -638,6 +761,7 @@ struct Solver {
       if ((rc = residual_norm(b, U, &rf))) return rc;
       st->rel_res[b] = r_init[b] > 0 ? rf / r_init[b] : 0.0;
     }
+    HIPCHK(hipMemcpyAsync(Uout, U, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
     if ((rc = launch_diagnostics(m, pv, U, &st->mass, &st->energy, s))) return rc;
     st->converged = (all_conv && block_conv) ? 1 : 0;
     return st->converged ? CHNS_OK : CHNS_NOT_CONVERGED;
@@ -748,20 +872,16 @@ int chns_mesh_upload(chns_mesh* m, void* stream) {
 
 int chns_mesh_free(chns_mesh* m) {
   if (!m) return CHNS_OK;
+  free_workspace(m->ws);
   void* ptrs[] = {m->d_elem, m->d_hoff, m->d_hids, m->d_anchor, m->d_level,
                   m->d_hw, m->d_hw32, m->d_flag, m->d_part, m->d_sum,
                   m->d_tgt_off, m->d_tgt, m->d_inc_off, m->d_node_off, m->d_node_slot, m->d_inc_corner,
                   m->d_bflags, m->d_inc_w, m->d_touch_off, m->d_ntouch_off, m->d_ntouch_slot,
-                  m->d_partial, m->d_tbuf,
-                  m->ws.Uk, m->ws.Uprev, m->ws.r, m->ws.x, m->ws.D, m->ws.Di, m->ws.Di32,
-                  m->ws.U1f, m->ws.U0f, m->ws.V64, m->ws.Z64, m->ws.w64, m->ws.b64, m->ws.V32,
-                  m->ws.Z32, m->ws.w32, m->ws.b32, m->ws.part, m->ws.dots, m->ws.flag};
+                  m->d_partial, m->d_tbuf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (m->h_flag) (void)hipHostFree(m->h_flag);
   if (m->h_sum) (void)hipHostFree(m->h_sum);
-  if (m->ws.hdots) (void)hipHostFree(m->ws.hdots);
-  if (m->ws.hflag) (void)hipHostFree(m->ws.hflag);
   delete m;
   return CHNS_OK;
 }
@@ -829,7 +949,7 @@ int chns_step(chns_mesh* m, const chns_params* params, const chns_solver_opts* o
   if ((rc = phys_view(params, pv))) return rc;
   if (!opts || !U || !out) return fail(CHNS_EINVAL, "opts, U and out must not be NULL");
   if (opts->gmres_restart < 1 || opts->gmres_restart > dev::kMaxBasis - 1)
-    return fail(CHNS_EINVAL, "gmres_restart must be in [1, 31]");
+    return fail(CHNS_EINVAL, "gmres_restart must be in [1, " + std::to_string(dev::kMaxBasis - 1) + "]");
   if (opts->precision != 0 && opts->precision != 1) return fail(CHNS_EINVAL, "precision must be 0 or 1");
   if (opts->precond != 0 && opts->precond != 1) return fail(CHNS_EINVAL, "precond must be 0 or 1");
   if (opts->block_max_it < 1 || opts->gmres_max_it < 1) return fail(CHNS_EINVAL, "iteration limits must be positive");
@@ -873,20 +993,20 @@ int chns_launch_element_loop(chns_mesh* m, const chns_params* params, int block,
       if (block == CHNS_BLOCK_CH)
         hipLaunchKernelGGL((dev::k_ch_jvp<double, double, double>), g, b,
                            (dev::ChunkLDS<double, 5, 2, 2>::bytes(cc)), s, mv, pl, pv, cc, U_new, U_old,
-                           (const double*)dU, 6, off, p64);
+                           (const double*)dU, 6, off, p64, (const int*)nullptr);
       else
         hipLaunchKernelGGL((dev::k_ns_jvp<double, double, double>), g, b,
                            (dev::ChunkLDS<double, 6, 4, 4>::bytes(cc)), s, mv, pl, pv, cc, U_new, U_old,
-                           (const double*)dU, 6, off, p64);
+                           (const double*)dU, 6, off, p64, (const int*)nullptr);
     } else if (op == 2) {
       if (block == CHNS_BLOCK_CH)
         hipLaunchKernelGGL((dev::k_ch_jvp<float, double, float>), g, b,
                            (dev::ChunkLDS<float, 5, 2, 2>::bytes(cc)), s, mv, pl, pv, cc, U_new, U_old,
-                           (const float*)dU, 6, off, p32);
+                           (const float*)dU, 6, off, p32, (const int*)nullptr);
       else
         hipLaunchKernelGGL((dev::k_ns_jvp<float, double, float>), g, b,
                            (dev::ChunkLDS<float, 6, 4, 4>::bytes(cc)), s, mv, pl, pv, cc, U_new, U_old,
-                           (const float*)dU, 6, off, p32);
+                           (const float*)dU, 6, off, p32, (const int*)nullptr);
     } else if (op == 3) {
       if (block == CHNS_BLOCK_CH)
         hipLaunchKernelGGL((dev::k_diag<double, 0>), g, b, 0, s, mv, pl, pv, U_new, U_old, m->d_tbuf);

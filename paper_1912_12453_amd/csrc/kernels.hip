@@ -199,7 +199,8 @@ template <class T, class TS, class TD>
 __global__ __launch_bounds__(256) void k_ch_jvp(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
                                                 const TS* __restrict__ U1, const TS* __restrict__ U0,
                                                 const TD* __restrict__ dU, int ldD, int offD,
-                                                T* __restrict__ partial) {
+                                                T* __restrict__ partial, const int* skip) {
+  if (skip && *skip) return;  // GMRES control: this step is not needed
   extern __shared__ double smem_d[];
   using CL = ChunkLDS<T, 5, 2, 2>;
   CL S;
@@ -436,7 +437,8 @@ template <class T, class TS, class TD>
 __global__ __launch_bounds__(256) void k_ns_jvp(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
                                                 const TS* __restrict__ U1, const TS* __restrict__ U0,
                                                 const TD* __restrict__ dU, int ldD, int offD,
-                                                T* __restrict__ partial) {
+                                                T* __restrict__ partial, const int* skip) {
+  if (skip && *skip) return;  // GMRES control: this step is not needed
   extern __shared__ double smem_d[];
   using CL = ChunkLDS<T, 6, 4, 4>;
   CL S;
@@ -482,7 +484,8 @@ template <int NF, class TP, class TO, int MODE>
 __global__ void k_gather(PlanView pl, int64_t n, const TP* __restrict__ partial,
                          TO* __restrict__ out, int ld, int off, const double* __restrict__ U1,
                          const double* __restrict__ U0, const TO* __restrict__ dU, int ldD,
-                         int offD) {
+                         int offD, const int* skip) {
+  if (skip && *skip) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     TP acc[NF];

@@ -11,10 +11,14 @@
 namespace chns {
 namespace dev {
 
-constexpr int kMaxBasis = 32;  // restart length + 1 fits the by-value coefficient block
-struct Coef {
-  double c[kMaxBasis];
-};
+constexpr int kMaxBasis = 128;  // restart length + 1
+constexpr int kDotTile = 32;    // basis vectors per multi-dot workgroup
+
+// Kernels that run inside a GMRES cycle take a skip flag (device int): when
+// it is set the whole grid returns at once.  The host can then enqueue a full
+// restart cycle without reading anything back; the cycle's control kernels
+// raise the flag once the iteration has stopped.
+__device__ __forceinline__ bool skipped(const int* skip) { return skip && *skip; }
 
 template <class T>
 __global__ void k_fill(T* __restrict__ x, int64_t n, T v) {
@@ -24,7 +28,8 @@ __global__ void k_fill(T* __restrict__ x, int64_t n, T v) {
 }
 
 template <class TA, class TB>
-__global__ void k_convert(const TA* __restrict__ a, TB* __restrict__ b, int64_t n) {
+__global__ void k_convert(const TA* __restrict__ a, TB* __restrict__ b, int64_t n, const int* skip) {
+  if (skipped(skip)) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     b[i] = (TB)a[i];
@@ -69,30 +74,40 @@ __device__ __forceinline__ double block_reduce_max(double v, double* sh) {
   return r;
 }
 
-// part[j * gridDim.x + b] = partial sum over block b of V_j . w, j < k
+// part[j * gridDim.x + b] = partial sum over block b of V_j . w, j < k.
+// blockIdx.y picks a tile of kDotTile basis vectors (grid.y = ceil(k / kDotTile)).
 template <class TV>
 __global__ __launch_bounds__(256) void k_multidot(const TV* __restrict__ V, int64_t stride, int k,
                                                   const TV* __restrict__ w, int64_t n,
-                                                  double* __restrict__ part) {
+                                                  double* __restrict__ part, const int* skip) {
+  if (skipped(skip)) return;
   __shared__ double sh[4];
-  double acc[kMaxBasis];
+  const int j0 = blockIdx.y * kDotTile;
+  const int kk = min(kDotTile, k - j0);
+  const TV* __restrict__ Vt = V + (int64_t)j0 * stride;
+  double acc[kDotTile];
 #pragma unroll
-  for (int j = 0; j < kMaxBasis; ++j) acc[j] = 0;
+  for (int j = 0; j < kDotTile; ++j) acc[j] = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const double wi = (double)w[i];
 #pragma unroll
-    for (int j = 0; j < kMaxBasis; ++j)
-      if (j < k) acc[j] += (double)V[j * stride + i] * wi;
+    for (int j = 0; j < kDotTile; ++j)
+      if (j < kk) acc[j] += (double)Vt[j * stride + i] * wi;
   }
-  for (int j = 0; j < k; ++j) {
-    const double s = block_reduce_sum(acc[j], sh);
-    if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = s;
+#pragma unroll
+  for (int j = 0; j < kDotTile; ++j) {  // unrolled: acc stays in registers
+    if (j < kk) {
+      const double s = block_reduce_sum(acc[j], sh);
+      if (threadIdx.x == 0) part[(int64_t)(j0 + j) * gridDim.x + blockIdx.x] = s;
+    }
   }
 }
 
 // out[j] = sum_b part[j * nb + b] in block order
-__global__ void k_finish_sum(const double* __restrict__ part, int nb, int k, double* __restrict__ out) {
+__global__ void k_finish_sum(const double* __restrict__ part, int nb, int k, double* __restrict__ out,
+                             const int* skip) {
+  if (skipped(skip)) return;
   __shared__ double sh[4];
   for (int j = blockIdx.x; j < k; j += gridDim.x) {
     double s = 0;
@@ -110,16 +125,20 @@ __global__ void k_finish_max(const double* __restrict__ part, int nb, double* __
   if (threadIdx.x == 0) out[0] = s;
 }
 
-// w -= sum_{j<k} c_j V_j
+// w -= sum_{j<k} c_j V_j  (c in device memory, staged in LDS)
 template <class TV>
-__global__ void k_multi_axpy(TV* __restrict__ w, const TV* __restrict__ V, int64_t stride, int k,
-                             Coef c, int64_t n) {
+__global__ __launch_bounds__(256) void k_multi_axpy(TV* __restrict__ w, const TV* __restrict__ V,
+                                                    int64_t stride, int k, const double* __restrict__ c,
+                                                    int64_t n, const int* skip) {
+  if (skipped(skip)) return;
+  __shared__ double cc[kMaxBasis];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) cc[j] = c[j];
+  __syncthreads();
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     double s = (double)w[i];
-#pragma unroll
-    for (int j = 0; j < kMaxBasis; ++j)
-      if (j < k) s -= c.c[j] * (double)V[j * stride + i];
+#pragma unroll 8
+    for (int j = 0; j < k; ++j) s -= cc[j] * (double)V[j * stride + i];
     w[i] = (TV)s;
   }
 }
@@ -127,16 +146,20 @@ __global__ void k_multi_axpy(TV* __restrict__ w, const TV* __restrict__ V, int64
 // w -= sum_{j<k} c_j V_j and the partial sums of w . w (slot 0)
 template <class TV>
 __global__ __launch_bounds__(256) void k_axpy_norm(TV* __restrict__ w, const TV* __restrict__ V,
-                                                   int64_t stride, int k, Coef c, int64_t n,
-                                                   double* __restrict__ part) {
+                                                   int64_t stride, int k, const double* __restrict__ c,
+                                                   int64_t n, double* __restrict__ part,
+                                                   const int* skip) {
+  if (skipped(skip)) return;
   __shared__ double sh[4];
+  __shared__ double cc[kMaxBasis];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) cc[j] = c[j];
+  __syncthreads();
   double acc = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     double s = (double)w[i];
-#pragma unroll
-    for (int j = 0; j < kMaxBasis; ++j)
-      if (j < k) s -= c.c[j] * (double)V[j * stride + i];
+#pragma unroll 8
+    for (int j = 0; j < k; ++j) s -= cc[j] * (double)V[j * stride + i];
     const TV st = (TV)s;
     w[i] = st;
     acc += (double)st * (double)st;
@@ -145,18 +168,176 @@ __global__ __launch_bounds__(256) void k_axpy_norm(TV* __restrict__ w, const TV*
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// x += sum_{j<k} c_j Z_j  (x in FP64)
+// x += sum_{j<*kp} c_j Z_j  (x in FP64; count and coefficients in device memory)
 template <class TV>
-__global__ void k_multi_update(double* __restrict__ x, const TV* __restrict__ Z, int64_t stride,
-                               int k, Coef c, int64_t n) {
+__global__ __launch_bounds__(256) void k_multi_update(double* __restrict__ x, const TV* __restrict__ Z,
+                                                      int64_t stride, const int* __restrict__ kp,
+                                                      const double* __restrict__ c, int64_t n) {
+  const int k = *kp;
+  if (k == 0) return;
+  __shared__ double cc[kMaxBasis];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) cc[j] = c[j];
+  __syncthreads();
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     double s = x[i];
-#pragma unroll
-    for (int j = 0; j < kMaxBasis; ++j)
-      if (j < k) s += c.c[j] * (double)Z[j * stride + i];
+#pragma unroll 8
+    for (int j = 0; j < k; ++j) s += cc[j] * (double)Z[j * stride + i];
     x[i] = s;
   }
+}
+
+// y = (*a) * x
+template <class TV>
+__global__ void k_scale_dev(TV* __restrict__ y, const TV* __restrict__ x, const double* __restrict__ a,
+                            int64_t n, const int* skip) {
+  if (skipped(skip)) return;
+  const double s = *a;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (TV)(s * (double)x[i]);
+}
+
+// ------------------------------------------------------ GMRES control ----
+// State of one right-preconditioned restarted GMRES run, kept in device
+// memory and advanced by single-workgroup kernels.  The host reads the first
+// five ints after each cycle.
+struct GmresCtl {
+  int idle;      // 1: the Arnoldi steps still queued in this cycle do nothing
+  int finished;  // 1: stopped (converged, breakdown, iteration cap or error)
+  int its;       // Arnoldi steps taken
+  int err;       // 1: a norm was not finite
+  int kcols;     // Arnoldi columns of the current cycle
+  int ncols;     // columns used by the last solution update
+  int max_it, mres;
+  double rtol, bn, beta;
+  double inv_scale;  // 1/beta for V_0, then 1/h_{k+1,k} for V_{k+1}
+  double h1[kMaxBasis], h2[kMaxBasis];
+  double H[kMaxBasis * kMaxBasis];  // column k: H[i * kMaxBasis + k]
+  double cs[kMaxBasis], sn[kMaxBasis], g[kMaxBasis + 1], y[kMaxBasis];
+};
+
+// fixed-order sum of nb partials, valid on thread 0
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nb) {
+  __shared__ double sh[4];
+  double s = 0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+  return block_reduce_sum(s, sh);
+}
+
+// Starts a run from the partial sums of b . b (x_0 = 0, so r_0 = b).
+__global__ void k_gmres_begin(GmresCtl* __restrict__ C, const double* __restrict__ part, int nb,
+                              int max_it, int mres, double rtol) {
+  const double bb = sum_partials(part, nb);
+  if (threadIdx.x != 0) return;
+  const double bn = sqrt(bb);
+  C->its = 0;
+  C->err = 0;
+  C->kcols = 0;
+  C->ncols = 0;
+  C->max_it = max_it;
+  C->mres = mres;
+  C->rtol = rtol;
+  C->bn = bn;
+  C->beta = bn;
+  C->inv_scale = 0.0;
+  C->g[0] = bn;
+  if (!isfinite(bn)) C->err = 1;
+  const bool stop = C->err || bn == 0.0 || max_it <= 0;
+  C->finished = stop ? 1 : 0;
+  C->idle = stop ? 1 : 0;
+  if (!stop) C->inv_scale = 1.0 / bn;
+}
+
+// Closes Arnoldi step k: column k of H from the two Gram-Schmidt passes, the
+// new norm h_{k+1,k} from the partial sums of w . w, the Givens rotations and
+// the stopping test.  One workgroup; the rotation chain runs on thread 0 over
+// the column staged in LDS.
+__global__ __launch_bounds__(256) void k_arnoldi_close(GmresCtl* __restrict__ C, int k,
+                                                       const double* __restrict__ part, int nb) {
+  if (C->idle) return;
+  __shared__ double col[kMaxBasis + 1];
+  for (int j = threadIdx.x; j <= k; j += blockDim.x) col[j] = C->h1[j] + C->h2[j];
+  const double hh = sum_partials(part, nb);  // synchronises the workgroup
+  if (threadIdx.x != 0) return;
+  const int ld = kMaxBasis;
+  double* H = C->H;
+  const double hn = sqrt(hh);
+  C->its += 1;
+  C->kcols = k + 1;
+  if (!isfinite(hn)) {
+    C->err = 1;
+    C->finished = 1;
+    C->idle = 1;
+    return;
+  }
+  C->inv_scale = hn > 0 ? 1.0 / hn : 0.0;
+  col[k + 1] = hn;
+  for (int j = 0; j < k; ++j) {
+    const double a = col[j], b = col[j + 1];
+    col[j] = C->cs[j] * a + C->sn[j] * b;
+    col[j + 1] = -C->sn[j] * a + C->cs[j] * b;
+  }
+  const double a = col[k], b = col[k + 1];
+  const double den = hypot(a, b);
+  C->cs[k] = den > 0 ? a / den : 1.0;
+  C->sn[k] = den > 0 ? b / den : 0.0;
+  col[k] = den;
+  for (int j = 0; j <= k; ++j) H[j * ld + k] = col[j];
+  H[(k + 1) * ld + k] = 0.0;
+  C->g[k + 1] = -C->sn[k] * C->g[k];
+  C->g[k] = C->cs[k] * C->g[k];
+  if (fabs(C->g[k + 1]) <= C->rtol * C->bn || den == 0.0 || hn == 0.0 || C->its >= C->max_it) {
+    C->finished = 1;
+    C->idle = 1;
+  } else if (k + 1 >= C->mres) {
+    C->idle = 1;
+  }
+}
+
+// Back substitution H y = g over the cycle's columns, column by column (one
+// workgroup: y_i on thread 0, then every thread updates the rows above).
+__global__ __launch_bounds__(256) void k_gmres_solve(GmresCtl* __restrict__ C) {
+  __shared__ double gg[kMaxBasis + 1];
+  __shared__ double yi;
+  const int k = C->kcols, ld = kMaxBasis;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) gg[i] = C->g[i];
+  __syncthreads();
+  for (int i = k - 1; i >= 0; --i) {
+    if (threadIdx.x == 0) {
+      const double d = C->H[i * ld + i];
+      yi = d != 0 ? gg[i] / d : 0.0;
+      C->y[i] = yi;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < i; j += blockDim.x) gg[j] -= C->H[j * ld + i] * yi;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    C->ncols = k;
+    C->kcols = 0;
+  }
+}
+
+// New cycle from the partial sums of r . r, r = b - J x.
+__global__ void k_gmres_restart(GmresCtl* __restrict__ C, const double* __restrict__ part, int nb) {
+  if (C->finished) return;
+  const double rr = sum_partials(part, nb);
+  if (threadIdx.x != 0) return;
+  const double beta = sqrt(rr);
+  C->beta = beta;
+  if (!isfinite(beta)) {
+    C->err = 1;
+    C->finished = 1;
+    return;
+  }
+  if (beta <= C->rtol * C->bn) {
+    C->finished = 1;
+    return;
+  }
+  C->g[0] = beta;
+  C->inv_scale = 1.0 / beta;
+  C->idle = 0;
 }
 
 // y = a * x
@@ -169,7 +350,8 @@ __global__ void k_scale(TB* __restrict__ y, const TA* __restrict__ x, double a, 
 
 // r = b - r  (r holds J x on entry)
 template <class TV>
-__global__ void k_rsub(TV* __restrict__ r, const TV* __restrict__ b, int64_t n) {
+__global__ void k_rsub(TV* __restrict__ r, const TV* __restrict__ b, int64_t n, const int* skip) {
+  if (skipped(skip)) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     r[i] = b[i] - r[i];
@@ -245,7 +427,8 @@ __global__ void k_invert_blocks(const double* __restrict__ D, double* __restrict
 // z = Dinv v, node by node
 template <int NF, class TV, class TM>
 __global__ void k_precond(const TM* __restrict__ Di, const TV* __restrict__ v, TV* __restrict__ z,
-                          int64_t nn) {
+                          int64_t nn, const int* skip) {
+  if (skipped(skip)) return;
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn;
        n += (int64_t)gridDim.x * blockDim.x) {
     TM x[NF];

@@ -115,3 +115,36 @@ def test_nonfinite_state_is_reported(torch, chns, orc):
     with pytest.raises(chns.ChnsError) as ei:
         pm.step(chns.make_params(w.physics), chns.make_opts(), d)
     assert ei.value.code in (chns.CHNS_ENONFINITE, chns.CHNS_ETAU)
+
+
+def test_graph_cycles_match_launches(torch, chns, orc):
+    """GMRES restart cycles replayed as HIP graphs give bit-identical steps to
+    the same kernels launched one by one, over several steps, both precisions
+    on one mesh (the graph cache is reused), with eager library work between
+    the replays."""
+    w, pm, om, U = drop(chns, orc, 4)
+    p = chns.make_params(w.physics)
+    res = {}
+    for graphs in (0, 1):
+        for precision in (0, 1, 0):
+            print(f"case graphs={graphs} precision={precision}", flush=True)
+            d = torch.tensor(U, device="cuda:0")
+            opts = chns.make_opts(precision=precision, gmres_restart=40,
+                                  gmres_rtol=1e-7 if precision == 0 else 1e-5)
+            traj = []
+            for _ in range(3):
+                rc, st = pm.step(p, opts, d)
+                assert rc == chns.CHNS_OK, st.as_dict()
+                R = pm.residual(p, chns.CHNS_BLOCK_CH, d, d)  # eager work between replays
+                torch.cuda.synchronize()
+                traj.append((d.cpu().numpy().copy(), tuple(st.gmres_its), R.cpu().numpy()))
+            key = (graphs, precision)
+            if key in res:  # the same run again on the warm cache
+                for a, b in zip(res[key], traj):
+                    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+            res[key] = traj
+    for precision in (0, 1):
+        for a, b in zip(res[(0, precision)], res[(1, precision)]):
+            assert a[1] == b[1]
+            assert np.array_equal(a[0], b[0])
+            assert np.array_equal(a[2], b[2])
