@@ -18,8 +18,13 @@ The roofline object describes the NS JVP element kernel, timed live with HIP
 events on the stream it is launched on.  The CPU baseline is the FP64 oracle
 (test infrastructure) computing the same 6-DoF JVP on the same mesh and state.
 
+The cn_steps object times full Crank-Nicolson steps (block iteration,
+Newton to 1e-8, GMRES(120) with node-block Jacobi) on the 16^3 drop, FP64
+and mixed precision.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
                        [--workload bubble_l9|bubble_l8|drop16|rt_l10] [--no-cpu-baseline]
+                       [--cn-steps K] [--no-steps]
 """
 import argparse
 import json
@@ -48,6 +53,52 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cn_steps(chns, W, torch, dev, nsteps):
+    """Consecutive Crank-Nicolson steps of the 16^3 drop (4913 nodes) to the
+    1e-8 relative Newton residual, FP64 and mixed precision from the same
+    U^0: steps/s, p50/p99 step latency, solver counts, energy trace."""
+    import numpy as np
+    w = W.drop16()
+    mesh = chns.Mesh.from_spec(w.mesh)
+    mesh.upload()
+    xyz, bf = mesh.nodes()
+    U0 = W.initial_state(xyz, W.sphere_phi((0.5, 0.5, 0.5), 0.25, w.physics.Cn), bf,
+                         phi_noise=1e-3, seed=0)
+    p = chns.make_params(w.physics)
+    out = {"workload": "drop16", "nodes": mesh.n_nodes, "newton_rtol": 1e-8, "steps": nsteps}
+    for prec, name, grtol in ((0, "fp64", 1e-7), (1, "mixed", 1e-5)):
+        opts = chns.make_opts(precision=prec, gmres_rtol=grtol, gmres_restart=120)
+        U = torch.tensor(U0, device=dev)
+        rc, st = mesh.step(p, opts, U)  # warm-up: workspace and graph capture
+        U.copy_(torch.tensor(U0, device=dev))
+        mass0, e0 = mesh.diagnostics(p, U)
+        torch.cuda.synchronize()
+        lat, energy, conv, gits, rel = [], [e0], True, [0, 0], 0.0
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            ts = time.perf_counter()
+            rc, st = mesh.step(p, opts, U)
+            lat.append((time.perf_counter() - ts) * 1e3)
+            if rc not in (chns.CHNS_OK, chns.CHNS_NOT_CONVERGED):
+                raise RuntimeError(f"step failed with {rc}")
+            conv = conv and rc == chns.CHNS_OK
+            energy.append(st.energy)
+            gits = [gits[0] + st.gmres_its[0], gits[1] + st.gmres_its[1]]
+            rel = max(rel, st.rel_res[0])
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[name] = {"steps_per_s": round(nsteps / t, 3),
+                     "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                     "all_converged": bool(conv), "max_rel_res_ch": rel,
+                     "gmres_its_per_step": [g / nsteps for g in gits],
+                     "energy_non_increasing": bool(all(b <= a for a, b in zip(energy, energy[1:]))),
+                     "mass_drift": st.mass - mass0}
+        log(f"[bench] cn steps {name}: {out[name]}")
+    out["mixed_speedup"] = round(out["mixed"]["steps_per_s"] / out["fp64"]["steps_per_s"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +109,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=2)
+    ap.add_argument("--cn-steps", type=int, default=10)
+    ap.add_argument("--no-steps", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
@@ -175,6 +228,9 @@ def main():
             "flops_per_launch": flops_per_launch, "algorithmic_bytes_per_launch": bytes_per_launch,
             "algorithmic_GBps": round(ach_gbs, 1), "hbm_frac": round(ach_gbs / PEAK_HBM_GBS, 4)}
 
+    # ---- full Crank-Nicolson steps at the 1e-8 Newton tolerance, FP64 vs mixed
+    steps = None if args.no_steps else cn_steps(chns, W, torch, dev, args.cn_steps)
+
     # ---- CPU baseline: the oracle's 6-DoF JVP on the same mesh and state
     cpu = None
     if not args.no_cpu_baseline:
@@ -206,6 +262,7 @@ def main():
                    "p99_ms": round(float(np.percentile(lat, 99)), 3)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cn_steps": steps,
         "kernels": {k: round(v, 4) for k, v in kern.items()},
     }
     print(json.dumps(res), flush=True)

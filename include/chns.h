@@ -219,6 +219,76 @@ int chns_launch_element_loop(chns_mesh* mesh, const chns_params* params, int blo
                              const double* U_new, const double* U_old, const void* dU, void* out,
                              int reps, void* stream, int64_t* grid);
 
+/* ------------------------------------------------------------ serving ----
+ * A request loop for many independent droplet / bubble problems of different
+ * octree sizes.  Each request is (mesh spec, parameters, number of Crank-
+ * Nicolson steps); its initial state is phi = phi0 at the nodes, mu = phi^3 -
+ * phi, v = 0, p = 0.  A builder thread inside the server makes the host mesh,
+ * the scatter plan and U^0 of queued requests while the GPU works.  Each
+ * round (chns_server_run_round) first admits built requests in arrival order
+ * while their exact device footprint (mesh arrays + solver workspace for the
+ * server's options) fits in the HBM budget, then advances every resident
+ * request by one step: each on its own stream and host thread, so their
+ * element loops and Krylov kernels overlap on the device, with GMRES cycles
+ * replayed as HIP graphs.  A request that has taken its last step leaves:
+ * its final state is copied to host memory the server owns and its device
+ * memory is freed before the next round admits more.  Requests never share
+ * data, so a request's result does not depend on what else is resident.
+ * One thread drives a server (submit, poll and run_round may be called from
+ * one thread at a time). */
+typedef struct chns_server chns_server;
+
+enum {
+  CHNS_REQ_QUEUED = 0,   /* waiting for the builder                        */
+  CHNS_REQ_READY = 1,    /* mesh and U^0 built, waiting for device memory  */
+  CHNS_REQ_RESIDENT = 2, /* on the device, stepping                        */
+  CHNS_REQ_DONE = 3,     /* all steps taken; final state on the host       */
+  CHNS_REQ_FAILED = 4    /* build, upload or a step returned an error      */
+};
+
+typedef struct {
+  int32_t state;            /* CHNS_REQ_*                                   */
+  int32_t status;           /* last library status of the request           */
+  int32_t n_steps, steps_done;
+  int64_t n_leaves, n_nodes;
+  int64_t footprint_bytes;  /* device bytes reserved while resident         */
+  double t_submit_ms, t_admit_ms, t_done_ms; /* since server creation       */
+} chns_request_info;
+
+typedef struct {
+  int64_t queued, ready, resident, done, failed;
+  int64_t bytes_in_use, budget_bytes;
+  int64_t rounds, steps;
+} chns_server_stats;
+
+/* Creates a server on the current device.  hbm_budget_bytes bounds the sum
+ * of the footprints of resident requests; max_resident bounds their number
+ * (1..64); opts apply to every step (graphs forced on). */
+int chns_server_create(size_t hbm_budget_bytes, int max_resident, const chns_solver_opts* opts,
+                       chns_server** out);
+/* Queues a request.  spec is copied (including explicit leaves); spec->phi0
+ * and spec->user must stay valid until the request leaves CHNS_REQ_QUEUED
+ * (the builder thread calls phi0).  params are validated here.  *ticket
+ * identifies the request (increasing from 0). */
+int chns_server_submit(chns_server* srv, const chns_mesh_spec* spec, const chns_params* params,
+                       int n_steps, int64_t* ticket);
+/* State of a request.  Any output may be NULL.  U_host_out (n_nodes*6
+ * doubles, see info->n_nodes) is written once the request is DONE;
+ * per_step (n_steps entries) and step_latency_ms (n_steps doubles: from the
+ * start of the round that ran the step to the end of that step) receive the
+ * steps taken so far. */
+int chns_server_poll(chns_server* srv, int64_t ticket, chns_request_info* info,
+                     double* U_host_out, chns_step_stats* per_step, double* step_latency_ms);
+/* One round: admission, then one step of every resident request.  The round
+ * starts after the work already queued on `stream` and work queued on
+ * `stream` afterwards runs after the round.  Returns the number of steps
+ * taken (>= 0) or a negative status for a failure of the server itself;
+ * a failing request only moves to CHNS_REQ_FAILED. */
+int chns_server_run_round(chns_server* srv, void* stream);
+int chns_server_stats_get(chns_server* srv, chns_server_stats* out);
+/* Stops the builder, frees every request's device and host memory. */
+int chns_server_destroy(chns_server* srv);
+
 const char* chns_last_error(void);
 
 #ifdef __cplusplus

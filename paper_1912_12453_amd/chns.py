@@ -28,6 +28,7 @@ CHNS_BLOCK_CH = 0
 CHNS_BLOCK_NS = 1
 CHNS_F64 = 0
 CHNS_F32 = 1
+CHNS_REQ_QUEUED, CHNS_REQ_READY, CHNS_REQ_RESIDENT, CHNS_REQ_DONE, CHNS_REQ_FAILED = range(5)
 
 PHI0_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double), C.c_void_p)
 
@@ -80,6 +81,22 @@ class chns_step_stats(C.Structure):
                 "t_ms": self.t_ms}
 
 
+class chns_request_info(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("n_steps", C.c_int32),
+                ("steps_done", C.c_int32), ("n_leaves", C.c_int64), ("n_nodes", C.c_int64),
+                ("footprint_bytes", C.c_int64), ("t_submit_ms", C.c_double),
+                ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double)]
+
+
+class chns_server_stats(C.Structure):
+    _fields_ = [("queued", C.c_int64), ("ready", C.c_int64), ("resident", C.c_int64),
+                ("done", C.c_int64), ("failed", C.c_int64), ("bytes_in_use", C.c_int64),
+                ("budget_bytes", C.c_int64), ("rounds", C.c_int64), ("steps", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -107,6 +124,13 @@ def lib():
                                 C.POINTER(chns_step_stats), vp]
         L.chns_launch_element_loop.argtypes = [vp, C.POINTER(chns_params), C.c_int, C.c_int, vp, vp,
                                                vp, vp, C.c_int, vp, C.POINTER(C.c_int64)]
+        L.chns_server_create.argtypes = [C.c_size_t, C.c_int, C.POINTER(chns_solver_opts), C.POINTER(vp)]
+        L.chns_server_submit.argtypes = [vp, C.POINTER(chns_mesh_spec), C.POINTER(chns_params), C.c_int,
+                                         C.POINTER(C.c_int64)]
+        L.chns_server_poll.argtypes = [vp, C.c_int64, C.POINTER(chns_request_info), vp, vp, vp]
+        L.chns_server_run_round.argtypes = [vp, vp]
+        L.chns_server_stats_get.argtypes = [vp, C.POINTER(chns_server_stats)]
+        L.chns_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -200,6 +224,54 @@ def chns_launch_element_loop(mesh, params, block, op, U_new, U_old, dU, out, rep
     return g.value
 
 
+def chns_server_create(hbm_budget_bytes, max_resident, opts):
+    h = C.c_void_p()
+    _check(lib().chns_server_create(int(hbm_budget_bytes), int(max_resident), C.byref(opts),
+                                    C.byref(h)))
+    return h
+
+
+def chns_server_submit(server, spec, params, n_steps):
+    t = C.c_int64()
+    _check(lib().chns_server_submit(server, C.byref(spec), C.byref(params), int(n_steps), C.byref(t)))
+    return t.value
+
+
+def chns_server_poll(server, ticket, want_state=False, want_steps=False):
+    """Returns (info, U or None, [step stats], [step latency ms])."""
+    info = chns_request_info()
+    _check(lib().chns_server_poll(server, ticket, C.byref(info), None, None, None))
+    U = None
+    stats, lat = [], []
+    n = int(info.steps_done)
+    if want_steps and n:
+        arr = (chns_step_stats * n)()
+        la = (C.c_double * n)()
+        _check(lib().chns_server_poll(server, ticket, None, None, arr, la))
+        stats, lat = list(arr), list(la)
+    if want_state and info.state == CHNS_REQ_DONE:
+        U = np.zeros((int(info.n_nodes), 6))
+        _check(lib().chns_server_poll(server, ticket, None, U.ctypes.data, None, None))
+    return info, U, stats, lat
+
+
+def chns_server_run_round(server, stream=None):
+    rc = lib().chns_server_run_round(server, _stream(stream))
+    if rc < 0:
+        _check(rc)
+    return rc
+
+
+def chns_server_stats_get(server):
+    st = chns_server_stats()
+    _check(lib().chns_server_stats_get(server, C.byref(st)))
+    return st
+
+
+def chns_server_destroy(server):
+    _check(lib().chns_server_destroy(server))
+
+
 def _stream(stream):
     if stream is not None:
         return C.c_void_p(stream)
@@ -218,29 +290,77 @@ def _dev(t, dtype):
 
 
 # ------------------------------------------------------- convenience ------
+def make_spec(trees=(1, 1, 1), level_min=0, level_max=0, phi0=None, band=0.9, leaves=None):
+    """A chns_mesh_spec and the Python objects it points to (keep them alive
+    while the library may read the spec)."""
+    spec = chns_mesh_spec()
+    spec.trees = (C.c_int32 * 3)(*trees)
+    spec.level_min = level_min
+    spec.level_max = level_max
+    spec.band = band
+    cb = PHI0_FN()
+    if phi0 is not None:
+        def _cb(xyz, n, out, user, _f=phi0):
+            pts = np.ctypeslib.as_array(xyz, shape=(n, 3))
+            res = np.ctypeslib.as_array(out, shape=(n,))
+            res[:] = _f(pts)
+        cb = PHI0_FN(_cb)
+    spec.phi0 = cb
+    lv = None
+    if leaves is not None:
+        lv = np.ascontiguousarray(leaves, dtype=np.int32).reshape(-1, 4)
+        spec.leaves = lv.ctypes.data_as(C.POINTER(C.c_int32))
+        spec.n_leaves = lv.shape[0]
+    return spec, (cb, lv)
+
+
+class Server:
+    """The serving loop (chns_server_*): submit independent problems, run
+    rounds, poll results."""
+
+    def __init__(self, hbm_budget_bytes, max_resident, opts):
+        self.h = chns_server_create(hbm_budget_bytes, max_resident, opts)
+        self._keep = {}
+
+    def submit(self, mesh_spec, physics, n_steps):
+        """mesh_spec: a workloads.MeshSpec; physics: a workloads.Physics."""
+        spec, keep = make_spec(mesh_spec.trees, mesh_spec.level_min, mesh_spec.level_max,
+                               mesh_spec.phi0, mesh_spec.band)
+        t = chns_server_submit(self.h, spec, make_params(physics), n_steps)
+        self._keep[t] = keep
+        return t
+
+    def poll(self, ticket, state=False, steps=False):
+        info, U, st, lat = chns_server_poll(self.h, ticket, state, steps)
+        if info.state >= CHNS_REQ_READY:
+            self._keep.pop(ticket, None)  # the builder no longer reads the spec
+        return info, U, st, lat
+
+    def run_round(self, stream=None):
+        return chns_server_run_round(self.h, stream)
+
+    def stats(self):
+        return chns_server_stats_get(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            chns_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Mesh:
     """A balanced octree mesh owned by libchns (Sec. 4)."""
 
     def __init__(self, trees=(1, 1, 1), level_min=0, level_max=0, phi0=None, band=0.9,
                  leaves=None):
-        spec = chns_mesh_spec()
-        spec.trees = (C.c_int32 * 3)(*trees)
-        spec.level_min = level_min
-        spec.level_max = level_max
-        spec.band = band
-        self._cb = PHI0_FN()
-        if phi0 is not None:
-            def cb(xyz, n, out, user, _f=phi0):
-                pts = np.ctypeslib.as_array(xyz, shape=(n, 3))
-                res = np.ctypeslib.as_array(out, shape=(n,))
-                res[:] = _f(pts)
-            self._cb = PHI0_FN(cb)
-        spec.phi0 = self._cb
-        self._leaves = None
-        if leaves is not None:
-            self._leaves = np.ascontiguousarray(leaves, dtype=np.int32).reshape(-1, 4)
-            spec.leaves = self._leaves.ctypes.data_as(C.POINTER(C.c_int32))
-            spec.n_leaves = self._leaves.shape[0]
+        spec, self._keep = make_spec(trees, level_min, level_max, phi0, band, leaves)
         self.h = chns_mesh_build(spec)
         self.stats = chns_mesh_info(self.h)
         self.trees = tuple(trees)

@@ -126,6 +126,7 @@ void free_workspace(Workspace& w) {
 struct chns_mesh {
   HostMesh h;
   ScatterPlan plan;
+  bool plan_ready = false;  // built ahead of upload (the serving builder does)
   int device = -1;
   bool uploaded = false;
   int32_t *d_elem = nullptr, *d_hoff = nullptr, *d_hids = nullptr, *d_anchor = nullptr;
@@ -235,13 +236,16 @@ int upload(chns_mesh* m, hipStream_t s) {
   const HostMesh& h = m->h;
   const size_t E = h.leaf_key.size(), NH = h.hang_key.size(), NC = h.hang_ids.size();
   if (h.max_fanin > 8) return fail(CHNS_EINVAL, "hanging-node fan-in above 8 is not supported");
-  std::string perr;
-  try {
-    perr = build_scatter_plan(h, m->plan);
-  } catch (const std::bad_alloc&) {
-    perr = "out of host memory building the scatter plan";
+  if (!m->plan_ready) {
+    std::string perr;
+    try {
+      perr = build_scatter_plan(h, m->plan);
+    } catch (const std::bad_alloc&) {
+      perr = "out of host memory building the scatter plan";
+    }
+    if (!perr.empty()) return fail(CHNS_ENOMEM, perr);
+    m->plan_ready = true;
   }
-  if (!perr.empty()) return fail(CHNS_ENOMEM, perr);
   const ScatterPlan& P = m->plan;
   std::vector<int32_t> anchor(E * 3);
   for (size_t e = 0; e < E; ++e) {
@@ -770,6 +774,18 @@ struct Solver {
 
 }  // namespace
 
+int check_opts(const chns_solver_opts* opts) {
+  if (opts->gmres_restart < 1 || opts->gmres_restart > dev::kMaxBasis - 1)
+    return fail(CHNS_EINVAL, "gmres_restart must be in [1, " + std::to_string(dev::kMaxBasis - 1) + "]");
+  if (opts->precision != 0 && opts->precision != 1) return fail(CHNS_EINVAL, "precision must be 0 or 1");
+  if (opts->precond != 0 && opts->precond != 1) return fail(CHNS_EINVAL, "precond must be 0 or 1");
+  if (opts->block_max_it < 1 || opts->gmres_max_it < 1)
+    return fail(CHNS_EINVAL, "iteration limits must be positive");
+  if (opts->newton_max_it_ch < 0 || opts->newton_max_it_ns < 0 || opts->block_min_it < 0)
+    return fail(CHNS_EINVAL, "iteration limits must not be negative");
+  return CHNS_OK;
+}
+
 // =================================================================== ABI ==
 extern "C" {
 
@@ -948,11 +964,7 @@ int chns_step(chns_mesh* m, const chns_params* params, const chns_solver_opts* o
   dev::PhysView pv;
   if ((rc = phys_view(params, pv))) return rc;
   if (!opts || !U || !out) return fail(CHNS_EINVAL, "opts, U and out must not be NULL");
-  if (opts->gmres_restart < 1 || opts->gmres_restart > dev::kMaxBasis - 1)
-    return fail(CHNS_EINVAL, "gmres_restart must be in [1, " + std::to_string(dev::kMaxBasis - 1) + "]");
-  if (opts->precision != 0 && opts->precision != 1) return fail(CHNS_EINVAL, "precision must be 0 or 1");
-  if (opts->precond != 0 && opts->precond != 1) return fail(CHNS_EINVAL, "precond must be 0 or 1");
-  if (opts->block_max_it < 1 || opts->gmres_max_it < 1) return fail(CHNS_EINVAL, "iteration limits must be positive");
+  if ((rc = check_opts(opts))) return rc;
   std::memset(out, 0, sizeof(*out));
   const auto t0 = std::chrono::steady_clock::now();
   Solver S(m, pv, *opts, s);
@@ -1022,3 +1034,5 @@ int chns_launch_element_loop(chns_mesh* m, const chns_params* params, int block,
 }
 
 }  // extern "C"
+
+#include "serve.inl"

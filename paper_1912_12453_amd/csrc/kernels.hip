@@ -499,7 +499,7 @@ __global__ void k_gather(PlanView pl, int64_t n, const TP* __restrict__ partial,
     TO v[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) v[f] = (TO)acc[f];
-    if (MODE != 0) {
+    if constexpr (MODE != 0) {
       const uint8_t b = pl.bflags[i];
       if (b & 1) {
 #pragma unroll

@@ -1,0 +1,74 @@
+"""Request loop over the libchns server: replays a stream of timed requests
+(workloads.serving_stream), submitting each when its arrival time has passed
+and running rounds while anything is resident or waiting, then summarises
+per-step latency and throughput.
+
+Per-step latency runs from the start of the round in which the step was
+runnable to the end of that step (the library measures it); a request that
+waits for memory or for the builder is not runnable and its waiting shows in
+its time to admission instead.
+"""
+import time
+
+import numpy as np
+
+from . import chns
+
+
+def run_stream(server, requests, time_scale=1.0, log=None, max_wall_s=None):
+    """Runs the requests (objects with .arrival_s, .workload, .kind) through
+    `server` (a chns.Server).  Arrival times are multiplied by time_scale.
+    Returns (summary dict, per-request list)."""
+    pending = sorted(requests, key=lambda r: r.arrival_s)
+    tickets = {}
+    t0 = time.perf_counter()
+    i = 0
+    rounds = 0
+    while True:
+        now = time.perf_counter() - t0
+        while i < len(pending) and pending[i].arrival_s * time_scale <= now:
+            r = pending[i]
+            tickets[r.rid] = (server.submit(r.workload.mesh, r.workload.physics, r.workload.steps), now)
+            i += 1
+        st = server.stats()
+        if st.done + st.failed == len(pending):
+            break
+        if max_wall_s is not None and now > max_wall_s:
+            raise TimeoutError(f"serving stream did not finish in {max_wall_s} s: {st.as_dict()}")
+        if st.resident or st.ready:
+            n = server.run_round()
+            rounds += 1
+            if log and rounds % 10 == 0:
+                log(f"[serve] t={now:.1f}s round {rounds}: {st.as_dict()} steps this round {n}")
+            if n > 0:
+                continue
+        # nothing runnable: wait for the builder or the next arrival
+        nxt = pending[i].arrival_s * time_scale - now if i < len(pending) else 0.002
+        time.sleep(min(max(nxt, 0.0), 0.002))
+    wall = time.perf_counter() - t0
+    per = []
+    lat = []
+    dof_steps = 0
+    conv = 0
+    nsteps = 0
+    for r in pending:
+        t, t_arr = tickets[r.rid]
+        info, U, stats, la = server.poll(t, steps=True)
+        per.append({"rid": r.rid, "kind": r.kind, "state": int(info.state), "nodes": int(info.n_nodes),
+                    "steps": int(info.steps_done), "arrival_s": t_arr,
+                    "admit_wait_ms": float(info.t_admit_ms - info.t_submit_ms) if info.t_admit_ms else None,
+                    "latency_ms": la, "converged": [bool(s.converged) for s in stats],
+                    "gmres_its": [list(s.gmres_its) for s in stats]})
+        lat += la
+        dof_steps += 6 * int(info.n_nodes) * int(info.steps_done)
+        conv += sum(1 for s in stats if s.converged)
+        nsteps += len(stats)
+    sst = server.stats().as_dict()
+    summary = {"requests": len(pending), "done": sst["done"], "failed": sst["failed"],
+               "rounds": sst["rounds"], "steps": nsteps, "wall_s": round(wall, 3),
+               "steps_per_s": round(nsteps / wall, 3),
+               "dof_steps_per_s": round(dof_steps / wall, 1),
+               "p50_step_ms": round(float(np.percentile(lat, 50)), 3) if lat else None,
+               "p99_step_ms": round(float(np.percentile(lat, 99)), 3) if lat else None,
+               "converged_step_fraction": round(conv / nsteps, 4) if nsteps else None}
+    return summary, per

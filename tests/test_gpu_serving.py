@@ -1,0 +1,146 @@
+"""The serving loop (chns_server_*): a request's result is the same alone and
+in a mix with other requests admitted while it runs, admission respects the
+HBM budget, and one failing request does not disturb the others."""
+import numpy as np
+import pytest
+
+from paper_1912_12453_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def chns():
+    from paper_1912_12453_amd import chns as c
+    c.lib()
+    return c
+
+
+def request(level, drops, bubble, ratio, visc, steps=3, Cn=0.04):
+    inside = -1.0
+    return W.Workload(
+        name=f"r{level}", mesh=W.MeshSpec((1, 1, 1), 3, level, W.drops_phi(drops, Cn, inside), 0.9),
+        physics=W.Physics(Cn=Cn, Pe=1.0 / (3 * Cn * Cn), Re=35.0, We=10.0, Fr=1.0,
+                          rho_minus=(1.0 / ratio) if bubble else ratio,
+                          eta_minus=(1.0 / visc) if bubble else visc, dt=5e-4),
+        steps=steps)
+
+
+REQS = [
+    request(5, [((0.5, 0.5, 0.5), 0.2)], True, 10.0, 5.0),
+    request(4, [((0.3, 0.4, 0.5), 0.15), ((0.7, 0.6, 0.5), 0.12)], False, 3.0, 2.0, steps=4),
+    request(5, [((0.4, 0.5, 0.6), 0.18)], False, 20.0, 10.0, steps=2),
+]
+
+
+def opts(chns):
+    return chns.make_opts(precision=1, gmres_rtol=1e-5, gmres_restart=60)
+
+
+def drain(server, max_rounds=200):
+    for _ in range(max_rounds):
+        st = server.stats()
+        if st.queued == 0 and st.ready == 0 and st.resident == 0:
+            return
+        if server.run_round() == 0:
+            import time
+            time.sleep(0.002)
+    raise AssertionError("server did not drain")
+
+
+def test_alone_equals_mix(torch, chns):
+    """Request 0 run alone, and run while requests 1 and 2 arrive and leave
+    around it, gives bit-identical final states and solver counts; both equal
+    chns_step applied n_steps times to the same mesh and U^0."""
+    print("case serving alone-vs-mix", flush=True)
+    alone = chns.Server(1 << 34, 1, opts(chns))
+    t = alone.submit(REQS[0].mesh, REQS[0].physics, REQS[0].steps)
+    drain(alone)
+    ia, Ua, sa, _ = alone.poll(t, state=True, steps=True)
+    assert ia.state == chns.CHNS_REQ_DONE, ia.status
+    alone.close()
+
+    mix = chns.Server(1 << 34, 3, opts(chns))
+    t1 = mix.submit(REQS[1].mesh, REQS[1].physics, REQS[1].steps)
+    t0 = mix.submit(REQS[0].mesh, REQS[0].physics, REQS[0].steps)
+    # let the first round start with what is built, then add the third
+    import time
+    time.sleep(0.2)
+    mix.run_round()
+    t2 = mix.submit(REQS[2].mesh, REQS[2].physics, REQS[2].steps)
+    drain(mix)
+    im, Um, sm, lat = mix.poll(t0, state=True, steps=True)
+    assert im.state == chns.CHNS_REQ_DONE
+    assert np.array_equal(Ua, Um)
+    assert [list(s.gmres_its) for s in sa] == [list(s.gmres_its) for s in sm]
+    assert len(lat) == REQS[0].steps and all(v > 0 for v in lat)
+    for tk in (t1, t2):
+        info, U, _, _ = mix.poll(tk, state=True)
+        assert info.state == chns.CHNS_REQ_DONE and np.isfinite(U).all()
+    assert mix.stats().rounds >= max(r.steps for r in REQS)
+    mix.close()
+
+    # the same steps through chns_step
+    m = chns.Mesh.from_spec(REQS[0].mesh)
+    xyz, bf = m.nodes()
+    phi = REQS[0].mesh.phi0(xyz)
+    U = np.zeros((m.n_nodes, 6))
+    U[:, 0] = phi
+    U[:, 1] = phi * phi * phi - phi
+    d = torch.tensor(U, device="cuda:0")
+    p = chns.make_params(REQS[0].physics)
+    o = opts(chns)
+    for _ in range(REQS[0].steps):
+        rc, st = m.step(p, o, d)
+        assert rc in (chns.CHNS_OK, chns.CHNS_NOT_CONVERGED)
+    assert np.array_equal(d.cpu().numpy(), Ua)
+
+
+def test_admission_by_footprint(torch, chns):
+    """A budget that holds one request at a time serialises them; all finish."""
+    print("case serving admission", flush=True)
+    probe = chns.Server(1 << 34, 4, opts(chns))
+    tks = [probe.submit(r.mesh, r.physics, 1) for r in REQS]
+    import time
+    for _ in range(500):
+        if all(probe.poll(t)[0].state >= chns.CHNS_REQ_READY for t in tks):
+            break
+        time.sleep(0.01)
+    fps = [probe.poll(t)[0].footprint_bytes for t in tks]
+    probe.close()
+    assert all(f > 0 for f in fps)
+    srv = chns.Server(max(fps) + 1, 4, opts(chns))
+    tks = [srv.submit(r.mesh, r.physics, r.steps) for r in REQS]
+    for _ in range(200):
+        st = srv.stats()
+        assert st.resident <= 1 and st.bytes_in_use <= max(fps) + 1
+        if st.done == len(REQS):
+            break
+        if srv.run_round() == 0:
+            time.sleep(0.002)
+    assert srv.stats().done == len(REQS)
+    assert srv.stats().bytes_in_use == 0
+    srv.close()
+
+
+def test_oversized_request_fails_alone(torch, chns):
+    """A request above the budget fails with a message; the others complete."""
+    print("case serving oversized", flush=True)
+    big = request(7, [((0.5, 0.5, 0.5), 0.3)], True, 10.0, 5.0, steps=1)
+    small = REQS[1]
+    srv = chns.Server(64 << 20, 2, opts(chns))
+    tb = srv.submit(big.mesh, big.physics, 1)
+    ts = srv.submit(small.mesh, small.physics, 2)
+    drain(srv)
+    ib = srv.poll(tb)[0]
+    assert ib.state == chns.CHNS_REQ_FAILED and ib.status == chns.CHNS_EINVAL
+    assert "budget" in chns.lib().chns_last_error().decode()
+    assert srv.poll(ts)[0].state == chns.CHNS_REQ_DONE
+    srv.close()
