@@ -25,6 +25,7 @@ and mixed precision.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
                        [--workload bubble_l9|bubble_l8|drop16|rt_l10] [--no-cpu-baseline]
                        [--cn-steps K] [--no-steps]
+       python bench.py --serving [--serve-requests 64] [--serve-steps 10] ...
 """
 import argparse
 import json
@@ -99,6 +100,41 @@ def cn_steps(chns, W, torch, dev, nsteps):
     return out
 
 
+def serving_main(args):
+    """Config of the serving stream: Poisson arrivals of independent droplet /
+    bubble problems (workloads.serving_stream), mixed precision, admitted by
+    footprint into an HBM budget.  Prints one JSON line."""
+    import torch
+
+    from paper_1912_12453_amd import chns, serving
+    from paper_1912_12453_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    reqs = W.serving_stream(n_requests=args.serve_requests, rate_hz=20.0, seed=4,
+                            level_range=(args.serve_level_min, args.serve_level_max),
+                            steps=args.serve_steps)
+    opts = chns.make_opts(precision=1, gmres_rtol=1e-5, gmres_restart=60,
+                          gmres_max_it=args.serve_gmres_max_it, newton_max_it_ch=4,
+                          newton_max_it_ns=4, block_max_it=2)
+    srv = chns.Server(args.serve_budget_gib << 30, args.serve_max_resident, opts)
+    summ, per = serving.run_stream(srv, reqs, log=log, max_wall_s=args.serve_max_wall_s)
+    srv.close()
+    res = {"metric": "serving CN steps/s with p50/p99 per-step latency", "value": summ["steps_per_s"],
+           "unit": "steps/s", "n_gpus": 1, "steps": summ["steps"], "warmup": 0,
+           "ms_per_step": round(1e3 * summ["wall_s"] / max(summ["steps"], 1), 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+           "data": "synthetic",
+           "config": {"workload": "serving_stream", "requests": args.serve_requests, "rate_hz": 20.0,
+                      "levels": [args.serve_level_min, args.serve_level_max],
+                      "steps_per_request": args.serve_steps, "budget_gib": args.serve_budget_gib,
+                      "max_resident": args.serve_max_resident,
+                      "gmres_max_it": args.serve_gmres_max_it},
+           "serving": summ,
+           "largest_requests": sorted(({"nodes": p["nodes"], "latency_ms": [round(x, 1) for x in p["latency_ms"]]}
+                                       for p in per), key=lambda d: -d["nodes"])[:3]}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,11 +147,22 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--cn-steps", type=int, default=10)
     ap.add_argument("--no-steps", action="store_true")
+    ap.add_argument("--serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=10)
+    ap.add_argument("--serve-level-min", type=int, default=6)
+    ap.add_argument("--serve-level-max", type=int, default=8)
+    ap.add_argument("--serve-budget-gib", type=int, default=160)
+    ap.add_argument("--serve-max-resident", type=int, default=16)
+    ap.add_argument("--serve-gmres-max-it", type=int, default=60)
+    ap.add_argument("--serve-max-wall-s", type=float, default=900.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.serving:
+        return serving_main(args)
 
     import numpy as np
     import torch
@@ -219,8 +266,8 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        ent = tr.get("kernels", {}).get(kname)
-        if ent and ent.get("workload") == name and ent.get("leaves") == E:
+        ent = tr.get("kernels", {}).get(kname, {}).get(name)
+        if ent and ent.get("leaves") == E:
             traffic = ent["hbm_bytes_per_launch"]
     roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_TFLOPS[prec],
             "unit": "TFLOP/s", "frac": round(tflops / PEAK_TFLOPS[prec], 4), "traffic": traffic,

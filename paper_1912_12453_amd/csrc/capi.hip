@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,13 @@ using namespace chns;
 namespace {
 
 thread_local std::string g_err;
+
+// Allocation, release, stream creation and graph capture of every mesh and
+// server go through this lock, so that a capture in progress on one host
+// thread never overlaps an allocation or a free (with its implicit device
+// synchronisation) made by another.  Kernel launches, copies and
+// synchronisation of streams do not take it.
+std::mutex g_struct_mu;
 int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
@@ -256,6 +264,7 @@ int upload(chns_mesh* m, hipStream_t s) {
     anchor[3 * e + 2] = (int32_t)z;
   }
   std::vector<float> w32(h.hang_w.begin(), h.hang_w.end());
+  std::lock_guard<std::mutex> lk(g_struct_mu);
   int64_t& B = m->device_bytes;
   B = 0;
   int rc;
@@ -300,6 +309,7 @@ int upload(chns_mesh* m, hipStream_t s) {
 
 int ensure_tbuf(chns_mesh* m) {
   if (m->d_tbuf) return CHNS_OK;
+  std::lock_guard<std::mutex> lk(g_struct_mu);
   return dalloc(&m->d_tbuf, (size_t)m->plan.ntouch_slot.size() * 16, &m->device_bytes);
 }
 
@@ -415,6 +425,7 @@ struct Solver {
       : m(m_), pv(pv_), o(o_), s(s_), w(m_->ws), n((int64_t)m_->h.node_key.size()) {}
 
   int ensure_workspace() {
+    std::lock_guard<std::mutex> lk(g_struct_mu);
     int rc;
     int64_t& B = w.bytes;
     const size_t N = (size_t)n * 4;
@@ -585,6 +596,7 @@ struct Solver {
         break;
       }
     if (!ex) {
+      std::lock_guard<std::mutex> lk(g_struct_mu);
       if (w.graphs.size() >= 64) drop_graphs(w);
       hipGraph_t graph = nullptr;
       hipStream_t caller = s;
@@ -888,6 +900,7 @@ int chns_mesh_upload(chns_mesh* m, void* stream) {
 
 int chns_mesh_free(chns_mesh* m) {
   if (!m) return CHNS_OK;
+  std::lock_guard<std::mutex> lk(g_struct_mu);
   free_workspace(m->ws);
   void* ptrs[] = {m->d_elem, m->d_hoff, m->d_hids, m->d_anchor, m->d_level,
                   m->d_hw, m->d_hw32, m->d_flag, m->d_part, m->d_sum,

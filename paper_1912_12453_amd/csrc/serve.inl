@@ -3,11 +3,12 @@
 // capi.hip (it drives the same Solver and upload code).
 //
 // Request life: QUEUED (spec copied) -> builder thread: host octree, scatter
-// plan, U^0 and exact device footprint -> READY -> a round admits it while
-// the footprint fits the budget: upload on the request's own stream ->
-// RESIDENT: one Crank-Nicolson step per round, each resident on its own
-// host thread and stream -> DONE after its last step (state copied to the
-// host, device memory freed) or FAILED.
+// plan, U^0 and exact device footprint -> READY -> admitted by
+// chns_server_run_round while the footprint fits the budget: upload on the
+// request's own stream -> RESIDENT: a driver thread of its own runs its
+// Crank-Nicolson steps back to back on that stream -> DONE after its last
+// step (state copied to the host, device memory freed) or FAILED.  Steps of
+// different residents overlap on the device; none waits for another.
 
 #include <condition_variable>
 #include <deque>
@@ -60,11 +61,14 @@ struct Request {
   chns_mesh* mesh = nullptr;
   std::vector<double> U0;        // host U^0, then the final state
   int64_t footprint = 0;
+  int64_t n_leaves = 0, n_nodes = 0;
   double* dU = nullptr;          // device state
   hipStream_t stream = nullptr;
   std::vector<chns_step_stats> stats;
   std::vector<double> latency_ms;
   double t_submit = 0, t_admit = 0, t_done = 0;
+  std::thread driver;
+  bool finished = false;  // the driver has left (joined by the next round)
 };
 
 }  // namespace
@@ -76,13 +80,16 @@ struct chns_server {
   chns_solver_opts opts{};
   Clock::time_point t0;
   std::mutex mu;
-  std::condition_variable cv;
+  std::condition_variable cv;        // builder work
+  std::condition_variable progress;  // a step ended, a request left or became READY
   bool stop = false;
   std::deque<Request*> build_queue;
   std::vector<Request*> ready;     // arrival order
   std::vector<Request*> resident;
   std::map<int64_t, std::unique_ptr<Request>> all;
   int64_t next_ticket = 0, in_use = 0, rounds = 0, steps = 0;
+  int wait_ms = 20;     // longest wait of a round for progress
+  int64_t events = 0;   // steps ended, requests left or became READY
   std::thread builder;
 
   double now_ms() const { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); }
@@ -128,6 +135,8 @@ void build_request(chns_server* S, Request* r) {
   std::lock_guard<std::mutex> lk(S->mu);
   r->mesh = m;
   if (err.empty()) {
+    r->n_leaves = (int64_t)m->h.leaf_key.size();
+    r->n_nodes = (int64_t)m->h.node_key.size();
     r->footprint = mesh_footprint(m) + workspace_footprint((int64_t)m->h.node_key.size(), S->opts);
     if (r->footprint > S->budget) err = "request needs " + std::to_string(r->footprint) +
                                         " device bytes, above the server budget";
@@ -139,10 +148,14 @@ void build_request(chns_server* S, Request* r) {
     r->t_done = S->now_ms();
     if (m) chns_mesh_free(m);
     r->mesh = nullptr;
+    S->events += 1;
+    S->progress.notify_all();
     return;
   }
   r->state = CHNS_REQ_READY;
   S->ready.push_back(r);
+  S->events += 1;
+  S->progress.notify_all();
 }
 
 void builder_main(chns_server* S) {
@@ -160,32 +173,97 @@ void builder_main(chns_server* S) {
 }
 
 void free_request(Request* r) {
+  if (r->mesh) chns_mesh_free(r->mesh);  // takes the structural lock itself
+  r->mesh = nullptr;
+  std::lock_guard<std::mutex> lk(g_struct_mu);
   if (r->dU) (void)hipFree(r->dU);
   r->dU = nullptr;
-  if (r->mesh) chns_mesh_free(r->mesh);
-  r->mesh = nullptr;
   if (r->stream) (void)hipStreamDestroy(r->stream);
   r->stream = nullptr;
 }
 
-// Frees an admitted request's device resources and returns its footprint to
-// the budget (called without the lock held).
-void release(chns_server* S, Request* r) {
-  free_request(r);
-  std::lock_guard<std::mutex> lk(S->mu);
-  S->in_use -= r->footprint;
-}
-
-int admit_upload(chns_server* S, Request* r) {
-  HIPCHK(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking));
+int admit_upload(chns_server* S, Request* r, hipEvent_t after) {
+  const size_t n = r->mesh->h.node_key.size();
+  {
+    std::lock_guard<std::mutex> lk(g_struct_mu);
+    HIPCHK(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking));
+    const int rc = dalloc(&r->dU, n * 6, nullptr);
+    if (rc) return rc;
+  }
+  HIPCHK(hipStreamWaitEvent(r->stream, after, 0));
   int rc = upload(r->mesh, r->stream);
   if (rc) return rc;
   if ((rc = ensure_tbuf(r->mesh))) return rc;
-  const size_t n = r->mesh->h.node_key.size();
-  if ((rc = dalloc(&r->dU, n * 6, nullptr))) return rc;
   HIPCHK(hipMemcpyAsync(r->dU, r->U0.data(), n * 6 * sizeof(double), hipMemcpyHostToDevice, r->stream));
   HIPCHK(hipStreamSynchronize(r->stream));
   return CHNS_OK;
+}
+
+// Driver of one resident request: its steps back to back on its stream.
+// Per-step latency runs from the moment the step became runnable (admission
+// or the end of the previous step) to its end.
+void drive(chns_server* S, Request* r) {
+  int rc = CHNS_OK;
+  std::string err;
+  if (hipSetDevice(S->device) != hipSuccess) {
+    rc = CHNS_EHIP;
+    err = "hipSetDevice failed in a request driver";
+  }
+  auto t_ready = Clock::now();
+  for (int k = 0; rc >= 0 && k < r->n_steps; ++k) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (S->stop) {
+        rc = CHNS_EINVAL;
+        err = "server destroyed while the request ran";
+        break;
+      }
+    }
+    chns_step_stats st;
+    std::memset(&st, 0, sizeof(st));
+    const auto ts = Clock::now();
+    Solver sol(r->mesh, r->pv, S->opts, r->stream);
+    const int src = sol.step(r->dU, &st);
+    const auto te = Clock::now();
+    if (src < 0) {
+      rc = src;
+      err = g_err;
+      break;
+    }
+    st.t_ms = std::chrono::duration<double, std::milli>(te - ts).count();
+    std::lock_guard<std::mutex> lk(S->mu);
+    r->stats.push_back(st);
+    r->latency_ms.push_back(std::chrono::duration<double, std::milli>(te - t_ready).count());
+    r->steps_done += 1;
+    r->status = src;
+    S->steps += 1;
+    t_ready = te;
+    S->events += 1;
+    S->progress.notify_all();
+  }
+  if (rc >= 0) {
+    if (hipMemcpyAsync(r->U0.data(), r->dU, r->U0.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       r->stream) != hipSuccess ||
+        hipStreamSynchronize(r->stream) != hipSuccess) {
+      rc = CHNS_EHIP;
+      err = "copying the final state to the host failed";
+    }
+  }
+  free_request(r);
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->in_use -= r->footprint;
+  S->resident.erase(std::find(S->resident.begin(), S->resident.end(), r));
+  r->t_done = S->now_ms();
+  if (rc < 0) {
+    r->state = CHNS_REQ_FAILED;
+    r->status = rc;
+    r->err = err;
+  } else {
+    r->state = CHNS_REQ_DONE;
+  }
+  r->finished = true;
+  S->events += 1;
+  S->progress.notify_all();
 }
 
 }  // namespace
@@ -255,12 +333,8 @@ int chns_server_poll(chns_server* S, int64_t ticket, chns_request_info* info, do
     info->status = r->status;
     info->n_steps = r->n_steps;
     info->steps_done = r->steps_done;
-    if (r->state == CHNS_REQ_DONE) {
-      info->n_nodes = (int64_t)r->U0.size() / 6;
-    } else if (r->mesh) {
-      info->n_nodes = (int64_t)r->mesh->h.node_key.size();
-      info->n_leaves = (int64_t)r->mesh->h.leaf_key.size();
-    }
+    info->n_nodes = r->n_nodes;
+    info->n_leaves = r->n_leaves;
     info->footprint_bytes = r->footprint;
     info->t_submit_ms = r->t_submit;
     info->t_admit_ms = r->t_admit;
@@ -278,12 +352,22 @@ int chns_server_poll(chns_server* S, int64_t ticket, chns_request_info* info, do
 
 int chns_server_run_round(chns_server* S, void* stream) {
   if (!S) return fail(CHNS_EINVAL, "server is NULL");
-  hipStream_t caller = (hipStream_t)stream;
   HIPCHK(hipSetDevice(S->device));
-  // admission: arrival order, skipping requests that do not fit yet
-  std::vector<Request*> admitted;
+  // join drivers that have left
+  std::vector<Request*> gone;
   {
     std::lock_guard<std::mutex> lk(S->mu);
+    for (auto& kv : S->all)
+      if (kv.second->finished && kv.second->driver.joinable()) gone.push_back(kv.second.get());
+  }
+  for (Request* r : gone) r->driver.join();
+  // admission: arrival order, skipping requests that do not fit yet
+  std::vector<Request*> admitted;
+  int64_t s0, e0;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    s0 = S->steps;
+    e0 = S->events;
     for (auto it = S->ready.begin(); it != S->ready.end();) {
       Request* r = *it;
       if ((int)(S->resident.size() + admitted.size()) >= S->max_resident) break;
@@ -298,108 +382,47 @@ int chns_server_run_round(chns_server* S, void* stream) {
       it = S->ready.erase(it);
     }
   }
-  for (Request* r : admitted) {
-    const int rc = admit_upload(S, r);
-    if (rc) {
-      std::string msg = g_err;
-      release(S, r);
+  if (!admitted.empty()) {
+    // uploads start after the work already queued on the caller's stream
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, (hipStream_t)stream));
+    for (Request* r : admitted) {
+      const int rc = admit_upload(S, r, ev);
+      if (rc) {
+        const std::string msg = g_err;
+        free_request(r);
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->in_use -= r->footprint;
+        r->state = CHNS_REQ_FAILED;
+        r->status = rc;
+        r->err = msg;
+        r->t_done = S->now_ms();
+        r->finished = true;
+        continue;
+      }
       std::lock_guard<std::mutex> lk(S->mu);
-      r->state = CHNS_REQ_FAILED;
-      r->status = rc;
-      r->err = msg;
-      r->t_done = S->now_ms();
-      continue;
-    }
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->resident.push_back(r);
-  }
-  std::vector<Request*> run;
-  {
-    std::lock_guard<std::mutex> lk(S->mu);
-    run = S->resident;
-  }
-  if (run.empty()) return 0;
-  // the round starts after the caller's queued work
-  hipEvent_t ev;
-  HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-  HIPCHK(hipEventRecord(ev, caller));
-  for (Request* r : run) HIPCHK(hipStreamWaitEvent(r->stream, ev, 0));
-  (void)hipEventDestroy(ev);
-  const auto t_round = Clock::now();
-  std::vector<int> rcs(run.size(), CHNS_OK);
-  std::vector<std::string> errs(run.size());
-  std::vector<chns_step_stats> sts(run.size());
-  std::vector<double> lat(run.size(), 0.0);
-  auto work = [&](size_t i) {
-    Request* r = run[i];
-    if (hipSetDevice(S->device) != hipSuccess) {
-      rcs[i] = CHNS_EHIP;
-      errs[i] = "hipSetDevice failed in a server worker";
-      return;
-    }
-    std::memset(&sts[i], 0, sizeof(chns_step_stats));
-    const auto ts = Clock::now();
-    Solver sol(r->mesh, r->pv, S->opts, r->stream);
-    rcs[i] = sol.step(r->dU, &sts[i]);
-    const auto te = Clock::now();
-    sts[i].t_ms = std::chrono::duration<double, std::milli>(te - ts).count();
-    lat[i] = std::chrono::duration<double, std::milli>(te - t_round).count();
-    if (rcs[i] < 0) errs[i] = g_err;
-  };
-  std::vector<std::thread> th;
-  th.reserve(run.size());
-  try {
-    for (size_t i = 1; i < run.size(); ++i) th.emplace_back(work, i);
-  } catch (...) {
-    for (auto& t : th) t.join();
-    return fail(CHNS_ENOMEM, "cannot start server worker threads");
-  }
-  work(0);
-  for (auto& t : th) t.join();
-  int n_ok = 0;
-  for (size_t i = 0; i < run.size(); ++i) {
-    Request* r = run[i];
-    bool leave = false;
-    if (rcs[i] < 0) {
-      leave = true;
-    } else {
-      ++n_ok;
-      r->stats.push_back(sts[i]);
-      r->latency_ms.push_back(lat[i]);
-      r->steps_done += 1;
-      r->status = rcs[i];
-      if (r->steps_done >= r->n_steps) {
-        const size_t n = r->U0.size();
-        if (hipMemcpyAsync(r->U0.data(), r->dU, n * sizeof(double), hipMemcpyDeviceToHost, r->stream) !=
-                hipSuccess ||
-            hipStreamSynchronize(r->stream) != hipSuccess) {
-          rcs[i] = CHNS_EHIP;
-          errs[i] = "copying the final state to the host failed";
-        }
-        leave = true;
+      S->resident.push_back(r);
+      try {
+        r->driver = std::thread(drive, S, r);
+      } catch (...) {
+        S->resident.pop_back();
+        S->in_use -= r->footprint;
+        r->state = CHNS_REQ_FAILED;
+        r->status = CHNS_ENOMEM;
+        r->err = "cannot start a request driver thread";
+        r->t_done = S->now_ms();
+        r->finished = true;
       }
     }
-    if (!leave) continue;
-    release(S, r);
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->resident.erase(std::find(S->resident.begin(), S->resident.end(), r));
-    r->t_done = S->now_ms();
-    if (rcs[i] < 0) {
-      r->state = CHNS_REQ_FAILED;
-      r->status = rcs[i];
-      r->err = errs[i];
-    } else {
-      r->state = CHNS_REQ_DONE;
-    }
+    (void)hipEventDestroy(ev);
   }
-  {
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->rounds += 1;
-    S->steps += n_ok;
-  }
-  // work queued on the caller's stream afterwards runs after the round
-  // (every resident stream was synchronised by its step)
-  return n_ok;
+  // wait for progress: a step ends, a request leaves or becomes READY
+  std::unique_lock<std::mutex> lk(S->mu);
+  S->rounds += 1;
+  if (S->resident.empty()) return 0;
+  S->progress.wait_for(lk, std::chrono::milliseconds(S->wait_ms), [&] { return S->events > e0; });
+  return (int)(S->steps - s0);
 }
 
 int chns_server_stats_get(chns_server* S, chns_server_stats* out) {
@@ -429,7 +452,11 @@ int chns_server_destroy(chns_server* S) {
     S->stop = true;
   }
   S->cv.notify_all();
+  S->progress.notify_all();
   if (S->builder.joinable()) S->builder.join();
+  // drivers stop before their next step; the one in progress completes
+  for (auto& kv : S->all)
+    if (kv.second->driver.joinable()) kv.second->driver.join();
   for (auto& kv : S->all) free_request(kv.second.get());
   delete S;
   return CHNS_OK;

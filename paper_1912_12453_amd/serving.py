@@ -3,10 +3,10 @@
 and running rounds while anything is resident or waiting, then summarises
 per-step latency and throughput.
 
-Per-step latency runs from the start of the round in which the step was
-runnable to the end of that step (the library measures it); a request that
-waits for memory or for the builder is not runnable and its waiting shows in
-its time to admission instead.
+Per-step latency runs from the moment the step became runnable (admission,
+or the end of the request's previous step) to its end; the library measures
+it.  A request that waits for the builder or for memory is not runnable yet:
+that wait shows in its time to admission.
 """
 import time
 
@@ -24,6 +24,7 @@ def run_stream(server, requests, time_scale=1.0, log=None, max_wall_s=None):
     t0 = time.perf_counter()
     i = 0
     rounds = 0
+    t_log = 0.0
     while True:
         now = time.perf_counter() - t0
         while i < len(pending) and pending[i].arrival_s * time_scale <= now:
@@ -35,13 +36,13 @@ def run_stream(server, requests, time_scale=1.0, log=None, max_wall_s=None):
             break
         if max_wall_s is not None and now > max_wall_s:
             raise TimeoutError(f"serving stream did not finish in {max_wall_s} s: {st.as_dict()}")
+        if log and now - t_log >= 2.0:
+            t_log = now
+            log(f"[serve] t={now:.1f}s submitted {i}: {st.as_dict()}")
         if st.resident or st.ready:
-            n = server.run_round()
+            server.run_round()  # admits, then waits up to a few ms for progress
             rounds += 1
-            if log and rounds % 10 == 0:
-                log(f"[serve] t={now:.1f}s round {rounds}: {st.as_dict()} steps this round {n}")
-            if n > 0:
-                continue
+            continue
         # nothing runnable: wait for the builder or the next arrival
         nxt = pending[i].arrival_s * time_scale - now if i < len(pending) else 0.002
         time.sleep(min(max(nxt, 0.0), 0.002))
