@@ -177,12 +177,26 @@ typedef struct {
   int32_t precision;   /* 0: FP64 throughout; 1: FP32 inner Krylov (JVP,
                           preconditioner, basis) with FP64 dot products,
                           Hessenberg, update and Newton residual            */
-  int32_t precond;     /* 0: point Jacobi; 1: node-block Jacobi             */
+  int32_t precond;     /* 0: point Jacobi; 1: node-block Jacobi; 2: octree
+                          geometric multigrid V-cycle (below)             */
   int32_t graphs;      /* 1: each GMRES restart cycle is captured once as a
                           HIP graph (per mesh, block, precision, restart
                           length and parameters) and replayed; 0: the same
                           kernels are launched one by one.  Results are
                           identical.                                        */
+  /* precond = 2: one V-cycle per preconditioner application.  The coarse
+   * meshes merge the finest sibling groups level by level (chns_mesh_coarsen)
+   * down to mg_levels meshes in all (0: until a mesh has at most 4096 nodes
+   * or is level 1).  Coarse operators are the same element loop on the
+   * coarse mesh with the state injected at its nodes; transfers are the
+   * trilinear prolongation and its transpose; smoothing is damped node-block
+   * Jacobi (mg_smooth sweeps before and after the coarse correction,
+   * mg_coarse_sweeps on the coarsest mesh).  The V-cycle is a fixed linear
+   * operator, as right preconditioning in GMRES requires. */
+  double mg_omega;          /* damping of the Jacobi sweeps, 0.6            */
+  int32_t mg_levels;        /* 0: automatic                                 */
+  int32_t mg_smooth;        /* 2                                            */
+  int32_t mg_coarse_sweeps; /* 8                                            */
 } chns_solver_opts;
 
 typedef struct {
@@ -219,23 +233,45 @@ int chns_launch_element_loop(chns_mesh* mesh, const chns_params* params, int blo
                              const double* U_new, const double* U_old, const void* dU, void* out,
                              int reps, void* stream, int64_t* grid);
 
+/* ------------------------------------------------ multigrid hierarchy ----
+ * Host-only helpers of the octree multigrid preconditioner (precond = 2 in
+ * chns_solver_opts); they also give the intergrid transfer between nested
+ * octree meshes (Sec. 4 "Intergrid transfer").
+ *
+ * chns_mesh_coarsen: the mesh with every sibling group of its finest level
+ * merged into the parent (level_max - 1).  The result is 2:1 balanced and
+ * each of its nodes is a node of `mesh`.  *coarse is released with
+ * chns_mesh_free. */
+int chns_mesh_coarsen(const chns_mesh* mesh, chns_mesh** coarse);
+/* Transfer between `fine` and `coarse` = chns_mesh_coarsen(fine).  Fine
+ * independent node i takes sum_k p_w[k] * value(coarse node p_idx[k]),
+ * k in [p_off[i], p_off[i+1]): the coarse trilinear field (through its
+ * hanging-node constraints) evaluated at node i; weights are dyadic and
+ * exact.  inj[j] is the fine node at coarse node j.  *nnz receives the
+ * number of entries; any array may be NULL (sizes: p_off n_fine + 1, p_idx
+ * and p_w nnz, inj n_coarse). */
+int chns_mesh_transfer(const chns_mesh* fine, const chns_mesh* coarse, int64_t* nnz, int32_t* p_off,
+                       int32_t* p_idx, double* p_w, int32_t* inj);
+
 /* ------------------------------------------------------------ serving ----
  * A request loop for many independent droplet / bubble problems of different
  * octree sizes.  Each request is (mesh spec, parameters, number of Crank-
  * Nicolson steps); its initial state is phi = phi0 at the nodes, mu = phi^3 -
  * phi, v = 0, p = 0.  A builder thread inside the server makes the host mesh,
- * the scatter plan and U^0 of queued requests while the GPU works.  Each
- * round (chns_server_run_round) first admits built requests in arrival order
- * while their exact device footprint (mesh arrays + solver workspace for the
- * server's options) fits in the HBM budget, then advances every resident
- * request by one step: each on its own stream and host thread, so their
- * element loops and Krylov kernels overlap on the device, with GMRES cycles
- * replayed as HIP graphs.  A request that has taken its last step leaves:
- * its final state is copied to host memory the server owns and its device
- * memory is freed before the next round admits more.  Requests never share
- * data, so a request's result does not depend on what else is resident.
- * One thread drives a server (submit, poll and run_round may be called from
- * one thread at a time). */
+ * the scatter plan and U^0 of queued requests while the GPU works.
+ * chns_server_run_round admits built requests in arrival order while their
+ * device footprint fits in the HBM budget (mesh arrays + solver workspace for
+ * the server's options, exact; with precond = 2 plus a bound for the coarse
+ * levels: the fine mesh's size again), a request that does not fit yet
+ * letting later, smaller ones pass.  An admitted request is uploaded on a
+ * stream of its own and a driver thread of its own runs its steps back to
+ * back, so the element loops and Krylov kernels of all residents overlap on
+ * the device and no request waits for another's step; GMRES cycles are
+ * replayed as HIP graphs.  After its last step a request's final state is
+ * copied to host memory the server owns and its device memory is freed,
+ * which lets the next round admit more.  Requests never share data, so a
+ * request's result does not depend on what else is resident.  One host
+ * thread drives a server (submit, poll and run_round). */
 typedef struct chns_server chns_server;
 
 enum {
@@ -263,7 +299,8 @@ typedef struct {
 
 /* Creates a server on the current device.  hbm_budget_bytes bounds the sum
  * of the footprints of resident requests; max_resident bounds their number
- * (1..64); opts apply to every step (graphs forced on). */
+ * (1..64); opts apply to every step (graphs forced on).  Up to max_resident
+ * driver threads run at once. */
 int chns_server_create(size_t hbm_budget_bytes, int max_resident, const chns_solver_opts* opts,
                        chns_server** out);
 /* Queues a request.  spec is copied (including explicit leaves); spec->phi0
@@ -275,14 +312,15 @@ int chns_server_submit(chns_server* srv, const chns_mesh_spec* spec, const chns_
 /* State of a request.  Any output may be NULL.  U_host_out (n_nodes*6
  * doubles, see info->n_nodes) is written once the request is DONE;
  * per_step (n_steps entries) and step_latency_ms (n_steps doubles: from the
- * start of the round that ran the step to the end of that step) receive the
- * steps taken so far. */
+ * moment the step became runnable, i.e. admission or the end of the
+ * request's previous step, to its end) receive the steps taken so far. */
 int chns_server_poll(chns_server* srv, int64_t ticket, chns_request_info* info,
                      double* U_host_out, chns_step_stats* per_step, double* step_latency_ms);
-/* One round: admission, then one step of every resident request.  The round
- * starts after the work already queued on `stream` and work queued on
- * `stream` afterwards runs after the round.  Returns the number of steps
- * taken (>= 0) or a negative status for a failure of the server itself;
+/* One scheduling round: joins the drivers of requests that have left,
+ * admits what fits (uploads start after the work already queued on
+ * `stream`), then waits up to 20 ms for progress (a step ending, a request
+ * leaving or becoming READY).  Returns the number of steps that ended during
+ * the call (>= 0), or a negative status for a failure of the server itself;
  * a failing request only moves to CHNS_REQ_FAILED. */
 int chns_server_run_round(chns_server* srv, void* stream);
 int chns_server_stats_get(chns_server* srv, chns_server_stats* out);

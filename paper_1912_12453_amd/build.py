@@ -6,13 +6,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchns.so")
-SOURCES = ["capi.hip", "mesh_host.cpp"]
+SOURCES = ["capi.hip", "mesh_host.cpp", "multigrid_host.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # FP64/FP32 atomic adds to device memory as single hardware instructions
-    "-munsafe-fp-atomics",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

@@ -65,7 +65,8 @@ class chns_solver_opts(C.Structure):
                 ("gmres_restart", C.c_int32), ("gmres_max_it", C.c_int32),
                 ("block_max_it", C.c_int32), ("block_min_it", C.c_int32),
                 ("precision", C.c_int32), ("precond", C.c_int32),
-                ("graphs", C.c_int32)]
+                ("graphs", C.c_int32), ("mg_omega", C.c_double), ("mg_levels", C.c_int32),
+                ("mg_smooth", C.c_int32), ("mg_coarse_sweeps", C.c_int32)]
 
 
 class chns_step_stats(C.Structure):
@@ -124,6 +125,8 @@ def lib():
                                 C.POINTER(chns_step_stats), vp]
         L.chns_launch_element_loop.argtypes = [vp, C.POINTER(chns_params), C.c_int, C.c_int, vp, vp,
                                                vp, vp, C.c_int, vp, C.POINTER(C.c_int64)]
+        L.chns_mesh_coarsen.argtypes = [vp, C.POINTER(vp)]
+        L.chns_mesh_transfer.argtypes = [vp, vp, C.POINTER(C.c_int64), vp, vp, vp, vp]
         L.chns_server_create.argtypes = [C.c_size_t, C.c_int, C.POINTER(chns_solver_opts), C.POINTER(vp)]
         L.chns_server_submit.argtypes = [vp, C.POINTER(chns_mesh_spec), C.POINTER(chns_params), C.c_int,
                                          C.POINTER(C.c_int64)]
@@ -153,10 +156,12 @@ def make_params(physics):
 
 def make_opts(newton_rtol=1e-8, newton_atol=1e-12, block_tol=1e-4, gmres_rtol=1e-7,
               newton_max_it_ch=20, newton_max_it_ns=40, gmres_restart=120, gmres_max_it=1000,
-              block_max_it=10, block_min_it=1, precision=0, precond=1, graphs=1):
+              block_max_it=10, block_min_it=1, precision=0, precond=1, graphs=1, mg_omega=0.6,
+              mg_levels=0, mg_smooth=2, mg_coarse_sweeps=8):
     return chns_solver_opts(newton_rtol, newton_atol, block_tol, gmres_rtol, newton_max_it_ch,
                             newton_max_it_ns, gmres_restart, gmres_max_it, block_max_it,
-                            block_min_it, precision, precond, graphs)
+                            block_min_it, precision, precond, graphs, mg_omega, mg_levels, mg_smooth,
+                            mg_coarse_sweeps)
 
 
 # ------------------------------------------------ C ABI, same names ------
@@ -407,6 +412,31 @@ class Mesh:
         bf = np.zeros(self.n_nodes, np.uint8)
         _check(lib().chns_mesh_nodes(self.h, xyz.ctypes.data, bf.ctypes.data))
         return xyz, bf
+
+    def coarsen(self):
+        """The mesh with its finest level merged into the parents (a Mesh)."""
+        h = C.c_void_p()
+        _check(lib().chns_mesh_coarsen(self.h, C.byref(h)))
+        m = Mesh.__new__(Mesh)
+        m.h = h
+        m._keep = None
+        m.stats = chns_mesh_info(h)
+        m.trees = self.trees
+        m.level_max = self.level_max - 1
+        return m
+
+    def transfer(self, coarse):
+        """(p_off, p_idx, p_w, inj): prolongation from `coarse` to this mesh
+        and the injection of coarse nodes (see chns_mesh_transfer)."""
+        nnz = C.c_int64()
+        _check(lib().chns_mesh_transfer(self.h, coarse.h, C.byref(nnz), None, None, None, None))
+        p_off = np.zeros(self.n_nodes + 1, np.int32)
+        p_idx = np.zeros(nnz.value, np.int32)
+        p_w = np.zeros(nnz.value, np.float64)
+        inj = np.zeros(coarse.n_nodes, np.int32)
+        _check(lib().chns_mesh_transfer(self.h, coarse.h, None, p_off.ctypes.data, p_idx.ctypes.data,
+                                        p_w.ctypes.data, inj.ctypes.data))
+        return p_off, p_idx, p_w, inj
 
     def upload(self, stream=None):
         chns_mesh_upload(self.h, stream)

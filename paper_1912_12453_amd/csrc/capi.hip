@@ -14,6 +14,7 @@
 #include "internal.hpp"
 #include "kernels.hip"
 #include "linalg.hpp"
+#include "multigrid.hpp"
 
 using namespace chns;
 
@@ -64,6 +65,8 @@ inline unsigned grid_stride(int64_t n, int block = 256, int cap = 2048) {
 // captured on.
 struct CycleGraph {
   int block = 0, tv = 0, mres = 0, seg = 0;
+  int precond = 0, mg_levels = 0, mg_smooth = 0, mg_coarse = 0;
+  double mg_omega = 0;
   dev::PhysView pv;
   hipGraphExec_t exec = nullptr;
 };
@@ -129,6 +132,19 @@ void free_workspace(Workspace& w) {
   w = Workspace();
 }
 
+// One mesh of the multigrid hierarchy.  Level 0 is the mesh itself; the
+// transfer arrays of level l connect it with level l + 1.
+struct MGLevel {
+  chns_mesh* mesh = nullptr;  // owned for levels >= 1
+  int64_t n = 0;
+  int32_t *p_off = nullptr, *p_idx = nullptr, *r_off = nullptr, *r_idx = nullptr, *inj = nullptr;
+  double *p_w = nullptr, *r_w = nullptr;
+  double *U1 = nullptr, *U0 = nullptr, *D = nullptr, *Di = nullptr;  // levels >= 1
+  float *U1f = nullptr, *U0f = nullptr, *Di32 = nullptr;
+  double *b64 = nullptr, *x64 = nullptr, *r64 = nullptr;
+  float *b32 = nullptr, *x32 = nullptr, *r32 = nullptr;
+};
+
 }  // namespace
 
 struct chns_mesh {
@@ -156,7 +172,14 @@ struct chns_mesh {
   double* h_sum = nullptr;
   int64_t device_bytes = 0;
   Workspace ws;
+  std::vector<MGLevel> mg;  // multigrid hierarchy, built on first use
+  int mg_key = -1;          // mg_levels it was built for
 };
+
+namespace {
+void free_mesh_locked(chns_mesh* m);  // frees everything; caller holds g_struct_mu
+void free_mg_locked(chns_mesh* m);    // frees the multigrid hierarchy; same
+}  // namespace
 
 namespace {
 
@@ -413,6 +436,101 @@ int launch_diagnostics(chns_mesh* m, const dev::PhysView& pv, const double* U, d
   return CHNS_OK;
 }
 
+// ------------------------------------------------------ multigrid setup ----
+constexpr int64_t kMGCoarsest = 4096;  // automatic depth stops at this many nodes
+
+int mg_alloc_level(MGLevel& L, bool coarse) {
+  std::lock_guard<std::mutex> lk(g_struct_mu);
+  const size_t n = (size_t)L.n;
+  int rc;
+  if ((rc = dalloc(&L.r64, 4 * n, nullptr)) || (rc = dalloc(&L.r32, 4 * n, nullptr))) return rc;
+  if (!coarse) return CHNS_OK;
+  if ((rc = dalloc(&L.U1, 6 * n, nullptr)) || (rc = dalloc(&L.U0, 6 * n, nullptr)) ||
+      (rc = dalloc(&L.U1f, 6 * n, nullptr)) || (rc = dalloc(&L.U0f, 6 * n, nullptr)) ||
+      (rc = dalloc(&L.D, 16 * n, nullptr)) || (rc = dalloc(&L.Di, 16 * n, nullptr)) ||
+      (rc = dalloc(&L.Di32, 16 * n, nullptr)) || (rc = dalloc(&L.b64, 4 * n, nullptr)) ||
+      (rc = dalloc(&L.x64, 4 * n, nullptr)) || (rc = dalloc(&L.b32, 4 * n, nullptr)) ||
+      (rc = dalloc(&L.x32, 4 * n, nullptr)))
+    return rc;
+  return CHNS_OK;
+}
+
+int mg_upload_transfer(MGLevel& F, const Transfer& t, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(g_struct_mu);
+    int rc;
+    if ((rc = dalloc(&F.p_off, t.p_off.size(), nullptr)) || (rc = dalloc(&F.p_idx, t.p_idx.size(), nullptr)) ||
+        (rc = dalloc(&F.p_w, t.p_w.size(), nullptr)) || (rc = dalloc(&F.r_off, t.r_off.size(), nullptr)) ||
+        (rc = dalloc(&F.r_idx, t.r_idx.size(), nullptr)) || (rc = dalloc(&F.r_w, t.r_w.size(), nullptr)) ||
+        (rc = dalloc(&F.inj, t.inj.size(), nullptr)))
+      return rc;
+  }
+  int rc;
+  if ((rc = h2d(F.p_off, t.p_off, s)) || (rc = h2d(F.p_idx, t.p_idx, s)) || (rc = h2d(F.p_w, t.p_w, s)) ||
+      (rc = h2d(F.r_off, t.r_off, s)) || (rc = h2d(F.r_idx, t.r_idx, s)) || (rc = h2d(F.r_w, t.r_w, s)) ||
+      (rc = h2d(F.inj, t.inj, s)))
+    return rc;
+  HIPCHK(hipStreamSynchronize(s));  // t is released by the caller
+  return CHNS_OK;
+}
+
+// Builds (once per requested depth) the coarse meshes, their device copies,
+// the transfers and the per-level buffers of the V-cycle.
+int build_mg(chns_mesh* m, int levels, hipStream_t s) {
+  if (m->mg_key == levels && !m->mg.empty()) return CHNS_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_struct_mu);
+    drop_graphs(m->ws);
+    free_mg_locked(m);
+  }
+  auto bail = [&](int rc) {
+    std::lock_guard<std::mutex> lk(g_struct_mu);
+    free_mg_locked(m);
+    return rc;
+  };
+  m->mg.resize(1);
+  m->mg[0].mesh = m;
+  m->mg[0].n = (int64_t)m->h.node_key.size();
+  int rc = mg_alloc_level(m->mg[0], false);
+  if (rc) return bail(rc);
+  const int maxl = levels > 0 ? levels : 64;
+  while ((int)m->mg.size() < maxl) {
+    const size_t f = m->mg.size() - 1;
+    const HostMesh& hf = m->mg[f].mesh->h;
+    if (hf.D < 1) break;
+    if (levels == 0 && ((int64_t)hf.node_key.size() <= kMGCoarsest || hf.D <= 1)) break;
+    chns_mesh* c = new (std::nothrow) chns_mesh();
+    if (!c) return bail(fail(CHNS_ENOMEM, "out of host memory"));
+    Transfer t;
+    std::string err;
+    try {
+      err = coarsen_host_mesh(hf, c->h);
+      if (err.empty()) err = build_transfer(hf, c->h, t);
+    } catch (const std::bad_alloc&) {
+      err = "out of host memory while building the multigrid hierarchy";
+    }
+    if (!err.empty()) {
+      delete c;
+      return bail(fail(CHNS_EINVAL, err));
+    }
+    if ((rc = upload(c, s)) || (rc = ensure_tbuf(c))) {
+      {
+        std::lock_guard<std::mutex> lk(g_struct_mu);
+        free_mesh_locked(c);
+      }
+      return bail(rc);
+    }
+    MGLevel C;
+    C.mesh = c;
+    C.n = (int64_t)c->h.node_key.size();
+    m->mg.push_back(C);
+    if ((rc = mg_alloc_level(m->mg.back(), true)) || (rc = mg_upload_transfer(m->mg[f], t, s)))
+      return bail(rc);
+  }
+  m->mg_key = levels;
+  return CHNS_OK;
+}
+
 // --------------------------------------------------------------- solver ----
 struct Solver {
   chns_mesh* m;
@@ -500,7 +618,11 @@ struct Solver {
   }
 
   template <class TV>
-  void precondition(int block, const TV* v, TV* z, const int* skip) {
+  int precondition(int block, const TV* v, TV* z, const int* skip, const double* U1, const double* U0) {
+    if (o.precond == 2) {
+      if (block == CHNS_BLOCK_CH) return vcycle<TV, 2>(block, 0, v, z, skip, U1, U0);
+      return vcycle<TV, 4>(block, 0, v, z, skip, U1, U0);
+    }
     const dim3 g(grid_stride(n)), b(256);
     if (block == CHNS_BLOCK_CH) {
       if (std::is_same<TV, double>::value)
@@ -513,6 +635,85 @@ struct Solver {
       else
         hipLaunchKernelGGL((dev::k_precond<4, TV, float>), g, b, 0, s, w.Di32, v, z, n, skip);
     }
+    HIPCHK(hipGetLastError());
+    return CHNS_OK;
+  }
+
+  // One V-cycle x = M^-1 b on level l of the hierarchy (x overwritten).
+  // Level 0 is the Krylov system itself: its operator is the Jacobian of
+  // (U1, U0) and its block inverse the Newton iteration's w.Di.
+  template <class TV, int NF>
+  int vcycle(int block, size_t l, const TV* b, TV* x, const int* skip, const double* U1, const double* U0) {
+    using TM = TV;  // the block inverse is used at the basis precision
+    MGLevel& L = m->mg[l];
+    chns_mesh* mm = L.mesh;
+    const int64_t nl = L.n, N = nl * NF;
+    const bool dbl = std::is_same<TV, double>::value;
+    TV* r = dbl ? (TV*)L.r64 : (TV*)L.r32;
+    const TM* Di = l == 0 ? (dbl ? (const TM*)w.Di : (const TM*)w.Di32) : (dbl ? (const TM*)L.Di : (const TM*)L.Di32);
+    const TV* S1 = l == 0 ? (dbl ? (const TV*)U1 : (const TV*)w.U1f) : (dbl ? (const TV*)L.U1 : (const TV*)L.U1f);
+    const TV* S0 = l == 0 ? (dbl ? (const TV*)U0 : (const TV*)w.U0f) : (dbl ? (const TV*)L.U0 : (const TV*)L.U0f);
+    const dim3 g(grid_stride(nl)), gs(grid_stride(N)), bl(256);
+    auto A = [&](const TV* in, TV* out) {
+      return launch_jvp<TV, TV, TV>(mm, pv, block, S1, S0, in, NF, 0, out, NF, 0, s, skip);
+    };
+    auto jac = [&](const TV* Ax) {
+      hipLaunchKernelGGL((dev::k_jacobi<NF, TV, TM>), g, bl, 0, s, Di, b, Ax, x, mm->d_bflags, block,
+                         o.mg_omega, nl, skip);
+    };
+    const bool coarsest = l + 1 == m->mg.size();
+    const int pre = coarsest ? o.mg_coarse_sweeps : o.mg_smooth;
+    int rc;
+    jac(nullptr);
+    for (int i = 1; i < pre; ++i) {
+      if ((rc = A(x, r))) return rc;
+      jac(r);
+    }
+    if (coarsest) {
+      HIPCHK(hipGetLastError());
+      return CHNS_OK;
+    }
+    if ((rc = A(x, r))) return rc;
+    hipLaunchKernelGGL(dev::k_rsub<TV>, gs, bl, 0, s, r, b, N, skip);
+    MGLevel& C = m->mg[l + 1];
+    TV* bc = dbl ? (TV*)C.b64 : (TV*)C.b32;
+    TV* xc = dbl ? (TV*)C.x64 : (TV*)C.x32;
+    hipLaunchKernelGGL((dev::k_restrict<NF, TV>), dim3(grid_stride(C.n)), bl, 0, s, r, mm->d_bflags, L.r_off,
+                       L.r_idx, L.r_w, C.n, C.mesh->d_bflags, block, bc, skip);
+    if ((rc = vcycle<TV, NF>(block, l + 1, bc, xc, skip, U1, U0))) return rc;
+    hipLaunchKernelGGL((dev::k_prolong_add<NF, TV>), g, bl, 0, s, x, mm->d_bflags, L.p_off, L.p_idx, L.p_w, nl,
+                       xc, block, skip);
+    for (int i = 0; i < o.mg_smooth; ++i) {
+      if ((rc = A(x, r))) return rc;
+      jac(r);
+    }
+    HIPCHK(hipGetLastError());
+    return CHNS_OK;
+  }
+
+  // Coarse-level states (injected from the level above) and node-block
+  // diagonals, once per Newton iteration.
+  int mg_setup(int block, const double* U1, const double* U0) {
+    const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+    for (size_t l = 1; l < m->mg.size(); ++l) {
+      MGLevel& F = m->mg[l - 1];
+      MGLevel& C = m->mg[l];
+      const double* s1 = l == 1 ? U1 : F.U1;
+      const double* s0 = l == 1 ? U0 : F.U0;
+      const dim3 g(grid_stride(C.n * 6)), b(256);
+      hipLaunchKernelGGL(dev::k_inject6, g, b, 0, s, s1, F.inj, C.n, C.U1, C.U1f);
+      hipLaunchKernelGGL(dev::k_inject6, g, b, 0, s, s0, F.inj, C.n, C.U0, C.U0f);
+      int rc = launch_diag(C.mesh, pv, block, C.U1, C.U0, C.D, s);
+      if (rc) return rc;
+      if (nf == 2)
+        hipLaunchKernelGGL(dev::k_invert_blocks<2>, dim3(grid_for(C.n)), b, 0, s, C.D, C.Di, C.Di32, C.n, 0,
+                           w.flag);
+      else
+        hipLaunchKernelGGL(dev::k_invert_blocks<4>, dim3(grid_for(C.n)), b, 0, s, C.D, C.Di, C.Di32, C.n, 0,
+                           w.flag);
+    }
+    HIPCHK(hipGetLastError());
+    return CHNS_OK;
   }
 
   // Right-preconditioned restarted GMRES(mres) with classical Gram-Schmidt
@@ -536,7 +737,7 @@ struct Solver {
       TV* Vk = V + (int64_t)k * N;
       TV* Zk = Z + (int64_t)k * N;
       const dim3 gp(w.nb_part, (k + dev::kDotTile) / dev::kDotTile);  // ceil((k + 1) / tile)
-      precondition<TV>(block, Vk, Zk, idle);
+      if ((rc = precondition<TV>(block, Vk, Zk, idle, U1, U0))) return rc;
       if ((rc = apply<TV>(block, Zk, wv, U1, U0, idle))) return rc;
       hipLaunchKernelGGL(dev::k_multidot<TV>, gp, b, 0, s, V, N, k + 1, wv, N, w.part, idle);
       hipLaunchKernelGGL(dev::k_finish_sum, dim3(k + 1), b, 0, s, w.part, w.nb_part, k + 1, C->h1, idle);
@@ -590,8 +791,9 @@ struct Solver {
     const int tv = std::is_same<TV, double>::value ? 0 : 1;
     hipGraphExec_t ex = nullptr;
     for (auto& g : w.graphs)
-      if (g.block == block && g.tv == tv && g.mres == mres && g.seg == seg &&
-          std::memcmp(&g.pv, &pv, sizeof(pv)) == 0) {
+      if (g.block == block && g.tv == tv && g.mres == mres && g.seg == seg && g.precond == o.precond &&
+          g.mg_levels == o.mg_levels && g.mg_smooth == o.mg_smooth && g.mg_coarse == o.mg_coarse_sweeps &&
+          g.mg_omega == o.mg_omega && std::memcmp(&g.pv, &pv, sizeof(pv)) == 0) {
         ex = g.exec;
         break;
       }
@@ -615,6 +817,11 @@ struct Solver {
       g.tv = tv;
       g.mres = mres;
       g.seg = seg;
+      g.precond = o.precond;
+      g.mg_levels = o.mg_levels;
+      g.mg_smooth = o.mg_smooth;
+      g.mg_coarse = o.mg_coarse_sweeps;
+      g.mg_omega = o.mg_omega;
       g.pv = pv;
       const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
@@ -703,6 +910,7 @@ struct Solver {
         hipLaunchKernelGGL(dev::k_invert_blocks<4>, dim3(grid_for(n)), dim3(256), 0, s, w.D, w.Di, w.Di32,
                            n, o.precond == 0 ? 1 : 0, w.flag);
       HIPCHK(hipGetLastError());
+      if (o.precond == 2 && (rc = mg_setup(block, U, w.Uk))) return rc;
       int its = 0;
       if (o.precision == 0) {
         hipLaunchKernelGGL((dev::k_scale<double, double>), dim3(grid_stride(N)), dim3(256), 0, s, w.b64,
@@ -743,6 +951,7 @@ struct Solver {
   int step(double* Uout, chns_step_stats* st) {
     int rc = ensure_workspace();
     if (rc) return rc;
+    if (o.precond == 2 && (rc = build_mg(m, o.mg_levels, s))) return rc;
     double* U = w.U1;
     HIPCHK(hipMemcpyAsync(U, Uout, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(w.Uk, Uout, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
@@ -790,7 +999,13 @@ int check_opts(const chns_solver_opts* opts) {
   if (opts->gmres_restart < 1 || opts->gmres_restart > dev::kMaxBasis - 1)
     return fail(CHNS_EINVAL, "gmres_restart must be in [1, " + std::to_string(dev::kMaxBasis - 1) + "]");
   if (opts->precision != 0 && opts->precision != 1) return fail(CHNS_EINVAL, "precision must be 0 or 1");
-  if (opts->precond != 0 && opts->precond != 1) return fail(CHNS_EINVAL, "precond must be 0 or 1");
+  if (opts->precond < 0 || opts->precond > 2) return fail(CHNS_EINVAL, "precond must be 0, 1 or 2");
+  if (opts->precond == 2) {
+    if (!(opts->mg_omega > 0.0 && opts->mg_omega < 2.0)) return fail(CHNS_EINVAL, "mg_omega must be in (0, 2)");
+    if (opts->mg_smooth < 1 || opts->mg_smooth > 16 || opts->mg_coarse_sweeps < 1 ||
+        opts->mg_coarse_sweeps > 256 || opts->mg_levels < 0 || opts->mg_levels > 16)
+      return fail(CHNS_EINVAL, "mg_smooth in [1, 16], mg_coarse_sweeps in [1, 256], mg_levels in [0, 16]");
+  }
   if (opts->block_max_it < 1 || opts->gmres_max_it < 1)
     return fail(CHNS_EINVAL, "iteration limits must be positive");
   if (opts->newton_max_it_ch < 0 || opts->newton_max_it_ns < 0 || opts->block_min_it < 0)
@@ -893,6 +1108,44 @@ int chns_mesh_nodes(const chns_mesh* m, double* xyz, uint8_t* bflags) {
   return CHNS_OK;
 }
 
+int chns_mesh_coarsen(const chns_mesh* m, chns_mesh** out) {
+  if (!m || !out) return fail(CHNS_EINVAL, "mesh and out must not be NULL");
+  *out = nullptr;
+  chns_mesh* c = new (std::nothrow) chns_mesh();
+  if (!c) return fail(CHNS_ENOMEM, "out of host memory");
+  std::string err;
+  try {
+    err = coarsen_host_mesh(m->h, c->h);
+  } catch (const std::bad_alloc&) {
+    err = "out of host memory while coarsening the mesh";
+  }
+  if (!err.empty()) {
+    delete c;
+    return fail(CHNS_EINVAL, err);
+  }
+  *out = c;
+  return CHNS_OK;
+}
+
+int chns_mesh_transfer(const chns_mesh* f, const chns_mesh* c, int64_t* nnz, int32_t* p_off,
+                       int32_t* p_idx, double* p_w, int32_t* inj) {
+  if (!f || !c) return fail(CHNS_EINVAL, "meshes must not be NULL");
+  Transfer t;
+  std::string err;
+  try {
+    err = build_transfer(f->h, c->h, t);
+  } catch (const std::bad_alloc&) {
+    err = "out of host memory while building the transfer";
+  }
+  if (!err.empty()) return fail(CHNS_EINVAL, err);
+  if (nnz) *nnz = (int64_t)t.p_idx.size();
+  if (p_off) std::memcpy(p_off, t.p_off.data(), t.p_off.size() * sizeof(int32_t));
+  if (p_idx) std::memcpy(p_idx, t.p_idx.data(), t.p_idx.size() * sizeof(int32_t));
+  if (p_w) std::memcpy(p_w, t.p_w.data(), t.p_w.size() * sizeof(double));
+  if (inj) std::memcpy(inj, t.inj.data(), t.inj.size() * sizeof(int32_t));
+  return CHNS_OK;
+}
+
 int chns_mesh_upload(chns_mesh* m, void* stream) {
   if (!m) return fail(CHNS_EINVAL, "mesh is NULL");
   return upload(m, (hipStream_t)stream);
@@ -901,6 +1154,29 @@ int chns_mesh_upload(chns_mesh* m, void* stream) {
 int chns_mesh_free(chns_mesh* m) {
   if (!m) return CHNS_OK;
   std::lock_guard<std::mutex> lk(g_struct_mu);
+  free_mesh_locked(m);
+  return CHNS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+void free_mg_locked(chns_mesh* m) {
+  for (size_t l = 0; l < m->mg.size(); ++l) {
+    MGLevel& L = m->mg[l];
+    void* ptrs[] = {L.p_off, L.p_idx, L.r_off, L.r_idx, L.inj, L.p_w, L.r_w, L.U1, L.U0, L.D, L.Di,
+                    L.U1f, L.U0f, L.Di32, L.b64, L.x64, L.r64, L.b32, L.x32, L.r32};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    if (l > 0 && L.mesh) free_mesh_locked(L.mesh);
+  }
+  m->mg.clear();
+  m->mg_key = -1;
+}
+
+void free_mesh_locked(chns_mesh* m) {
+  free_mg_locked(m);
   free_workspace(m->ws);
   void* ptrs[] = {m->d_elem, m->d_hoff, m->d_hids, m->d_anchor, m->d_level,
                   m->d_hw, m->d_hw32, m->d_flag, m->d_part, m->d_sum,
@@ -912,8 +1188,11 @@ int chns_mesh_free(chns_mesh* m) {
   if (m->h_flag) (void)hipHostFree(m->h_flag);
   if (m->h_sum) (void)hipHostFree(m->h_sum);
   delete m;
-  return CHNS_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int chns_residual(chns_mesh* m, const chns_params* params, int block, const double* U_new,
                   const double* U_old, double* R, void* stream) {

@@ -84,4 +84,16 @@ struct ScatterPlan {
 };
 std::string build_scatter_plan(const HostMesh& m, ScatterPlan& out);
 
+// Multigrid hierarchy (multigrid_host.cpp).  coarsen_host_mesh merges the
+// finest level of f into its parents; build_transfer gives the prolongation
+// P (fine independent node i <- sum_k p_w[k] * coarse node p_idx[k], k in
+// [p_off[i], p_off[i+1])), its transpose R (coarse node j <- fine nodes,
+// ascending), and the injection inj[j] = the fine node at coarse node j.
+std::string coarsen_host_mesh(const HostMesh& f, HostMesh& c);
+struct Transfer {
+  std::vector<int32_t> p_off, p_idx, r_off, r_idx, inj;
+  std::vector<double> p_w, r_w;
+};
+std::string build_transfer(const HostMesh& f, const HostMesh& c, Transfer& out);
+
 }  // namespace chns

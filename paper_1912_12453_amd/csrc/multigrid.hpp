@@ -1,0 +1,112 @@
+// Device kernels of the octree multigrid V-cycle: state injection, residual
+// restriction (P^T), correction prolongation (P) and damped node-block
+// Jacobi smoothing.  Transfers are gathers over host-built CSR lists, so
+// every result is summed in a fixed order.  Rows that the Navier-Stokes
+// block holds by Dirichlet conditions (velocity on the boundary, pressure at
+// the pinned node) take no coarse-grid correction and are smoothed exactly.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace chns {
+namespace dev {
+
+__device__ __forceinline__ bool dirichlet_row(uint8_t b, int block, int f) {
+  return block == 1 && ((f < 3 && (b & 1)) || (f == 3 && (b & 2)));
+}
+
+// Uc[j] = Uf[inj[j]] for the 6 fields (and an FP32 copy when Uc32 is set)
+__global__ void k_inject6(const double* __restrict__ Uf, const int32_t* __restrict__ inj, int64_t nc,
+                          double* __restrict__ Uc, float* __restrict__ Uc32) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nc * 6;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / 6;
+    const int f = (int)(t - j * 6);
+    const double v = Uf[(int64_t)inj[j] * 6 + f];
+    Uc[t] = v;
+    if (Uc32) Uc32[t] = (float)v;
+  }
+}
+
+// rc[j] = sum over the fine nodes i of node j's list of w * rf[i], Dirichlet
+// rows (fine and coarse) excluded
+template <int NF, class TV>
+__global__ void k_restrict(const TV* __restrict__ rf, const uint8_t* __restrict__ bf_f,
+                           const int32_t* __restrict__ r_off, const int32_t* __restrict__ r_idx,
+                           const double* __restrict__ r_w, int64_t nc, const uint8_t* __restrict__ bf_c,
+                           int block, TV* __restrict__ rc, const int* skip) {
+  if (skip && *skip) return;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nc;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    double acc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] = 0;
+    for (int k = r_off[j]; k < r_off[j + 1]; ++k) {
+      const int64_t i = r_idx[k];
+      const double w = r_w[k];
+      const uint8_t b = bf_f[i];
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        if (!dirichlet_row(b, block, f)) acc[f] += w * (double)rf[i * NF + f];
+    }
+    const uint8_t b = bf_c[j];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) rc[j * NF + f] = dirichlet_row(b, block, f) ? (TV)0 : (TV)acc[f];
+  }
+}
+
+// xf[i] += sum over coarse nodes j of node i's list of w * ec[j], Dirichlet
+// rows untouched
+template <int NF, class TV>
+__global__ void k_prolong_add(TV* __restrict__ xf, const uint8_t* __restrict__ bf_f,
+                              const int32_t* __restrict__ p_off, const int32_t* __restrict__ p_idx,
+                              const double* __restrict__ p_w, int64_t nfn, const TV* __restrict__ ec,
+                              int block, const int* skip) {
+  if (skip && *skip) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nfn;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double acc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] = 0;
+    for (int k = p_off[i]; k < p_off[i + 1]; ++k) {
+      const int64_t j = p_idx[k];
+      const double w = p_w[k];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) acc[f] += w * (double)ec[j * NF + f];
+    }
+    const uint8_t b = bf_f[i];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+      if (!dirichlet_row(b, block, f)) xf[i * NF + f] = (TV)((double)xf[i * NF + f] + acc[f]);
+  }
+}
+
+// Damped node-block Jacobi: x = omega Di b (Ax == nullptr, x starts at 0),
+// else x += omega Di (b - Ax).  Dirichlet rows use omega = 1: their rows of
+// the operator and of the diagonal block are identity rows, so they are then
+// solved exactly.
+template <int NF, class TV, class TM>
+__global__ void k_jacobi(const TM* __restrict__ Di, const TV* __restrict__ b, const TV* __restrict__ Ax,
+                         TV* __restrict__ x, const uint8_t* __restrict__ bf, int block, double omega,
+                         int64_t n, const int* skip) {
+  if (skip && *skip) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    TM r[NF];
+#pragma unroll
+    for (int c = 0; c < NF; ++c) r[c] = Ax ? (TM)b[i * NF + c] - (TM)Ax[i * NF + c] : (TM)b[i * NF + c];
+    const uint8_t bb = bf[i];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      TM s = 0;
+#pragma unroll
+      for (int c = 0; c < NF; ++c) s += Di[i * NF * NF + f * NF + c] * r[c];
+      const TM om = dirichlet_row(bb, block, f) ? (TM)1 : (TM)omega;
+      x[i * NF + f] = Ax ? (TV)((TM)x[i * NF + f] + om * s) : (TV)(om * s);
+    }
+  }
+}
+
+}  // namespace dev
+}  // namespace chns

@@ -138,6 +138,8 @@ void build_request(chns_server* S, Request* r) {
     r->n_leaves = (int64_t)m->h.leaf_key.size();
     r->n_nodes = (int64_t)m->h.node_key.size();
     r->footprint = mesh_footprint(m) + workspace_footprint((int64_t)m->h.node_key.size(), S->opts);
+    if (S->opts.precond == 2)  // coarse levels: at most the fine level's size again, plus V-cycle buffers
+      r->footprint += mesh_footprint(m) + 656 * (int64_t)m->h.node_key.size();
     if (r->footprint > S->budget) err = "request needs " + std::to_string(r->footprint) +
                                         " device bytes, above the server budget";
   }
