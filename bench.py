@@ -19,8 +19,9 @@ events on the stream it is launched on.  The CPU baseline is the FP64 oracle
 (test infrastructure) computing the same 6-DoF JVP on the same mesh and state.
 
 The cn_steps object times full Crank-Nicolson steps (block iteration,
-Newton to 1e-8, GMRES(120) with node-block Jacobi) on the 16^3 drop, FP64
-and mixed precision.
+Newton to 1e-8, GMRES(120) preconditioned by the octree multigrid V-cycle),
+FP64 and mixed precision, on the 16^3 drop and on the workload itself
+(bubble: v = 0 start), with the mixed trajectory's error against FP64.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
                        [--workload bubble_l9|bubble_l8|drop16|rt_l10] [--no-cpu-baseline]
@@ -54,23 +55,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cn_steps(chns, W, torch, dev, nsteps):
-    """Consecutive Crank-Nicolson steps of the 16^3 drop (4913 nodes) to the
-    1e-8 relative Newton residual, FP64 and mixed precision from the same
-    U^0: steps/s, p50/p99 step latency, solver counts, energy trace."""
+def cn_steps(chns, W, torch, dev, name, nsteps, precond):
+    """Consecutive Crank-Nicolson steps to the 1e-8 relative Newton residual,
+    FP64 and mixed precision from the same U^0: steps/s, p50/p99 step
+    latency, solver counts, energy trace, mass drift, and the field error of
+    the mixed-precision trajectory against the FP64 one."""
     import numpy as np
-    w = W.drop16()
+    w = W.by_name(name)
     mesh = chns.Mesh.from_spec(w.mesh)
     mesh.upload()
     xyz, bf = mesh.nodes()
-    U0 = W.initial_state(xyz, W.sphere_phi((0.5, 0.5, 0.5), 0.25, w.physics.Cn), bf,
-                         phi_noise=1e-3, seed=0)
+    if name.startswith("drop"):  # heavy drop at rest, phi perturbed (seed 0)
+        U0 = W.initial_state(xyz, W.sphere_phi((0.5, 0.5, 0.5), 0.25, w.physics.Cn), bf,
+                             phi_noise=1e-3, seed=0)
+    else:  # physical start: v = 0, p = 0
+        U0 = W.initial_state(xyz, w.mesh.phi0, bf)
     p = chns.make_params(w.physics)
-    out = {"workload": "drop16", "nodes": mesh.n_nodes, "newton_rtol": 1e-8, "steps": nsteps}
-    for prec, name, grtol in ((0, "fp64", 1e-7), (1, "mixed", 1e-5)):
-        opts = chns.make_opts(precision=prec, gmres_rtol=grtol, gmres_restart=120)
+    out = {"workload": name, "nodes": mesh.n_nodes, "leaves": mesh.n_leaves, "newton_rtol": 1e-8,
+           "precond": {1: "node-block Jacobi", 2: "octree multigrid V-cycle"}[precond], "steps": nsteps}
+    finals = {}
+    for prec, pname, grtol in ((0, "fp64", 1e-7), (1, "mixed", 1e-5)):
+        opts = chns.make_opts(precision=prec, gmres_rtol=grtol, gmres_restart=120, precond=precond)
         U = torch.tensor(U0, device=dev)
-        rc, st = mesh.step(p, opts, U)  # warm-up: workspace and graph capture
+        rc, st = mesh.step(p, opts, U)  # warm-up: workspace, hierarchy and graph capture
         U.copy_(torch.tensor(U0, device=dev))
         mass0, e0 = mesh.diagnostics(p, U)
         torch.cuda.synchronize()
@@ -88,22 +95,29 @@ def cn_steps(chns, W, torch, dev, nsteps):
             rel = max(rel, st.rel_res[0])
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        out[name] = {"steps_per_s": round(nsteps / t, 3),
-                     "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                     "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                     "all_converged": bool(conv), "max_rel_res_ch": rel,
-                     "gmres_its_per_step": [g / nsteps for g in gits],
-                     "energy_non_increasing": bool(all(b <= a for a, b in zip(energy, energy[1:]))),
-                     "mass_drift": st.mass - mass0}
-        log(f"[bench] cn steps {name}: {out[name]}")
+        finals[pname] = U.cpu().numpy()
+        out[pname] = {"steps_per_s": round(nsteps / t, 3),
+                      "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                      "all_converged": bool(conv), "max_rel_res_ch": rel,
+                      "gmres_its_per_step": [g / nsteps for g in gits],
+                      "energy_non_increasing": bool(all(b <= a for a, b in zip(energy, energy[1:]))),
+                      "energy": [round(e, 12) for e in energy],
+                      "mass_drift": st.mass - mass0}
+        log(f"[bench] cn steps {name} {pname}: {out[pname]}")
     out["mixed_speedup"] = round(out["mixed"]["steps_per_s"] / out["fp64"]["steps_per_s"], 3)
+    a, b = finals["mixed"], finals["fp64"]
+    out["mixed_vs_fp64_rel_l2"] = {f: float(np.linalg.norm(a[:, i] - b[:, i]) / max(np.linalg.norm(b[:, i]), 1e-300))
+                                   for i, f in enumerate(("phi", "mu", "u", "v", "w", "p"))}
+    mesh.close()
     return out
 
 
 def serving_main(args):
     """Config of the serving stream: Poisson arrivals of independent droplet /
-    bubble problems (workloads.serving_stream), mixed precision, admitted by
-    footprint into an HBM budget.  Prints one JSON line."""
+    bubble problems (workloads.serving_stream), mixed precision with the
+    multigrid-preconditioned solver at the default tolerances (Newton 1e-8),
+    admitted by footprint into an HBM budget.  Prints one JSON line."""
     import torch
 
     from paper_1912_12453_amd import chns, serving
@@ -113,9 +127,11 @@ def serving_main(args):
     reqs = W.serving_stream(n_requests=args.serve_requests, rate_hz=20.0, seed=4,
                             level_range=(args.serve_level_min, args.serve_level_max),
                             steps=args.serve_steps)
-    opts = chns.make_opts(precision=1, gmres_rtol=1e-5, gmres_restart=60,
-                          gmres_max_it=args.serve_gmres_max_it, newton_max_it_ch=4,
-                          newton_max_it_ns=4, block_max_it=2)
+    # per-step work is capped so that a hard request cannot hold the device
+    # for minutes: such steps end NOT_CONVERGED and are counted as such
+    opts = chns.make_opts(precision=1, gmres_rtol=1e-5, gmres_restart=60, precond=2,
+                          gmres_max_it=args.serve_gmres_max_it, newton_max_it_ch=8,
+                          newton_max_it_ns=8, block_max_it=3)
     srv = chns.Server(args.serve_budget_gib << 30, args.serve_max_resident, opts)
     summ, per = serving.run_stream(srv, reqs, log=log, max_wall_s=args.serve_max_wall_s)
     srv.close()
@@ -131,7 +147,11 @@ def serving_main(args):
                       "gmres_max_it": args.serve_gmres_max_it},
            "serving": summ,
            "largest_requests": sorted(({"nodes": p["nodes"], "latency_ms": [round(x, 1) for x in p["latency_ms"]]}
-                                       for p in per), key=lambda d: -d["nodes"])[:3]}
+                                       for p in per), key=lambda d: -d["nodes"])[:3],
+           "slowest_requests": sorted(({"nodes": p["nodes"], "rho_minus": p["rho_minus"], "kind": p["kind"],
+                                        "latency_ms": [round(x, 1) for x in p["latency_ms"]],
+                                        "converged": p["converged"]}
+                                       for p in per), key=lambda d: -max(d["latency_ms"] or [0]))[:3]}
     print(json.dumps(res), flush=True)
 
 
@@ -146,6 +166,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--cn-steps", type=int, default=10)
+    ap.add_argument("--cn-steps-large", type=int, default=5)
     ap.add_argument("--no-steps", action="store_true")
     ap.add_argument("--serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
@@ -276,7 +297,10 @@ def main():
             "algorithmic_GBps": round(ach_gbs, 1), "hbm_frac": round(ach_gbs / PEAK_HBM_GBS, 4)}
 
     # ---- full Crank-Nicolson steps at the 1e-8 Newton tolerance, FP64 vs mixed
-    steps = None if args.no_steps else cn_steps(chns, W, torch, dev, args.cn_steps)
+    steps = None
+    if not args.no_steps:
+        steps = {"drop16": cn_steps(chns, W, torch, dev, "drop16", args.cn_steps, 2),
+                 name: cn_steps(chns, W, torch, dev, name, args.cn_steps_large, 2)}
 
     # ---- CPU baseline: the oracle's 6-DoF JVP on the same mesh and state
     cpu = None

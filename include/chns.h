@@ -44,7 +44,8 @@ enum {
   CHNS_EHIP = -3,         /* a HIP runtime call failed                            */
   CHNS_ENONFINITE = -4,   /* a NaN or Inf appeared in a residual norm             */
   CHNS_ETAU = -5,         /* the tau_m bracket of Sec. 3.4 was not positive       */
-  CHNS_ENODEV = -6        /* no usable gfx950 device                              */
+  CHNS_ENODEV = -6,       /* no usable gfx950 device                              */
+  CHNS_ECANCELED = -7     /* a server step stopped because the server is destroyed */
 };
 
 /* The two sub-problems of the block iteration (Sec. 3, Fig. 1). */

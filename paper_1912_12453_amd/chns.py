@@ -24,6 +24,7 @@ CHNS_EHIP = -3
 CHNS_ENONFINITE = -4
 CHNS_ETAU = -5
 CHNS_ENODEV = -6
+CHNS_ECANCELED = -7
 CHNS_BLOCK_CH = 0
 CHNS_BLOCK_NS = 1
 CHNS_F64 = 0
@@ -102,9 +103,16 @@ _lib = None
 
 
 def lib():
-    """Loads libchns.so; raises if it has not been built."""
+    """Loads libchns.so; raises if it has not been built.
+
+    torch is imported first: its ROCm libraries are then already in the
+    process when libchns.so is loaded, so libchns binds to the same HIP
+    runtime (libamdhip64.so.7) as torch and torch's device pointers and
+    stream handles are valid inside the library.  Loading libchns first
+    would bring a second HIP runtime into the process."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (see above)
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "or python -m paper_1912_12453_amd.build")

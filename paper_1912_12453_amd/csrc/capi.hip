@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -533,6 +534,7 @@ int build_mg(chns_mesh* m, int levels, hipStream_t s) {
 
 // --------------------------------------------------------------- solver ----
 struct Solver {
+  const std::atomic<bool>* cancel = nullptr;  // set by a server that is shutting down
   chns_mesh* m;
   dev::PhysView pv;
   chns_solver_opts o;
@@ -541,6 +543,8 @@ struct Solver {
   int64_t n;
   Solver(chns_mesh* m_, const dev::PhysView& pv_, const chns_solver_opts& o_, hipStream_t s_)
       : m(m_), pv(pv_), o(o_), s(s_), w(m_->ws), n((int64_t)m_->h.node_key.size()) {}
+
+  bool cancelled() const { return cancel && cancel->load(std::memory_order_relaxed); }
 
   int ensure_workspace() {
     std::lock_guard<std::mutex> lk(g_struct_mu);
@@ -870,6 +874,7 @@ struct Solver {
       if ((rc = enqueue_part<TV>(block, V, Z, wv, bvec, U1, U0, mres, -1))) return rc;
       if ((rc = read_ctl())) return rc;
       if (w.hctl[1]) break;
+      if (cancelled()) return fail(CHNS_ECANCELED, "step cancelled");
     }
     *its = w.hctl[2];
     return CHNS_OK;
@@ -901,6 +906,7 @@ struct Solver {
         break;
       }
       if (*nits >= max_it) break;
+      if (cancelled()) return fail(CHNS_ECANCELED, "step cancelled");
       if ((rc = launch_diag(m, pv, block, U, w.Uk, w.D, s))) return rc;
       hipLaunchKernelGGL(dev::k_fill<int>, dim3(1), dim3(64), 0, s, w.flag, (int64_t)1, 0);
       if (nf == 2)

@@ -83,6 +83,7 @@ struct chns_server {
   std::condition_variable cv;        // builder work
   std::condition_variable progress;  // a step ended, a request left or became READY
   bool stop = false;
+  std::atomic<bool> cancel{false};  // running steps stop at their next check
   std::deque<Request*> build_queue;
   std::vector<Request*> ready;     // arrival order
   std::vector<Request*> resident;
@@ -225,6 +226,7 @@ void drive(chns_server* S, Request* r) {
     std::memset(&st, 0, sizeof(st));
     const auto ts = Clock::now();
     Solver sol(r->mesh, r->pv, S->opts, r->stream);
+    sol.cancel = &S->cancel;
     const int src = sol.step(r->dU, &st);
     const auto te = Clock::now();
     if (src < 0) {
@@ -453,10 +455,11 @@ int chns_server_destroy(chns_server* S) {
     std::lock_guard<std::mutex> lk(S->mu);
     S->stop = true;
   }
+  S->cancel.store(true);
   S->cv.notify_all();
   S->progress.notify_all();
   if (S->builder.joinable()) S->builder.join();
-  // drivers stop before their next step; the one in progress completes
+  // drivers stop at their next Newton iteration or GMRES cycle
   for (auto& kv : S->all)
     if (kv.second->driver.joinable()) kv.second->driver.join();
   for (auto& kv : S->all) free_request(kv.second.get());

@@ -35,7 +35,9 @@ def run_stream(server, requests, time_scale=1.0, log=None, max_wall_s=None):
         if st.done + st.failed == len(pending):
             break
         if max_wall_s is not None and now > max_wall_s:
-            raise TimeoutError(f"serving stream did not finish in {max_wall_s} s: {st.as_dict()}")
+            if log:
+                log(f"[serve] wall-clock limit {max_wall_s} s reached: {st.as_dict()}")
+            break
         if log and now - t_log >= 2.0:
             t_log = now
             log(f"[serve] t={now:.1f}s submitted {i}: {st.as_dict()}")
@@ -53,9 +55,12 @@ def run_stream(server, requests, time_scale=1.0, log=None, max_wall_s=None):
     conv = 0
     nsteps = 0
     for r in pending:
+        if r.rid not in tickets:
+            continue
         t, t_arr = tickets[r.rid]
         info, U, stats, la = server.poll(t, steps=True)
         per.append({"rid": r.rid, "kind": r.kind, "state": int(info.state), "nodes": int(info.n_nodes),
+                    "rho_minus": r.workload.physics.rho_minus,
                     "steps": int(info.steps_done), "arrival_s": t_arr,
                     "admit_wait_ms": float(info.t_admit_ms - info.t_submit_ms) if info.t_admit_ms else None,
                     "latency_ms": la, "converged": [bool(s.converged) for s in stats],
@@ -66,6 +71,7 @@ def run_stream(server, requests, time_scale=1.0, log=None, max_wall_s=None):
         nsteps += len(stats)
     sst = server.stats().as_dict()
     summary = {"requests": len(pending), "done": sst["done"], "failed": sst["failed"],
+               "unfinished": len(pending) - sst["done"] - sst["failed"],
                "rounds": sst["rounds"], "steps": nsteps, "wall_s": round(wall, 3),
                "steps_per_s": round(nsteps / wall, 3),
                "dof_steps_per_s": round(dof_steps / wall, 1),

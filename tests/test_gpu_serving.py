@@ -40,8 +40,8 @@ REQS = [
 ]
 
 
-def opts(chns):
-    return chns.make_opts(precision=1, gmres_rtol=1e-5, gmres_restart=60)
+def opts(chns, precond=1):
+    return chns.make_opts(precision=1, gmres_rtol=1e-5, gmres_restart=60, precond=precond)
 
 
 def drain(server, max_s=120.0):
@@ -56,19 +56,20 @@ def drain(server, max_s=120.0):
     raise AssertionError("server did not drain")
 
 
-def test_alone_equals_mix(torch, chns):
+@pytest.mark.parametrize("precond", [1, 2])
+def test_alone_equals_mix(torch, chns, precond):
     """Request 0 run alone, and run while requests 1 and 2 arrive and leave
     around it, gives bit-identical final states and solver counts; both equal
     chns_step applied n_steps times to the same mesh and U^0."""
-    print("case serving alone-vs-mix", flush=True)
-    alone = chns.Server(1 << 34, 1, opts(chns))
+    print(f"case serving alone-vs-mix precond={precond}", flush=True)
+    alone = chns.Server(1 << 34, 1, opts(chns, precond))
     t = alone.submit(REQS[0].mesh, REQS[0].physics, REQS[0].steps)
     drain(alone)
     ia, Ua, sa, _ = alone.poll(t, state=True, steps=True)
     assert ia.state == chns.CHNS_REQ_DONE, ia.status
     alone.close()
 
-    mix = chns.Server(1 << 34, 3, opts(chns))
+    mix = chns.Server(1 << 34, 3, opts(chns, precond))
     t1 = mix.submit(REQS[1].mesh, REQS[1].physics, REQS[1].steps)
     t0 = mix.submit(REQS[0].mesh, REQS[0].physics, REQS[0].steps)
     # let the first round start with what is built, then add the third
@@ -96,7 +97,7 @@ def test_alone_equals_mix(torch, chns):
     U[:, 1] = phi * phi * phi - phi
     d = torch.tensor(U, device="cuda:0")
     p = chns.make_params(REQS[0].physics)
-    o = opts(chns)
+    o = opts(chns, precond)
     for _ in range(REQS[0].steps):
         rc, st = m.step(p, o, d)
         assert rc in (chns.CHNS_OK, chns.CHNS_NOT_CONVERGED)

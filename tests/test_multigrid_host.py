@@ -17,18 +17,21 @@ def trilinear(xyz):
     return 1.0 + 2.0 * x - 3.0 * y + 0.5 * z + 1.25 * x * y - 0.75 * y * z + 0.5 * x * z + 0.25 * x * y * z
 
 
-def meshes():
-    yield "random", chns.Mesh(trees=(1, 1, 1), level_min=1, level_max=4,
-                              leaves=W.random_leaves((1, 1, 1), 4, seed=3, p_split=0.45, level_min=1))
-    yield "brick", chns.Mesh(trees=(2, 1, 1), level_min=1, level_max=3,
-                             leaves=W.random_leaves((2, 1, 1), 3, seed=5, p_split=0.5, level_min=1))
-    w = W.bubble(level_max=6, level_min=3)
-    yield "bubble6", chns.Mesh.from_spec(w.mesh)
-    yield "uniform", chns.Mesh(trees=(1, 1, 1), level_min=3, level_max=3)
+def make_mesh(name):
+    if name == "random":
+        return chns.Mesh(trees=(1, 1, 1), level_min=1, level_max=4,
+                         leaves=W.random_leaves((1, 1, 1), 4, seed=3, p_split=0.45, level_min=1))
+    if name == "brick":
+        return chns.Mesh(trees=(2, 1, 1), level_min=1, level_max=3,
+                         leaves=W.random_leaves((2, 1, 1), 3, seed=5, p_split=0.5, level_min=1))
+    if name == "bubble6":
+        return chns.Mesh.from_spec(W.bubble(level_max=6, level_min=3).mesh)
+    return chns.Mesh(trees=(1, 1, 1), level_min=3, level_max=3)
 
 
-@pytest.mark.parametrize("name,fine", list(meshes()), ids=lambda v: v if isinstance(v, str) else "")
-def test_coarsening_and_transfer(name, fine):
+@pytest.mark.parametrize("name", ["random", "brick", "bubble6", "uniform"])
+def test_coarsening_and_transfer(name):
+    fine = make_mesh(name)
     coarse = fine.coarsen()
     fa, ca = fine.arrays(), coarse.arrays()
     D = fine.level_max
