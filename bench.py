@@ -55,7 +55,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cn_steps(chns, W, torch, dev, name, nsteps, precond):
+def cn_steps(chns, W, torch, dev, name, nsteps, precond, restart=120):
     """Consecutive Crank-Nicolson steps to the 1e-8 relative Newton residual,
     FP64 and mixed precision from the same U^0: steps/s, p50/p99 step
     latency, solver counts, energy trace, mass drift, and the field error of
@@ -72,12 +72,14 @@ def cn_steps(chns, W, torch, dev, name, nsteps, precond):
         U0 = W.initial_state(xyz, w.mesh.phi0, bf)
     p = chns.make_params(w.physics)
     out = {"workload": name, "nodes": mesh.n_nodes, "leaves": mesh.n_leaves, "newton_rtol": 1e-8,
+           "gmres_restart": restart,
            "precond": {1: "node-block Jacobi", 2: "octree multigrid V-cycle"}[precond], "steps": nsteps}
     finals = {}
     for prec, pname, grtol in ((0, "fp64", 1e-7), (1, "mixed", 1e-5)):
-        opts = chns.make_opts(precision=prec, gmres_rtol=grtol, gmres_restart=120, precond=precond)
+        opts = chns.make_opts(precision=prec, gmres_rtol=grtol, gmres_restart=restart, precond=precond)
         U = torch.tensor(U0, device=dev)
         rc, st = mesh.step(p, opts, U)  # warm-up: workspace, hierarchy and graph capture
+        log(f"[bench] cn warm-up {name} {pname}: rc {rc}, gmres {list(st.gmres_its)}")
         U.copy_(torch.tensor(U0, device=dev))
         mass0, e0 = mesh.diagnostics(p, U)
         torch.cuda.synchronize()
@@ -90,6 +92,7 @@ def cn_steps(chns, W, torch, dev, name, nsteps, precond):
             if rc not in (chns.CHNS_OK, chns.CHNS_NOT_CONVERGED):
                 raise RuntimeError(f"step failed with {rc}")
             conv = conv and rc == chns.CHNS_OK
+            log(f"[bench] cn step {name} {pname}: {lat[-1]:.0f} ms, gmres {list(st.gmres_its)}, rc {rc}")
             energy.append(st.energy)
             gits = [gits[0] + st.gmres_its[0], gits[1] + st.gmres_its[1]]
             rel = max(rel, st.rel_res[0])
@@ -167,6 +170,7 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--cn-steps", type=int, default=10)
     ap.add_argument("--cn-steps-large", type=int, default=5)
+    ap.add_argument("--cn-restart", type=int, default=120)
     ap.add_argument("--no-steps", action="store_true")
     ap.add_argument("--serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
@@ -300,7 +304,7 @@ def main():
     steps = None
     if not args.no_steps:
         steps = {"drop16": cn_steps(chns, W, torch, dev, "drop16", args.cn_steps, 2),
-                 name: cn_steps(chns, W, torch, dev, name, args.cn_steps_large, 2)}
+                 name: cn_steps(chns, W, torch, dev, name, args.cn_steps_large, 2, args.cn_restart)}
 
     # ---- CPU baseline: the oracle's 6-DoF JVP on the same mesh and state
     cpu = None
