@@ -155,6 +155,23 @@ int chns_jvp(chns_mesh* mesh, const chns_params* params, int block, const double
 /* Node-block diagonal of the block Jacobian (2x2 for CH, 4x4 for NS per node,
  * row-major, device, n_nodes*nf*nf doubles), including the hanging-node
  * couplings; boundary rows are identity rows. */
+/* Cached linearisation of the NS block.  Within one Newton iteration the
+ * state is fixed, so the quantities of Def. 2 that the JVP differentiates
+ * around (rho, eta, v~ and its gradient, the mass flux J, the transport
+ * velocity of R_m, R_m, R_c, tau_m, tau_c: 27 values per Gauss point) can be
+ * evaluated once.  chns_linearize does that for (U_new, U_old) and keeps the
+ * values with the mesh (device memory, 27 * 8 values per element in the
+ * arithmetic of prec, allocated on first use); chns_jvp_lin then applies
+ * the chns_jvp of that state and prec to dU (same layout; same results up
+ * to rounding, since the compiler may contract multiply-adds differently in
+ * the two kernels) reading only the direction.  block must be
+ * CHNS_BLOCK_NS.  The cache holds the last chns_linearize, or the last
+ * Newton iteration of chns_step, on this mesh. */
+int chns_linearize(chns_mesh* mesh, const chns_params* params, int block, const double* U_new,
+                   const double* U_old, int prec, void* stream);
+int chns_jvp_lin(chns_mesh* mesh, const chns_params* params, int block, const void* dU, void* JdU,
+                 int prec, void* stream);
+
 int chns_diag_blocks(chns_mesh* mesh, const chns_params* params, int block,
                      const double* U_new, const double* U_old, double* D, void* stream);
 

@@ -173,6 +173,7 @@ struct chns_mesh {
   double* h_sum = nullptr;
   int64_t device_bytes = 0;
   Workspace ws;
+  void* d_lin[2] = {nullptr, nullptr};  // cached NS linearisation points (FP64, FP32)
   std::vector<MGLevel> mg;  // multigrid hierarchy, built on first use
   int mg_key = -1;          // mg_levels it was built for
 };
@@ -402,6 +403,49 @@ int launch_jvp(chns_mesh* m, const dev::PhysView& pv, int block, const TS* U1, c
   return CHNS_OK;
 }
 
+// Cached NS linearisation points (k_ns_lin) and the JVP that reads them.
+template <class T>
+int ensure_lin(chns_mesh* m) {
+  const int k = std::is_same<T, double>::value ? 0 : 1;
+  if (m->d_lin[k]) return CHNS_OK;
+  std::lock_guard<std::mutex> lk(g_struct_mu);
+  T* p = nullptr;
+  const int rc = dalloc(&p, (size_t)m->n_chunks * dev::kNSLin * dev::kChunkThreads, &m->device_bytes);
+  if (rc) return rc;
+  m->d_lin[k] = p;
+  return CHNS_OK;
+}
+
+template <class T, class TS>
+int launch_ns_lin(chns_mesh* m, const dev::PhysView& pv, const TS* U1, const TS* U0, hipStream_t s) {
+  int rc = ensure_lin<T>(m);
+  if (rc) return rc;
+  const dev::ChunkCaps cc = caps(m);
+  hipLaunchKernelGGL((dev::k_ns_lin<T, TS>), dim3((unsigned)m->n_chunks), dim3(dev::kChunkThreads),
+                     (dev::ChunkLDS<T, 6, 0, 4>::bytes(cc)), s, view(m), plan_view(m), pv, cc, U1, U0,
+                     (T*)m->d_lin[std::is_same<T, double>::value ? 0 : 1]);
+  HIPCHK(hipGetLastError());
+  return CHNS_OK;
+}
+
+template <class T, class TD>
+int launch_jvp_lin(chns_mesh* m, const dev::PhysView& pv, const TD* dU, int ldD, int offD, TD* out, int ldO,
+                   int offO, hipStream_t s, const int* skip = nullptr) {
+  const T* lin = (const T*)m->d_lin[std::is_same<T, double>::value ? 0 : 1];
+  if (!lin) return fail(CHNS_EINVAL, "no linearisation point: call chns_linearize first");
+  const int64_t n = (int64_t)m->h.node_key.size();
+  const dev::ChunkCaps cc = caps(m);
+  const auto pl = plan_view(m);
+  T* part = (T*)m->d_partial;
+  hipLaunchKernelGGL((dev::k_ns_jvp_lin<T, TD>), dim3((unsigned)m->n_chunks), dim3(dev::kChunkThreads),
+                     (dev::ChunkLDS<T, 0, 4, 4>::bytes(cc)), s, view(m), pl, pv, cc, lin, dU, ldD, offD, part,
+                     skip);
+  hipLaunchKernelGGL((dev::k_gather<4, T, TD, 2>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part, out, ldO,
+                     offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD, skip);
+  HIPCHK(hipGetLastError());
+  return CHNS_OK;
+}
+
 int launch_diag(chns_mesh* m, const dev::PhysView& pv, int block, const double* U1, const double* U0,
                 double* D, hipStream_t s) {
   const int64_t n = (int64_t)m->h.node_key.size();
@@ -616,6 +660,7 @@ struct Solver {
   template <class TV>
   int apply(int block, const TV* x, TV* y, const double* U1, const double* U0, const int* skip) {
     const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+    if (block == CHNS_BLOCK_NS) return launch_jvp_lin<TV, TV>(m, pv, x, nf, 0, y, nf, 0, s, skip);
     if (std::is_same<TV, double>::value)
       return launch_jvp<double, double, TV>(m, pv, block, U1, U0, x, nf, 0, y, nf, 0, s, skip);
     return launch_jvp<float, float, TV>(m, pv, block, w.U1f, w.U0f, x, nf, 0, y, nf, 0, s, skip);
@@ -659,6 +704,7 @@ struct Solver {
     const TV* S0 = l == 0 ? (dbl ? (const TV*)U0 : (const TV*)w.U0f) : (dbl ? (const TV*)L.U0 : (const TV*)L.U0f);
     const dim3 g(grid_stride(nl)), gs(grid_stride(N)), bl(256);
     auto A = [&](const TV* in, TV* out) {
+      if (block == CHNS_BLOCK_NS) return launch_jvp_lin<TV, TV>(mm, pv, in, NF, 0, out, NF, 0, s, skip);
       return launch_jvp<TV, TV, TV>(mm, pv, block, S1, S0, in, NF, 0, out, NF, 0, s, skip);
     };
     auto jac = [&](const TV* Ax) {
@@ -709,6 +755,11 @@ struct Solver {
       hipLaunchKernelGGL(dev::k_inject6, g, b, 0, s, s0, F.inj, C.n, C.U0, C.U0f);
       int rc = launch_diag(C.mesh, pv, block, C.U1, C.U0, C.D, s);
       if (rc) return rc;
+      if (block == CHNS_BLOCK_NS) {
+        rc = o.precision == 0 ? launch_ns_lin<double, double>(C.mesh, pv, C.U1, C.U0, s)
+                              : launch_ns_lin<float, float>(C.mesh, pv, C.U1f, C.U0f, s);
+        if (rc) return rc;
+      }
       if (nf == 2)
         hipLaunchKernelGGL(dev::k_invert_blocks<2>, dim3(grid_for(C.n)), b, 0, s, C.D, C.Di, C.Di32, C.n, 0,
                            w.flag);
@@ -921,6 +972,7 @@ struct Solver {
       if (o.precision == 0) {
         hipLaunchKernelGGL((dev::k_scale<double, double>), dim3(grid_stride(N)), dim3(256), 0, s, w.b64,
                            w.r, -1.0, N);
+        if (block == CHNS_BLOCK_NS && (rc = launch_ns_lin<double, double>(m, pv, U, w.Uk, s))) return rc;
         rc = gmres<double>(block, w.V64, w.Z64, w.w64, w.b64, U, w.Uk, &its);
       } else {
         hipLaunchKernelGGL((dev::k_convert<double, float>), dim3(grid_stride(n * 6)), dim3(256), 0, s, U,
@@ -929,6 +981,7 @@ struct Solver {
                            w.Uk, w.U0f, n * 6, (const int*)nullptr);
         hipLaunchKernelGGL((dev::k_scale<double, float>), dim3(grid_stride(N)), dim3(256), 0, s, w.b32,
                            w.r, -1.0, N);
+        if (block == CHNS_BLOCK_NS && (rc = launch_ns_lin<float, float>(m, pv, w.U1f, w.U0f, s))) return rc;
         rc = gmres<float>(block, w.V32, w.Z32, w.w32, w.b32, U, w.Uk, &its);
       }
       if (rc) return rc;
@@ -1188,7 +1241,7 @@ void free_mesh_locked(chns_mesh* m) {
                   m->d_hw, m->d_hw32, m->d_flag, m->d_part, m->d_sum,
                   m->d_tgt_off, m->d_tgt, m->d_inc_off, m->d_node_off, m->d_node_slot, m->d_inc_corner,
                   m->d_bflags, m->d_inc_w, m->d_touch_off, m->d_ntouch_off, m->d_ntouch_slot,
-                  m->d_partial, m->d_tbuf};
+                  m->d_partial, m->d_tbuf, m->d_lin[0], m->d_lin[1]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (m->h_flag) (void)hipHostFree(m->h_flag);
@@ -1228,6 +1281,36 @@ int chns_jvp(chns_mesh* m, const chns_params* params, int block, const double* U
   if (prec == CHNS_F32)
     return launch_jvp<float, double, float>(m, pv, block, U_new, U_old, (const float*)dU, 6, off,
                                             (float*)JdU, 6, off, s);
+  return fail(CHNS_EINVAL, "prec must be CHNS_F64 or CHNS_F32");
+}
+
+int chns_linearize(chns_mesh* m, const chns_params* params, int block, const double* U_new,
+                   const double* U_old, int prec, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int rc = check_mesh(m, s);
+  if (rc) return rc;
+  dev::PhysView pv;
+  if ((rc = phys_view(params, pv))) return rc;
+  if (block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "the cached linearisation is for the NS block");
+  if (!U_new || !U_old) return fail(CHNS_EINVAL, "pointers must not be NULL");
+  if (prec == CHNS_F64) return launch_ns_lin<double, double>(m, pv, U_new, U_old, s);
+  if (prec == CHNS_F32) return launch_ns_lin<float, double>(m, pv, U_new, U_old, s);
+  return fail(CHNS_EINVAL, "prec must be CHNS_F64 or CHNS_F32");
+}
+
+int chns_jvp_lin(chns_mesh* m, const chns_params* params, int block, const void* dU, void* JdU, int prec,
+                 void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int rc = check_mesh(m, s);
+  if (rc) return rc;
+  dev::PhysView pv;
+  if ((rc = phys_view(params, pv))) return rc;
+  if (block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "the cached linearisation is for the NS block");
+  if (!dU || !JdU) return fail(CHNS_EINVAL, "pointers must not be NULL");
+  if (prec == CHNS_F64)
+    return launch_jvp_lin<double, double>(m, pv, (const double*)dU, 6, 2, (double*)JdU, 6, 2, s);
+  if (prec == CHNS_F32)
+    return launch_jvp_lin<float, float>(m, pv, (const float*)dU, 6, 2, (float*)JdU, 6, 2, s);
   return fail(CHNS_EINVAL, "prec must be CHNS_F64 or CHNS_F32");
 }
 
@@ -1280,7 +1363,7 @@ int chns_launch_element_loop(chns_mesh* m, const chns_params* params, int block,
   dev::PhysView pv;
   if ((rc = phys_view(params, pv))) return rc;
   if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "unknown block");
-  if (!U_new || !U_old || (op != 0 && op != 3 && !dU)) return fail(CHNS_EINVAL, "NULL pointer");
+  if (!U_new || !U_old || (op != 0 && op != 3 && op != 5 && op != 7 && !dU)) return fail(CHNS_EINVAL, "NULL pointer");
   if (reps < 1) return fail(CHNS_EINVAL, "reps must be positive");
   if (op == 3 && (rc = ensure_tbuf(m))) return rc;
   (void)out;
@@ -1317,13 +1400,33 @@ int chns_launch_element_loop(chns_mesh* m, const chns_params* params, int block,
         hipLaunchKernelGGL((dev::k_ns_jvp<float, double, float>), g, b,
                            (dev::ChunkLDS<float, 6, 4, 4>::bytes(cc)), s, mv, pl, pv, cc, U_new, U_old,
                            (const float*)dU, 6, off, p32, (const int*)nullptr);
+    } else if (op == 4) {
+      if (block != CHNS_BLOCK_NS || !m->d_lin[0]) return fail(CHNS_EINVAL, "op 4 needs op 5 first (NS)");
+      hipLaunchKernelGGL((dev::k_ns_jvp_lin<double, double>), g, b, (dev::ChunkLDS<double, 0, 4, 4>::bytes(cc)),
+                         s, mv, pl, pv, cc, (const double*)m->d_lin[0], (const double*)dU, 6, off, p64,
+                         (const int*)nullptr);
+    } else if (op == 5) {
+      if (block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "op 5 is for the NS block");
+      if ((rc = ensure_lin<double>(m))) return rc;
+      hipLaunchKernelGGL((dev::k_ns_lin<double, double>), g, b, (dev::ChunkLDS<double, 6, 0, 4>::bytes(cc)), s,
+                         mv, pl, pv, cc, U_new, U_old, (double*)m->d_lin[0]);
+    } else if (op == 6) {
+      if (block != CHNS_BLOCK_NS || !m->d_lin[1]) return fail(CHNS_EINVAL, "op 6 needs op 7 first (NS)");
+      hipLaunchKernelGGL((dev::k_ns_jvp_lin<float, float>), g, b, (dev::ChunkLDS<float, 0, 4, 4>::bytes(cc)),
+                         s, mv, pl, pv, cc, (const float*)m->d_lin[1], (const float*)dU, 6, off, p32,
+                         (const int*)nullptr);
+    } else if (op == 7) {
+      if (block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "op 7 is for the NS block");
+      if ((rc = ensure_lin<float>(m))) return rc;
+      hipLaunchKernelGGL((dev::k_ns_lin<float, double>), g, b, (dev::ChunkLDS<float, 6, 0, 4>::bytes(cc)), s,
+                         mv, pl, pv, cc, U_new, U_old, (float*)m->d_lin[1]);
     } else if (op == 3) {
       if (block == CHNS_BLOCK_CH)
         hipLaunchKernelGGL((dev::k_diag<double, 0>), g, b, 0, s, mv, pl, pv, U_new, U_old, m->d_tbuf);
       else
         hipLaunchKernelGGL((dev::k_diag<double, 1>), g, b, 0, s, mv, pl, pv, U_new, U_old, m->d_tbuf);
     } else {
-      return fail(CHNS_EINVAL, "op must be 0..3");
+      return fail(CHNS_EINVAL, "op must be 0..7");
     }
   }
   HIPCHK(hipGetLastError());

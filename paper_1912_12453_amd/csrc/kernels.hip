@@ -104,12 +104,16 @@ struct ChunkLDS {
       const int j = i / NV, f = i - j * NV;
       const int64_t g = pl.tgt[s0 + j];
       T v;
-      if (f < NU) {
-        v = (T)U1[g * 6 + f];
-      } else if (ND == 0 || f < 2 * NU) {
-        v = (T)U0[g * 6 + f - NU];
+      if constexpr (NU > 0) {
+        if (f < NU) {
+          v = (T)U1[g * 6 + f];
+        } else if (ND == 0 || f < 2 * NU) {
+          v = (T)U0[g * 6 + f - NU];
+        } else {
+          if constexpr (ND > 0) v = (T)dU[g * ldD + offD + f - 2 * NU];
+        }
       } else {
-        if constexpr (ND > 0) v = (T)dU[g * ldD + offD + f - 2 * NU];
+        v = (T)dU[g * ldD + offD + f];  // direction only
       }
       val[j * SV + f] = v;
     }
@@ -468,6 +472,127 @@ __global__ __launch_bounds__(256) void k_ns_jvp(MeshView m, PlanView pl, PhysVie
     dvt[i].dz = (T)0.5 * g.dz;
   }
   const VG<T> dpt = eval_vg<T>((T)0.5 * c[15], L);
+  T r[4];
+  ns_jvp_point<T>(p, L, P, dvt, ddv, dpt, r);
+  S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
+}
+
+// ------------------------------------------- cached linearisation point ----
+// Within one Newton iteration the state is fixed, so the NS linearisation
+// point at every Gauss point (the 27 values ns_jvp_coef reads) can be
+// computed once and reused by every Jacobian-vector product of the linear
+// solve.  Layout (structure of arrays per chunk, coalesced for the 256 lanes
+// of the chunk's workgroup): lin[(chunk * kNSLin + k) * 256 + lane].
+constexpr int kNSLin = 27;
+
+template <class T>
+__device__ __forceinline__ void ns_lin_store(const NSPoint<T>& P, T* __restrict__ q) {
+  int k = 0;
+  q[(k++) * kChunkThreads] = P.rho;
+  q[(k++) * kChunkThreads] = P.inv_rho;
+  q[(k++) * kChunkThreads] = P.eta;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) q[(k++) * kChunkThreads] = P.vt[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) q[(k++) * kChunkThreads] = P.G[i][j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) q[(k++) * kChunkThreads] = P.J[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) q[(k++) * kChunkThreads] = P.adv[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) q[(k++) * kChunkThreads] = P.Rm[i];
+  q[(k++) * kChunkThreads] = P.Rc;
+  q[(k++) * kChunkThreads] = P.tau_m;
+  q[(k++) * kChunkThreads] = P.tau_c;
+}
+
+template <class T>
+__device__ __forceinline__ void ns_lin_load(const T* __restrict__ q, const Lane<T>& L, NSPoint<T>& P) {
+  int k = 0;
+  P.rho = q[(k++) * kChunkThreads];
+  P.inv_rho = q[(k++) * kChunkThreads];
+  P.eta = q[(k++) * kChunkThreads];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) P.vt[i] = q[(k++) * kChunkThreads];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) P.G[i][j] = q[(k++) * kChunkThreads];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) P.J[i] = q[(k++) * kChunkThreads];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) P.adv[i] = q[(k++) * kChunkThreads];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) P.Rm[i] = q[(k++) * kChunkThreads];
+  P.Rc = q[(k++) * kChunkThreads];
+  P.tau_m = q[(k++) * kChunkThreads];
+  P.tau_c = q[(k++) * kChunkThreads];
+  P.Gh = (T)4 / (L.h * L.h);
+}
+
+// Linearisation points of every Gauss point of the mesh (one workgroup per
+// chunk, as the element loop).
+template <class T, class TS>
+__global__ __launch_bounds__(256) void k_ns_lin(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
+                                                const TS* __restrict__ U1, const TS* __restrict__ U0,
+                                                T* __restrict__ lin) {
+  extern __shared__ double smem_d[];
+  using CL = ChunkLDS<T, 6, 0, 4>;
+  CL S;
+  S.carve((char*)smem_d, caps);
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int64_t e = e0 < m.E ? e0 : m.E - 1;
+  Lane<T> L;
+  L.init(threadIdx.x & 7, m.level[e]);
+  const int ref = m.elem[e * 8 + L.c];
+  S.stage(pl, U1, U0, (const TS*)nullptr, 0, 0);
+  __syncthreads();
+  T c[CL::NV];
+  S.corner(m, ref, c);
+  const T a[6] = {c[0], c[1], c[2], c[3], c[4], c[5]};
+  const T b[6] = {c[6], c[7], c[8], c[9], c[10], c[11]};
+  NSPoint<T> P;
+  ns_point<T>(p, L, a, b, P);
+  ns_lin_store<T>(P, lin + (int64_t)blockIdx.x * kNSLin * kChunkThreads + threadIdx.x);
+}
+
+// The NS Jacobian-vector product from the cached linearisation points: only
+// the direction is staged.
+template <class T, class TD>
+__global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
+                                                    const T* __restrict__ lin, const TD* __restrict__ dU,
+                                                    int ldD, int offD, T* __restrict__ partial,
+                                                    const int* skip) {
+  if (skip && *skip) return;  // GMRES control: this step is not needed
+  extern __shared__ double smem_d[];
+  using CL = ChunkLDS<T, 0, 4, 4>;
+  CL S;
+  S.carve((char*)smem_d, caps);
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int64_t e = e0 < m.E ? e0 : m.E - 1;
+  Lane<T> L;
+  L.init(threadIdx.x & 7, m.level[e]);
+  const int ref = m.elem[e * 8 + L.c];
+  S.stage(pl, (const TD*)nullptr, (const TD*)nullptr, dU, ldD, offD);
+  NSPoint<T> P;
+  ns_lin_load<T>(lin + (int64_t)blockIdx.x * kNSLin * kChunkThreads + threadIdx.x, L, P);
+  __syncthreads();
+  T c[CL::NV];
+  S.corner(m, ref, c);
+  VG<T> dvt[3];
+  T ddv[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const VG<T> g = eval_vg<T>(c[i], L);
+    ddv[i] = g.v;
+    dvt[i].v = (T)0.5 * g.v;
+    dvt[i].dx = (T)0.5 * g.dx;
+    dvt[i].dy = (T)0.5 * g.dy;
+    dvt[i].dz = (T)0.5 * g.dz;
+  }
+  const VG<T> dpt = eval_vg<T>((T)0.5 * c[3], L);
   T r[4];
   ns_jvp_point<T>(p, L, P, dvt, ddv, dpt, r);
   S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);

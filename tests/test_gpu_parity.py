@@ -111,6 +111,41 @@ def test_jvp_parity(torch, chns, orc, kind, block):
     assert e32 > 0
 
 
+@pytest.mark.parametrize("kind", KINDS)
+def test_cached_linearisation_jvp(torch, chns, orc, kind):
+    """chns_jvp_lin after chns_linearize matches the oracle to 1e-12 and
+    chns_jvp to rounding (the two kernels may contract multiply-adds across
+    the point/derivative boundary differently); the cache follows the last
+    linearize."""
+    pm, om = mesh_pair(chns, orc, kind)
+    print(f"case jvp_lin {kind} E={pm.n_leaves}", flush=True)
+    ph = W.moderate_physics()
+    p = chns.make_params(ph)
+    U1, U0 = W.random_state(pm.n_nodes, 210)
+    dU = W.direction(pm.n_nodes, 310)
+    d1, d0, ddU = to_dev(torch, U1), to_dev(torch, U0), to_dev(torch, dU)
+    ref = om.jvp(orc.Params.make(**vars(ph)), NS, U1, U0, dU)
+    pm.linearize(p, NS, d1, d0)
+    J = pm.jvp_lin(p, NS, ddU).cpu().numpy()
+    compare(J, ref, slice(2, 6), label=f"jvp_lin64 {kind}")
+    compare(J, pm.jvp(p, NS, d1, d0, ddU).cpu().numpy(), slice(2, 6), tol=1e-14,
+            label=f"jvp_lin64 vs jvp64 {kind}")
+    ddU32 = to_dev(torch, dU, torch.float32)
+    pm.linearize(p, NS, d1, d0, prec=chns.CHNS_F32)
+    J32 = pm.jvp_lin(p, NS, ddU32, prec=chns.CHNS_F32).cpu().numpy().astype(np.float64)
+    compare(J32, pm.jvp(p, NS, d1, d0, ddU32, prec=chns.CHNS_F32).cpu().numpy().astype(np.float64),
+            slice(2, 6), tol=1e-5, label=f"jvp_lin32 vs jvp32 {kind}")
+    compare(J32, ref, slice(2, 6), tol=1e-4, label=f"jvp_lin32 {kind}")
+    # a new linearisation point replaces the cache
+    U1b, U0b = W.random_state(pm.n_nodes, 211)
+    pm.linearize(p, NS, to_dev(torch, U1b), to_dev(torch, U0b))
+    Jb = pm.jvp_lin(p, NS, ddU).cpu().numpy()
+    refb = om.jvp(orc.Params.make(**vars(ph)), NS, U1b, U0b, dU)
+    compare(Jb, refb, slice(2, 6), label=f"jvp_lin64 relinearised {kind}")
+    with pytest.raises(chns.ChnsError):
+        pm.linearize(p, CH, d1, d0)
+
+
 @pytest.mark.parametrize("kind", ["single", "adaptive", "brick", "drop16"])
 @pytest.mark.parametrize("block", [CH, NS])
 def test_diag_blocks_parity(torch, chns, orc, kind, block):
