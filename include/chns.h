@@ -271,6 +271,31 @@ int chns_mesh_coarsen(const chns_mesh* mesh, chns_mesh** coarse);
 int chns_mesh_transfer(const chns_mesh* fine, const chns_mesh* coarse, int64_t* nnz, int32_t* p_off,
                        int32_t* p_idx, double* p_w, int32_t* inj);
 
+/* ------------------------------------------ remeshing and transfer ----
+ * Sec. 4 "Remeshing": as the interface moves it leaves the finely refined
+ * band, so the octree is rebuilt around the current phi and the fields are
+ * carried over by the intergrid transfer.
+ *
+ * chns_mesh_remesh: a new mesh of the same brick, refined top-down and 2:1
+ * balanced exactly as chns_mesh_build does, with phi0 replaced by the
+ * trilinear field of phi = U_host[6i] on `mesh` (host array, n_nodes*6).
+ * Host only; *out is released with chns_mesh_free. */
+int chns_mesh_remesh(const chns_mesh* mesh, const double* U_host, int level_min, int level_max,
+                     double band, chns_mesh** out);
+/* Intergrid transfer between any two meshes of one brick: node i of `to`
+ * takes sum_k w[k] * (node idx[k] of `from`), k in [off[i], off[i+1]), the
+ * trilinear field of `from` (through its hanging constraints) at that node.
+ * chns_mesh_interp_weights returns the lists (host only; arrays may be NULL,
+ * sizes off n_to + 1, idx and w *nnz).  chns_mesh_interpolate applies them
+ * to all 6 fields on the device (U_from: from's n_nodes*6, U_to: to's);
+ * with conserve_mass != 0 it then shifts phi by the constant that restores
+ * the integral of phi (params needed for that, else may be NULL).
+ * Synchronises the stream. */
+int chns_mesh_interp_weights(const chns_mesh* from, const chns_mesh* to, int64_t* nnz, int32_t* off,
+                             int32_t* idx, double* w);
+int chns_mesh_interpolate(chns_mesh* from, chns_mesh* to, const double* U_from, double* U_to,
+                          const chns_params* params, int conserve_mass, void* stream);
+
 /* ------------------------------------------------------------ serving ----
  * A request loop for many independent droplet / bubble problems of different
  * octree sizes.  Each request is (mesh spec, parameters, number of Crank-

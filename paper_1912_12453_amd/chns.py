@@ -137,6 +137,9 @@ def lib():
                                                vp, vp, C.c_int, vp, C.POINTER(C.c_int64)]
         L.chns_mesh_coarsen.argtypes = [vp, C.POINTER(vp)]
         L.chns_mesh_transfer.argtypes = [vp, vp, C.POINTER(C.c_int64), vp, vp, vp, vp]
+        L.chns_mesh_remesh.argtypes = [vp, vp, C.c_int, C.c_int, C.c_double, C.POINTER(vp)]
+        L.chns_mesh_interp_weights.argtypes = [vp, vp, C.POINTER(C.c_int64), vp, vp, vp]
+        L.chns_mesh_interpolate.argtypes = [vp, vp, vp, vp, C.POINTER(chns_params), C.c_int, vp]
         L.chns_server_create.argtypes = [C.c_size_t, C.c_int, C.POINTER(chns_solver_opts), C.POINTER(vp)]
         L.chns_server_submit.argtypes = [vp, C.POINTER(chns_mesh_spec), C.POINTER(chns_params), C.c_int,
                                          C.POINTER(C.c_int64)]
@@ -440,13 +443,7 @@ class Mesh:
         """The mesh with its finest level merged into the parents (a Mesh)."""
         h = C.c_void_p()
         _check(lib().chns_mesh_coarsen(self.h, C.byref(h)))
-        m = Mesh.__new__(Mesh)
-        m.h = h
-        m._keep = None
-        m.stats = chns_mesh_info(h)
-        m.trees = self.trees
-        m.level_max = self.level_max - 1
-        return m
+        return Mesh._wrap(h, self.trees, self.level_max - 1)
 
     def transfer(self, coarse):
         """(p_off, p_idx, p_w, inj): prolongation from `coarse` to this mesh
@@ -460,6 +457,46 @@ class Mesh:
         _check(lib().chns_mesh_transfer(self.h, coarse.h, None, p_off.ctypes.data, p_idx.ctypes.data,
                                         p_w.ctypes.data, inj.ctypes.data))
         return p_off, p_idx, p_w, inj
+
+    @classmethod
+    def _wrap(cls, h, trees, level_max):
+        m = Mesh.__new__(Mesh)
+        m.h = h
+        m._keep = None
+        m.stats = chns_mesh_info(h)
+        m.trees = trees
+        m.level_max = level_max
+        return m
+
+    def remesh(self, U_host, level_min, level_max, band=0.9):
+        """A new Mesh refined around the trilinear phi of U_host (n_nodes x 6)."""
+        U = np.ascontiguousarray(U_host, dtype=np.float64)
+        if U.shape != (self.n_nodes, 6):
+            raise ValueError("U_host must be n_nodes x 6")
+        h = C.c_void_p()
+        _check(lib().chns_mesh_remesh(self.h, U.ctypes.data, level_min, level_max, band, C.byref(h)))
+        return Mesh._wrap(h, self.trees, level_max)
+
+    def interp_weights(self, to):
+        """(off, idx, w): the transfer from this mesh to `to`."""
+        nnz = C.c_int64()
+        _check(lib().chns_mesh_interp_weights(self.h, to.h, C.byref(nnz), None, None, None))
+        off = np.zeros(to.n_nodes + 1, np.int32)
+        idx = np.zeros(nnz.value, np.int32)
+        w = np.zeros(nnz.value, np.float64)
+        _check(lib().chns_mesh_interp_weights(self.h, to.h, None, off.ctypes.data, idx.ctypes.data,
+                                              w.ctypes.data))
+        return off, idx, w
+
+    def interpolate(self, to, U_from, params=None, conserve_mass=False, stream=None):
+        """The fields U_from (device, this mesh) carried to `to` (new device tensor)."""
+        import torch
+        _dev(U_from, "float64")
+        out = torch.empty((to.n_nodes, 6), dtype=torch.float64, device=U_from.device)
+        _check(lib().chns_mesh_interpolate(self.h, to.h, U_from.data_ptr(), out.data_ptr(),
+                                           C.byref(params) if params is not None else None,
+                                           1 if conserve_mass else 0, _stream(stream)))
+        return out
 
     def upload(self, stream=None):
         chns_mesh_upload(self.h, stream)

@@ -1205,6 +1205,112 @@ int chns_mesh_transfer(const chns_mesh* f, const chns_mesh* c, int64_t* nnz, int
   return CHNS_OK;
 }
 
+int chns_mesh_remesh(const chns_mesh* m, const double* U_host, int level_min, int level_max, double band,
+                     chns_mesh** out) {
+  if (!m || !U_host || !out) return fail(CHNS_EINVAL, "mesh, U_host and out must not be NULL");
+  *out = nullptr;
+  chns_mesh* c = new (std::nothrow) chns_mesh();
+  if (!c) return fail(CHNS_ENOMEM, "out of host memory");
+  std::string err;
+  try {
+    err = remesh_host(m->h, U_host, level_min, level_max, band, c->h);
+  } catch (const std::bad_alloc&) {
+    err = "out of host memory while remeshing";
+  }
+  if (!err.empty()) {
+    delete c;
+    return fail(err.find("memory") != std::string::npos ? CHNS_ENOMEM : CHNS_EINVAL, err);
+  }
+  *out = c;
+  return CHNS_OK;
+}
+
+int chns_mesh_interp_weights(const chns_mesh* from, const chns_mesh* to, int64_t* nnz, int32_t* off,
+                             int32_t* idx, double* w) {
+  if (!from || !to) return fail(CHNS_EINVAL, "meshes must not be NULL");
+  std::vector<int32_t> o, ix;
+  std::vector<double> ww;
+  std::string err;
+  try {
+    err = build_interp(from->h, to->h, o, ix, ww);
+  } catch (const std::bad_alloc&) {
+    err = "out of host memory while building the transfer";
+  }
+  if (!err.empty()) return fail(CHNS_EINVAL, err);
+  if (nnz) *nnz = (int64_t)ix.size();
+  if (off) std::memcpy(off, o.data(), o.size() * sizeof(int32_t));
+  if (idx) std::memcpy(idx, ix.data(), ix.size() * sizeof(int32_t));
+  if (w) std::memcpy(w, ww.data(), ww.size() * sizeof(double));
+  return CHNS_OK;
+}
+
+int chns_mesh_interpolate(chns_mesh* from, chns_mesh* to, const double* U_from, double* U_to,
+                          const chns_params* params, int conserve_mass, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (!from || !to || !U_from || !U_to) return fail(CHNS_EINVAL, "NULL argument");
+  if (conserve_mass && !params) return fail(CHNS_EINVAL, "conserve_mass needs params");
+  int rc;
+  if ((rc = check_mesh(from, s)) || (rc = check_mesh(to, s))) return rc;
+  std::vector<int32_t> o, ix;
+  std::vector<double> ww;
+  std::string err;
+  try {
+    err = build_interp(from->h, to->h, o, ix, ww);
+  } catch (const std::bad_alloc&) {
+    err = "out of host memory while building the transfer";
+  }
+  if (!err.empty()) return fail(CHNS_EINVAL, err);
+  int32_t *d_off = nullptr, *d_idx = nullptr;
+  double *d_w = nullptr, *d_c = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_struct_mu);
+    if ((rc = dalloc(&d_off, o.size(), nullptr)) || (rc = dalloc(&d_idx, ix.size(), nullptr)) ||
+        (rc = dalloc(&d_w, ww.size(), nullptr)) || (rc = dalloc(&d_c, 1, nullptr))) {
+      void* ps[] = {d_off, d_idx, d_w, d_c};
+      for (void* p : ps)
+        if (p) (void)hipFree(p);
+      return rc;
+    }
+  }
+  auto cleanup = [&]() {
+    std::lock_guard<std::mutex> lk(g_struct_mu);
+    void* ps[] = {d_off, d_idx, d_w, d_c};
+    for (void* p : ps)
+      if (p) (void)hipFree(p);
+  };
+  const int64_t nt = (int64_t)to->h.node_key.size();
+  if ((rc = h2d(d_off, o, s)) || (rc = h2d(d_idx, ix, s)) || (rc = h2d(d_w, ww, s))) {
+    cleanup();
+    return rc;
+  }
+  hipLaunchKernelGGL(dev::k_interp6, dim3(grid_stride(nt)), dim3(256), 0, s, U_from, d_off, d_idx, d_w, nt,
+                     U_to);
+  if (hipGetLastError() != hipSuccess) {
+    cleanup();
+    return fail(CHNS_EHIP, "launching the transfer failed");
+  }
+  if (conserve_mass) {
+    dev::PhysView pv;
+    double m0, m1, e;
+    if ((rc = phys_view(params, pv)) || (rc = launch_diagnostics(from, pv, U_from, &m0, &e, s)) ||
+        (rc = launch_diagnostics(to, pv, U_to, &m1, &e, s))) {
+      cleanup();
+      return rc;
+    }
+    const double vol = (double)to->h.T[0] * to->h.T[1] * to->h.T[2];
+    const double c = (m0 - m1) / vol;
+    if (hipMemcpyAsync(d_c, &c, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess) {
+      cleanup();
+      return fail(CHNS_EHIP, "copying the mass shift failed");
+    }
+    hipLaunchKernelGGL(dev::k_shift_phi, dim3(grid_stride(nt)), dim3(256), 0, s, U_to, nt, d_c);
+  }
+  const hipError_t e = hipStreamSynchronize(s);  // the host arrays above must outlive the copies
+  cleanup();
+  if (e != hipSuccess) return fail(CHNS_EHIP, std::string("transfer: ") + hipGetErrorString(e));
+  return CHNS_OK;
+}
+
 int chns_mesh_upload(chns_mesh* m, void* stream) {
   if (!m) return fail(CHNS_EINVAL, "mesh is NULL");
   return upload(m, (hipStream_t)stream);

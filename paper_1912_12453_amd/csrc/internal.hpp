@@ -96,4 +96,14 @@ struct Transfer {
 };
 std::string build_transfer(const HostMesh& f, const HostMesh& c, Transfer& out);
 
+// Remeshing and intergrid transfer between any two meshes of one brick
+// (remesh_host.cpp).  build_interp: node i of `to` takes sum_k w[k] *
+// (node idx[k] of `from`), k in [off[i], off[i+1]), the trilinear field of
+// `from` at that node.  remesh_host: a new mesh refined as build_host_mesh
+// does, with the trilinear field of U's phi on `old` as the indicator.
+std::string build_interp(const HostMesh& from, const HostMesh& to, std::vector<int32_t>& off,
+                         std::vector<int32_t>& idx, std::vector<double>& w);
+std::string remesh_host(const HostMesh& old, const double* U, int level_min, int level_max, double band,
+                        HostMesh& out);
+
 }  // namespace chns

@@ -108,5 +108,32 @@ __global__ void k_jacobi(const TM* __restrict__ Di, const TV* __restrict__ b, co
   }
 }
 
+// Ut[i] = sum_k w[k] * Uf[idx[k]] for the 6 fields of node i (intergrid
+// transfer, in the list's fixed order)
+__global__ void k_interp6(const double* __restrict__ Uf, const int32_t* __restrict__ off,
+                          const int32_t* __restrict__ idx, const double* __restrict__ w, int64_t n,
+                          double* __restrict__ Ut) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = off[i]; k < off[i + 1]; ++k) {
+      const int64_t j = idx[k];
+      const double wk = w[k];
+#pragma unroll
+      for (int f = 0; f < 6; ++f) acc[f] += wk * Uf[j * 6 + f];
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) Ut[i * 6 + f] = acc[f];
+  }
+}
+
+// U[i][0] += c for every node (a constant shift of phi)
+__global__ void k_shift_phi(double* __restrict__ U, int64_t n, const double* __restrict__ c) {
+  const double s = *c;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    U[i * 6] += s;
+}
+
 }  // namespace dev
 }  // namespace chns
