@@ -245,8 +245,10 @@ int chns_step(chns_mesh* mesh, const chns_params* params, const chns_solver_opts
  * them with its own HIP events on that stream.  The kernels write the mesh's
  * internal partial buffers; `out` is not used and may be NULL.  op: 0 residual
  * (FP64), 1 JVP FP64 (dU: n_nodes*6 doubles), 2 JVP FP32 (dU: n_nodes*6
- * floats), 3 node-block diagonal.  *grid (may be NULL) receives the number of
- * workgroups of one launch. */
+ * floats), 3 node-block diagonal; NS block only: 5 cached linearisation
+ * points of (U_new, U_old) in FP64, 4 the JVP from them (FP64 dU), 7 and 6
+ * the same in FP32 (4 and 6 fail unless 5 or 7 ran before on the mesh).
+ * *grid (may be NULL) receives the number of workgroups of one launch. */
 int chns_launch_element_loop(chns_mesh* mesh, const chns_params* params, int block, int op,
                              const double* U_new, const double* U_old, const void* dU, void* out,
                              int reps, void* stream, int64_t* grid);
