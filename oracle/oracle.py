@@ -80,6 +80,7 @@ def lib():
         L.orc_mesh_arrays.argtypes = [C.c_void_p] + [C.c_void_p] * 8
         L.orc_residual.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, dp, dp, dp, dp]
         L.orc_jvp.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, dp, dp, dp, dp]
+        L.orc_jvp_full.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, dp, dp, dp, dp]
         L.orc_residual_rows.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, dp, dp,
                                         C.POINTER(C.c_int32), C.c_int64, dp, dp]
         L.orc_diag_blocks.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, dp, dp, dp]
@@ -193,6 +194,16 @@ class Mesh:
         Unew, Uold, dU = _state(Unew, n), _state(Uold, n), _state(dU, n)
         out = np.zeros((n, 6))
         rc = lib().orc_jvp(self._h, C.byref(p), block, _dp(Unew), _dp(Uold), _dp(dU), _dp(out))
+        if rc != 0:
+            raise RuntimeError(_err())
+        return out
+
+    def jvp_full(self, p, block, Unew, Uold, dU):
+        """The block's rows of the coupled Jacobian applied to dU (all six fields)."""
+        n = self.n_nodes
+        Unew, Uold, dU = _state(Unew, n), _state(Uold, n), _state(dU, n)
+        out = np.zeros((n, 6))
+        rc = lib().orc_jvp_full(self._h, C.byref(p), block, _dp(Unew), _dp(Uold), _dp(dU), _dp(out))
         if rc != 0:
             raise RuntimeError(_err())
         return out

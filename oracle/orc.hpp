@@ -72,6 +72,11 @@ std::string residual(const Mesh& m, const Params& p, int block, const double* Un
                      const double* Uold, const double* forcing, double* R);
 std::string jvp(const Mesh& m, const Params& p, int block, const double* Unew,
                 const double* Uold, const double* dU, double* JdU);
+// The block's rows of the coupled Jacobian: the derivative with respect to all
+// six fields of U^{k+1} (the block iteration freezes the other block's fields;
+// a fully coupled Newton solve needs these cross terms).
+std::string jvp_full(const Mesh& m, const Params& p, int block, const double* Unew,
+                     const double* Uold, const double* dU, double* JdU);
 // Rows of R (6-interleaved) restricted to the listed nodes; out[k*6+f].
 std::string residual_rows(const Mesh& m, const Params& p, int block, const double* Unew,
                           const double* Uold, const int32_t* rows, int64_t nrows,

@@ -78,6 +78,12 @@ int orc_jvp(void* m, const orc::Params* p, int block, const double* Unew, const 
   return e.empty() ? 0 : fail(e);
 }
 
+int orc_jvp_full(void* m, const orc::Params* p, int block, const double* Unew, const double* Uold,
+                 const double* dU, double* JdU) {
+  std::string e = orc::jvp_full(*(orc::Mesh*)m, *p, block, Unew, Uold, dU, JdU);
+  return e.empty() ? 0 : fail(e);
+}
+
 int orc_residual_rows(void* m, const orc::Params* p, int block, const double* Unew,
                       const double* Uold, const int32_t* rows, int64_t nrows, const double* dU,
                       double* out) {

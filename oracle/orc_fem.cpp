@@ -151,6 +151,10 @@ static inline double phistar(double phi) {
   if (std::fabs(phi) <= 1.0) return phi;
   return phi > 0 ? 1.0 : -1.0;
 }
+static inline Dual phistar(Dual phi) {
+  if (std::fabs(phi.v) <= 1.0) return phi;
+  return Dual(phi.v > 0 ? 1.0 : -1.0);
+}
 // Mass flux coefficient: J = kappa grad(mu~) (thermo-consistency relation of
 // Sec. 2).  With rho = alpha phi + beta, the continuity equation and the CH
 // equation agree only for kappa = -alpha/Cn; the printed relation has -alpha.
@@ -166,24 +170,25 @@ static inline double kappa(const Params& p, const Mixture& mx) {
 // v~ = (v^k + v^{k+1})/2 frozen from the Navier-Stokes block.
 template <class S>
 static void ch_element(const Mesh& m, const Params& p, size_t e, const S phi1[8],
-                       const S mu1[8], const double* Uold, const double* Unew,
+                       const S mu1[8], const S v1[8][3], const double* Uold,
                        const double* forcing, S r[8][2]) {
   double x0[3], h;
   leaf_geometry(m, e, x0, h);
   QP q[8];
   element_qps(x0, h, q);
-  double phi0[8], mu0[8], vt[8][3];
+  double phi0[8], mu0[8];
+  S vt[8][3];
   for (int c = 0; c < 8; ++c) {
     phi0[c] = corner_value(m, e, c, Uold, 0);
     mu0[c] = corner_value(m, e, c, Uold, 1);
-    for (int d = 0; d < 3; ++d)
-      vt[c][d] = 0.5 * (corner_value(m, e, c, Uold, 2 + d) + corner_value(m, e, c, Unew, 2 + d));
+    for (int d = 0; d < 3; ++d) vt[c][d] = 0.5 * (corner_value(m, e, c, Uold, 2 + d) + v1[c][d]);
   }
   for (int a = 0; a < 8; ++a) r[a][0] = r[a][1] = S(0.0);
   for (int k = 0; k < 8; ++k) {
     const QP& Q = q[k];
     S ph1 = 0.0, mt = 0.0;
-    double ph0 = 0.0, v[3] = {0, 0, 0};
+    double ph0 = 0.0;
+    S v[3] = {0.0, 0.0, 0.0};
     S gph[3] = {0.0, 0.0, 0.0}, gmu[3] = {0.0, 0.0, 0.0};
     for (int c = 0; c < 8; ++c) {
       ph1 += Q.N[c] * phi1[c];
@@ -239,7 +244,7 @@ static void ch_element(const Mesh& m, const Params& p, size_t e, const S phi1[8]
 //    sign obtained by substituting v' = -tau_m R_m / rho into (q, dv'_i/dx_i).
 template <class S>
 static bool ns_element(const Mesh& m, const Params& p, size_t e, const S v1[8][3],
-                       const S p1[8], const double* Uold, const double* Unew,
+                       const S p1[8], const S phin[8], const S mun[8], const double* Uold,
                        const double* forcing, S r[8][4]) {
   const Mixture mx(p);
   const double kap = kappa(p, mx);
@@ -247,13 +252,14 @@ static bool ns_element(const Mesh& m, const Params& p, size_t e, const S v1[8][3
   leaf_geometry(m, e, x0, h);
   QP q[8];
   element_qps(x0, h, q);
-  double v0[8][3], p0[8], phi1[8], phit[8], mut[8];
+  double v0[8][3], p0[8];
+  S phi1[8], phit[8], mut[8];
   for (int c = 0; c < 8; ++c) {
     for (int d = 0; d < 3; ++d) v0[c][d] = corner_value(m, e, c, Uold, 2 + d);
     p0[c] = corner_value(m, e, c, Uold, 5);
-    phi1[c] = corner_value(m, e, c, Unew, 0);
-    phit[c] = 0.5 * (corner_value(m, e, c, Unew, 0) + corner_value(m, e, c, Uold, 0));
-    mut[c] = 0.5 * (corner_value(m, e, c, Unew, 1) + corner_value(m, e, c, Uold, 1));
+    phi1[c] = phin[c];
+    phit[c] = 0.5 * (phin[c] + corner_value(m, e, c, Uold, 0));
+    mut[c] = 0.5 * (mun[c] + corner_value(m, e, c, Uold, 1));
   }
   const double G = 4.0 / (h * h);        // G_ij = G delta_ij
   const double trG = 3.0 * G;            // tr G
@@ -263,8 +269,10 @@ static bool ns_element(const Mesh& m, const Params& p, size_t e, const S v1[8][3
   bool ok = true;
   for (int k = 0; k < 8; ++k) {
     const QP& Q = q[k];
-    // frozen fields
-    double ph1 = 0, gph1[3] = {0, 0, 0}, gpht[3] = {0, 0, 0}, Hpht[3][3] = {}, gmut[3] = {0, 0, 0};
+    // fields of the Cahn-Hilliard block (frozen in the block iteration)
+    S ph1 = 0.0, gph1[3] = {0.0, 0.0, 0.0}, gpht[3] = {0.0, 0.0, 0.0}, Hpht[3][3], gmut[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < 3; ++d)
+      for (int e2 = 0; e2 < 3; ++e2) Hpht[d][e2] = S(0.0);
     for (int c = 0; c < 8; ++c) {
       ph1 += Q.N[c] * phi1[c];
       for (int d = 0; d < 3; ++d) {
@@ -274,12 +282,12 @@ static bool ns_element(const Mesh& m, const Params& p, size_t e, const S v1[8][3
         for (int e2 = 0; e2 < 3; ++e2) Hpht[d][e2] += Q.d2N[c][d][e2] * phit[c];
       }
     }
-    const double ps = phistar(ph1);
-    const double rho = mx.alpha * ps + mx.beta;
-    const double eta = mx.gamma * ps + mx.xi;
-    double geta[3];
-    for (int d = 0; d < 3; ++d) geta[d] = std::fabs(ph1) <= 1.0 ? mx.gamma * gph1[d] : 0.0;
-    double J[3];
+    const S ps = phistar(ph1);
+    const S rho = mx.alpha * ps + mx.beta;
+    const S eta = mx.gamma * ps + mx.xi;
+    S geta[3];
+    for (int d = 0; d < 3; ++d) geta[d] = std::fabs(val(ph1)) <= 1.0 ? mx.gamma * gph1[d] : S(0.0);
+    S J[3];
     for (int d = 0; d < 3; ++d) J[d] = kap * gmut[d];
     // unknown-dependent fields
     S vt[3] = {0.0, 0.0, 0.0}, dv[3] = {0.0, 0.0, 0.0}, gvt[3][3], pt = 0.0, gpt[3];
@@ -305,7 +313,7 @@ static bool ns_element(const Mesh& m, const Params& p, size_t e, const S v1[8][3
       S t = rho * dv[i] / p.dt;
       for (int j = 0; j < 3; ++j) t += rho * vt[j] * gvt[i][j];
       for (int j = 0; j < 3; ++j) t += (1.0 / p.Pe) * J[j] * gvt[i][j];
-      double cap = 0;
+      S cap = 0.0;
       for (int j = 0; j < 3; ++j) cap += gpht[j] * Hpht[i][j];
       t += (p.Cn / p.We) * cap;
       t += (1.0 / p.We) * gpt[i];
@@ -319,7 +327,7 @@ static bool ns_element(const Mesh& m, const Params& p, size_t e, const S v1[8][3
     // stabilisation parameters
     S vGv = G * (vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2]);
     S vGJ = G * (vt[0] * J[0] + vt[1] * J[1] + vt[2] * J[2]);
-    double visc = p.C_I * (eta / (rho * p.Re)) * (eta / (rho * p.Re)) * GG;
+    S visc = p.C_I * (eta / (rho * p.Re)) * (eta / (rho * p.Re)) * GG;
     S bracket = 4.0 / (p.dt * p.dt) + vGv + (1.0 / (rho * p.Pe)) * vGJ + visc;
     if (!(val(bracket) > 0.0)) {
       ok = false;
@@ -383,13 +391,16 @@ static bool element_eval_seeded(const Mesh& m, const Params& p, int block, size_
                                 const double* forcing, double out[8][6], double dout[8][6]) {
   for (int c = 0; c < 8; ++c)
     for (int f = 0; f < 6; ++f) out[c][f] = dout[c][f] = 0.0;
+  Dual phi1[8], mu1[8], v1[8][3], p1[8];
+  for (int c = 0; c < 8; ++c) {
+    phi1[c] = Dual(corner_value(m, e, c, Unew, 0), dc[c][0]);
+    mu1[c] = Dual(corner_value(m, e, c, Unew, 1), dc[c][1]);
+    for (int d = 0; d < 3; ++d) v1[c][d] = Dual(corner_value(m, e, c, Unew, 2 + d), dc[c][2 + d]);
+    p1[c] = Dual(corner_value(m, e, c, Unew, 5), dc[c][5]);
+  }
   if (block == BLOCK_CH) {
-    Dual phi1[8], mu1[8], r[8][2];
-    for (int c = 0; c < 8; ++c) {
-      phi1[c] = Dual(corner_value(m, e, c, Unew, 0), dc[c][0]);
-      mu1[c] = Dual(corner_value(m, e, c, Unew, 1), dc[c][1]);
-    }
-    ch_element<Dual>(m, p, e, phi1, mu1, Uold, Unew, forcing, r);
+    Dual r[8][2];
+    ch_element<Dual>(m, p, e, phi1, mu1, v1, Uold, forcing, r);
     for (int c = 0; c < 8; ++c)
       for (int f = 0; f < 2; ++f) {
         out[c][f] = r[c][f].v;
@@ -397,12 +408,8 @@ static bool element_eval_seeded(const Mesh& m, const Params& p, int block, size_
       }
     return true;
   }
-  Dual v1[8][3], p1[8], r[8][4];
-  for (int c = 0; c < 8; ++c) {
-    for (int d = 0; d < 3; ++d) v1[c][d] = Dual(corner_value(m, e, c, Unew, 2 + d), dc[c][2 + d]);
-    p1[c] = Dual(corner_value(m, e, c, Unew, 5), dc[c][5]);
-  }
-  bool ok = ns_element<Dual>(m, p, e, v1, p1, Uold, Unew, forcing, r);
+  Dual r[8][4];
+  bool ok = ns_element<Dual>(m, p, e, v1, p1, phi1, mu1, Uold, forcing, r);
   for (int c = 0; c < 8; ++c)
     for (int f = 0; f < 4; ++f) {
       out[c][2 + f] = r[c][f].v;
@@ -411,18 +418,22 @@ static bool element_eval_seeded(const Mesh& m, const Params& p, int block, size_
   return ok;
 }
 
+// Seeds: the block's own unknowns (block Jacobian), or all six fields of
+// U^{k+1} (full: the block's rows of the coupled Jacobian).
 static bool element_eval(const Mesh& m, const Params& p, int block, size_t e,
                          const double* Unew, const double* Uold, const double* dU,
-                         const double* forcing, double out[8][6], double dout[8][6]) {
+                         const double* forcing, double out[8][6], double dout[8][6], bool full = false) {
+  const int f0 = block == BLOCK_CH ? 0 : 2, f1 = block == BLOCK_CH ? 2 : 6;
   double dc[8][6];
   for (int c = 0; c < 8; ++c)
-    for (int f = 0; f < 6; ++f) dc[c][f] = dU ? corner_value(m, e, c, dU, f) : 0.0;
+    for (int f = 0; f < 6; ++f)
+      dc[c][f] = (dU && (full || (f >= f0 && f < f1))) ? corner_value(m, e, c, dU, f) : 0.0;
   return element_eval_seeded(m, p, block, e, Unew, Uold, dc, forcing, out, dout);
 }
 
 static std::string assemble(const Mesh& m, const Params& p, int block, const double* Unew,
                             const double* Uold, const double* dU, const double* forcing,
-                            double* out, bool want_derivative) {
+                            double* out, bool want_derivative, bool full = false) {
   const size_t n = m.nodes.size(), E = m.leaves.size();
   std::memset(out, 0, sizeof(double) * n * 6);
   const int f0 = block == BLOCK_CH ? 0 : 2, nf = block == BLOCK_CH ? 2 : 4;
@@ -433,7 +444,7 @@ static std::string assemble(const Mesh& m, const Params& p, int block, const dou
 #pragma omp parallel for schedule(static) reduction(+ : bad)
   for (long e = 0; e < (long)E; ++e) {
     double o[8][6], d[8][6];
-    if (!element_eval(m, p, block, (size_t)e, Unew, Uold, dU, forcing, o, d)) bad += 1;
+    if (!element_eval(m, p, block, (size_t)e, Unew, Uold, dU, forcing, o, d, full)) bad += 1;
     std::memcpy(&ev[(size_t)e * 48], want_derivative ? &d[0][0] : &o[0][0], sizeof(double) * 48);
   }
   if (bad) return "tau_m bracket is not positive";
@@ -457,6 +468,11 @@ std::string residual(const Mesh& m, const Params& p, int block, const double* Un
 std::string jvp(const Mesh& m, const Params& p, int block, const double* Unew,
                 const double* Uold, const double* dU, double* JdU) {
   return assemble(m, p, block, Unew, Uold, dU, nullptr, JdU, true);
+}
+
+std::string jvp_full(const Mesh& m, const Params& p, int block, const double* Unew,
+                     const double* Uold, const double* dU, double* JdU) {
+  return assemble(m, p, block, Unew, Uold, dU, nullptr, JdU, true, true);
 }
 
 std::string residual_rows(const Mesh& m, const Params& p, int block, const double* Unew,

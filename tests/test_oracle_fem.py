@@ -442,3 +442,29 @@ def test_tau_bracket_error(orc, uni3):
     U[:, 2] = 1.0                       # v along +x: v.G.J < 0
     with pytest.raises(RuntimeError, match="tau_m"):
         m.residual(p, NS, U, U)
+
+
+@pytest.mark.parametrize("block", [CH, NS])
+@pytest.mark.parametrize("meshkind", ["uniform4", "adaptive"])
+def test_full_jvp_matches_central_differences(orc, adaptive, block, meshkind):
+    """The block's rows of the coupled Jacobian (derivatives with respect to
+    all six fields, the cross terms included) against central differences of
+    the residual; with the other block's seeds zero it is the block JVP."""
+    m = orc.Mesh((1, 1, 1), 2, 2) if meshkind == "uniform4" else adaptive
+    p = P(orc, dt=0.05)
+    U1, U0 = random_state(m, 15)
+    f = slice(0, 2) if block == CH else slice(2, 6)
+    other = slice(2, 6) if block == CH else slice(0, 2)
+    dU = np.random.default_rng(16).normal(0, 1, U1.shape)
+    Jd = m.jvp_full(p, block, U1, U0, dU)
+    eps = 1e-6 * np.linalg.norm(U1) / np.linalg.norm(dU)
+    fd = (m.residual(p, block, U1 + eps * dU, U0) - m.residual(p, block, U1 - eps * dU, U0)) / (2 * eps)
+    err = np.linalg.norm(fd[:, f] - Jd[:, f]) / np.linalg.norm(Jd[:, f])
+    assert err < 1e-7, err
+    assert np.abs(Jd[:, other]).max() == 0.0
+    # the cross part is there, and without it the block JVP comes back
+    dB = np.zeros_like(dU)
+    dB[:, f] = dU[:, f]
+    assert np.array_equal(m.jvp_full(p, block, U1, U0, dB), m.jvp(p, block, U1, U0, dB))
+    cross = Jd[:, f] - m.jvp(p, block, U1, U0, dB)[:, f]
+    assert np.linalg.norm(cross) > 1e-3 * np.linalg.norm(Jd[:, f])
