@@ -155,6 +155,17 @@ int chns_jvp(chns_mesh* mesh, const chns_params* params, int block, const double
 /* Node-block diagonal of the block Jacobian (2x2 for CH, 4x4 for NS per node,
  * row-major, device, n_nodes*nf*nf doubles), including the hanging-node
  * couplings; boundary rows are identity rows. */
+/* Rows of the coupled Jacobian (both blocks, derivatives with respect to all
+ * six fields of U^{k+1}, the cross terms d R_NS / d(phi, mu) and
+ * d R_CH / d v included) applied to dU (n_nodes*6 in the arithmetic of
+ * prec); JdU gets all six rows per node, the NS boundary rows being identity
+ * rows as in chns_jvp.  The block iteration of Fig. 1 uses the diagonal
+ * blocks only; a fully coupled Newton solve (chns_solver_opts.coupled) uses
+ * this operator.  Computed by forward-mode differentiation (dual numbers) of
+ * the residual kernels. */
+int chns_jvp_full(chns_mesh* mesh, const chns_params* params, const double* U_new, const double* U_old,
+                  const void* dU, void* JdU, int prec, void* stream);
+
 /* Cached linearisation of the NS block.  Within one Newton iteration the
  * state is fixed, so the quantities of Def. 2 that the JVP differentiates
  * around (rho, eta, v~ and its gradient, the mass flux J, the transport

@@ -127,6 +127,7 @@ def lib():
         L.chns_mesh_free.argtypes = [vp]
         L.chns_residual.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp]
         L.chns_jvp.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp, C.c_int, vp]
+        L.chns_jvp_full.argtypes = [vp, C.POINTER(chns_params), vp, vp, vp, vp, C.c_int, vp]
         L.chns_linearize.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, C.c_int, vp]
         L.chns_jvp_lin.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, C.c_int, vp]
         L.chns_diag_blocks.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp]
@@ -209,6 +210,13 @@ def chns_jvp(mesh, params, block, U_new, U_old, dU, JdU, prec=CHNS_F64, stream=N
     _dev(U_new, "float64"), _dev(U_old, "float64"), _dev(dU, dt), _dev(JdU, dt)
     return _check(lib().chns_jvp(mesh, C.byref(params), block, U_new.data_ptr(), U_old.data_ptr(),
                                  dU.data_ptr(), JdU.data_ptr(), prec, _stream(stream)))
+
+
+def chns_jvp_full(mesh, params, U_new, U_old, dU, JdU, prec=CHNS_F64, stream=None):
+    dt = "float64" if prec == CHNS_F64 else "float32"
+    _dev(U_new, "float64"), _dev(U_old, "float64"), _dev(dU, dt), _dev(JdU, dt)
+    return _check(lib().chns_jvp_full(mesh, C.byref(params), U_new.data_ptr(), U_old.data_ptr(),
+                                      dU.data_ptr(), JdU.data_ptr(), prec, _stream(stream)))
 
 
 def chns_linearize(mesh, params, block, U_new, U_old, prec=CHNS_F64, stream=None):
@@ -507,6 +515,13 @@ class Mesh:
         if out is None:
             out = torch.empty_like(U_new)
         chns_residual(self.h, params, block, U_new, U_old, out)
+        return out
+
+    def jvp_full(self, params, U_new, U_old, dU, prec=CHNS_F64, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(dU)
+        chns_jvp_full(self.h, params, U_new, U_old, dU, out, prec)
         return out
 
     def linearize(self, params, block, U_new, U_old, prec=CHNS_F64):

@@ -403,6 +403,29 @@ int launch_jvp(chns_mesh* m, const dev::PhysView& pv, int block, const TS* U1, c
   return CHNS_OK;
 }
 
+// Both blocks' rows of the coupled Jacobian applied to dU (node-major, 6 per
+// node): CH rows, then NS rows (which keep the CH rows).
+template <class T, class TS, class TD>
+int launch_jvp_full(chns_mesh* m, const dev::PhysView& pv, const TS* U1, const TS* U0, const TD* dU, TD* out,
+                    hipStream_t s, const int* skip = nullptr) {
+  const int64_t n = (int64_t)m->h.node_key.size();
+  const auto mv = view(m);
+  const auto pl = plan_view(m);
+  const dim3 g((unsigned)m->n_chunks), b(dev::kChunkThreads);
+  const dev::ChunkCaps cc = caps(m);
+  T* part = (T*)m->d_partial;
+  hipLaunchKernelGGL((dev::k_ch_jvp_full<T, TS, TD>), g, b, (dev::ChunkLDS<T, 5, 5, 2>::bytes(cc)), s, mv, pl, pv,
+                     cc, U1, U0, dU, part, skip);
+  hipLaunchKernelGGL((dev::k_gather<2, T, TD, 0>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part, out, 6, 0,
+                     (const double*)nullptr, (const double*)nullptr, dU, 6, 0, skip);
+  hipLaunchKernelGGL((dev::k_ns_jvp_full<T, TS, TD>), g, b, (dev::ChunkLDS<T, 6, 6, 4>::bytes(cc)), s, mv, pl, pv,
+                     cc, U1, U0, dU, part, skip);
+  hipLaunchKernelGGL((dev::k_gather<4, T, TD, 2, true>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part, out,
+                     6, 2, (const double*)nullptr, (const double*)nullptr, dU, 6, 2, skip);
+  HIPCHK(hipGetLastError());
+  return CHNS_OK;
+}
+
 // Cached NS linearisation points (k_ns_lin) and the JVP that reads them.
 template <class T>
 int ensure_lin(chns_mesh* m) {
@@ -1387,6 +1410,21 @@ int chns_jvp(chns_mesh* m, const chns_params* params, int block, const double* U
   if (prec == CHNS_F32)
     return launch_jvp<float, double, float>(m, pv, block, U_new, U_old, (const float*)dU, 6, off,
                                             (float*)JdU, 6, off, s);
+  return fail(CHNS_EINVAL, "prec must be CHNS_F64 or CHNS_F32");
+}
+
+int chns_jvp_full(chns_mesh* m, const chns_params* params, const double* U_new, const double* U_old,
+                  const void* dU, void* JdU, int prec, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int rc = check_mesh(m, s);
+  if (rc) return rc;
+  dev::PhysView pv;
+  if ((rc = phys_view(params, pv))) return rc;
+  if (!U_new || !U_old || !dU || !JdU) return fail(CHNS_EINVAL, "pointers must not be NULL");
+  if (prec == CHNS_F64)
+    return launch_jvp_full<double, double, double>(m, pv, U_new, U_old, (const double*)dU, (double*)JdU, s);
+  if (prec == CHNS_F32)
+    return launch_jvp_full<float, double, float>(m, pv, U_new, U_old, (const float*)dU, (float*)JdU, s);
   return fail(CHNS_EINVAL, "prec must be CHNS_F64 or CHNS_F32");
 }
 

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "element.hpp"
+#include "dual.hpp"
 
 namespace chns {
 namespace dev {
@@ -165,6 +166,25 @@ struct ChunkLDS {
 };
 
 // ------------------------------------------------------------ CH block ----
+// CH residual rows at the lane's Gauss point, contracted against the test
+// functions of the lane's corner; a / b: the corner's phi, mu, u, v, w at
+// k+1 / k.
+template <class T>
+__device__ __forceinline__ void ch_residual_point(const PhysView& p, const Lane<T>& L, const T (&a)[5],
+                                                  const T (&b)[5], T (&r)[2]) {
+  const VG<T> ph = eval_vg<T>((T)0.5 * (a[0] + b[0]), L);
+  const VG<T> mu = eval_vg<T>((T)0.5 * (a[1] + b[1]), L);
+  const T dphi = eval_v<T>(a[0] - b[0]);
+  const T vx = eval_v<T>((T)0.5 * (a[2] + b[2]));
+  const T vy = eval_v<T>((T)0.5 * (a[3] + b[3]));
+  const T vz = eval_v<T>((T)0.5 * (a[4] + b[4]));
+  const T w = L.wdet, kd = (T)p.inv_PeCn, cn2 = (T)p.Cn2;
+  r[0] = test_contract<T>(w * dphi * (T)p.inv_dt, w * (kd * mu.dx - vx * ph.v),
+                          w * (kd * mu.dy - vy * ph.v), w * (kd * mu.dz - vz * ph.v), L);
+  r[1] = test_contract<T>(w * (ph.v * ph.v * ph.v - ph.v - mu.v), w * cn2 * ph.dx,
+                          w * cn2 * ph.dy, w * cn2 * ph.dz, L);
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_ch_residual(MeshView m, PlanView pl, PhysView p,
                                                      ChunkCaps caps,
@@ -184,18 +204,10 @@ __global__ __launch_bounds__(256) void k_ch_residual(MeshView m, PlanView pl, Ph
   __syncthreads();
   T c[CL::NV];  // phi, mu, u, v, w at k+1, then at k
   S.corner(m, ref, c);
-  const VG<T> ph = eval_vg<T>((T)0.5 * (c[0] + c[5]), L);
-  const VG<T> mu = eval_vg<T>((T)0.5 * (c[1] + c[6]), L);
-  const T dphi = eval_v<T>(c[0] - c[5]);
-  const T vx = eval_v<T>((T)0.5 * (c[2] + c[7]));
-  const T vy = eval_v<T>((T)0.5 * (c[3] + c[8]));
-  const T vz = eval_v<T>((T)0.5 * (c[4] + c[9]));
-  const T w = L.wdet, kd = (T)p.inv_PeCn, cn2 = (T)p.Cn2;
+  const T a[5] = {c[0], c[1], c[2], c[3], c[4]};
+  const T b[5] = {c[5], c[6], c[7], c[8], c[9]};
   T r[2];
-  r[0] = test_contract<T>(w * dphi * (T)p.inv_dt, w * (kd * mu.dx - vx * ph.v),
-                          w * (kd * mu.dy - vy * ph.v), w * (kd * mu.dz - vz * ph.v), L);
-  r[1] = test_contract<T>(w * (ph.v * ph.v * ph.v - ph.v - mu.v), w * cn2 * ph.dx,
-                          w * cn2 * ph.dy, w * cn2 * ph.dz, L);
+  ch_residual_point<T>(p, L, a, b, r);
   S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
 }
 
@@ -598,6 +610,77 @@ __global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, Phy
   S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
 }
 
+// ---------------------------------------------- coupled Jacobian rows ----
+// Rows of one block of the coupled Jacobian applied to dU (all six fields of
+// U^{k+1}): the block's residual evaluated in dual numbers whose derivative
+// parts carry dU, so every dependence (the other block's fields included) is
+// differentiated exactly.
+template <class T, class TS, class TD>
+__global__ __launch_bounds__(256) void k_ch_jvp_full(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
+                                                     const TS* __restrict__ U1, const TS* __restrict__ U0,
+                                                     const TD* __restrict__ dU, T* __restrict__ partial,
+                                                     const int* skip) {
+  if (skip && *skip) return;
+  using D = Dual<T>;
+  extern __shared__ double smem_d[];
+  using CL = ChunkLDS<T, 5, 5, 2>;
+  CL S;
+  S.carve((char*)smem_d, caps);
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int64_t e = e0 < m.E ? e0 : m.E - 1;
+  Lane<D> L;
+  L.init(threadIdx.x & 7, m.level[e]);
+  const int ref = m.elem[e * 8 + L.c];
+  S.stage(pl, U1, U0, dU, 6, 0);
+  __syncthreads();
+  T c[CL::NV];  // phi, mu, u, v, w at k+1, at k, then their directions
+  S.corner(m, ref, c);
+  D a[5], b[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    a[f] = D(c[f], c[10 + f]);
+    b[f] = D(c[5 + f]);
+  }
+  D r[2];
+  ch_residual_point<D>(p, L, a, b, r);
+  const T rt[2] = {r[0].d, r[1].d};
+  S.finish((threadIdx.x >> 3) * 8 + L.c, rt, partial);
+}
+
+template <class T, class TS, class TD>
+__global__ __launch_bounds__(256) void k_ns_jvp_full(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
+                                                     const TS* __restrict__ U1, const TS* __restrict__ U0,
+                                                     const TD* __restrict__ dU, T* __restrict__ partial,
+                                                     const int* skip) {
+  if (skip && *skip) return;
+  using D = Dual<T>;
+  extern __shared__ double smem_d[];
+  using CL = ChunkLDS<T, 6, 6, 4>;
+  CL S;
+  S.carve((char*)smem_d, caps);
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int64_t e = e0 < m.E ? e0 : m.E - 1;
+  Lane<D> L;
+  L.init(threadIdx.x & 7, m.level[e]);
+  const int ref = m.elem[e * 8 + L.c];
+  S.stage(pl, U1, U0, dU, 6, 0);
+  __syncthreads();
+  T c[CL::NV];
+  S.corner(m, ref, c);
+  D a[6], b[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    a[f] = D(c[f], c[12 + f]);
+    b[f] = D(c[6 + f]);
+  }
+  NSPoint<D> P;
+  ns_point<D>(p, L, a, b, P);
+  D r[4];
+  ns_residual_point<D>(p, L, P, r);
+  const T rt[4] = {r[0].d, r[1].d, r[2].d, r[3].d};
+  S.finish((threadIdx.x >> 3) * 8 + L.c, rt, partial);
+}
+
 // -------------------------------------------------------- node gather ----
 // Every node sums its target slots in slot order and writes its rows of the
 // output (ld values per node starting at off; with ld = 6 the other block's
@@ -605,7 +688,7 @@ __global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, Phy
 // MODE 1 (residual) velocity rows v^{k+1} - v^k on boundary nodes and the
 // pressure row p^{k+1} - p^k of the pinned node; MODE 2 (JVP) the identity
 // rows dU.
-template <int NF, class TP, class TO, int MODE>
+template <int NF, class TP, class TO, int MODE, bool KEEP = false>
 __global__ void k_gather(PlanView pl, int64_t n, const TP* __restrict__ partial,
                          TO* __restrict__ out, int ld, int off, const double* __restrict__ U1,
                          const double* __restrict__ U0, const TO* __restrict__ dU, int ldD,
@@ -634,9 +717,9 @@ __global__ void k_gather(PlanView pl, int64_t n, const TP* __restrict__ partial,
       if (b & 2) v[3] = MODE == 1 ? (TO)(U1[i * 6 + 5] - U0[i * 6 + 5]) : dU[i * ldD + offD + 3];
     }
     TO* o = out + i * ld;
-    if (ld == NF) {
+    if (ld == NF || KEEP) {  // KEEP: the other block's entries are left as they are
 #pragma unroll
-      for (int f = 0; f < NF; ++f) o[f] = v[f];
+      for (int f = 0; f < NF; ++f) o[off + f] = v[f];
     } else {
       for (int f = 0; f < ld; ++f) o[f] = (f >= off && f < off + NF) ? v[f - off] : (TO)0;
     }

@@ -112,6 +112,35 @@ def test_jvp_parity(torch, chns, orc, kind, block):
 
 
 @pytest.mark.parametrize("kind", KINDS)
+def test_coupled_jacobian_rows(torch, chns, orc, kind):
+    """chns_jvp_full (dual-number differentiation of both residual kernels)
+    against the oracle's rows of the coupled Jacobian: FP64 to 1e-12, FP32 to
+    1e-4; its cross part is not negligible."""
+    pm, om = mesh_pair(chns, orc, kind)
+    print(f"case jvp_full {kind} E={pm.n_leaves}", flush=True)
+    ph = W.moderate_physics()
+    p = chns.make_params(ph)
+    po = orc.Params.make(**vars(ph))
+    U1, U0 = W.random_state(pm.n_nodes, 220)
+    dU = W.direction(pm.n_nodes, 320)
+    ref = np.zeros_like(U1)
+    ref[:, 0:2] = om.jvp_full(po, CH, U1, U0, dU)[:, 0:2]
+    ref[:, 2:6] = om.jvp_full(po, NS, U1, U0, dU)[:, 2:6]
+    d1, d0 = to_dev(torch, U1), to_dev(torch, U0)
+    J = pm.jvp_full(p, d1, d0, to_dev(torch, dU)).cpu().numpy()
+    compare(J, ref, slice(0, 2), label=f"jvp_full64 CH rows {kind}")
+    compare(J, ref, slice(2, 6), label=f"jvp_full64 NS rows {kind}")
+    J32 = pm.jvp_full(p, d1, d0, to_dev(torch, dU, torch.float32), prec=chns.CHNS_F32)
+    J32 = J32.cpu().numpy().astype(np.float64)
+    compare(J32, ref, slice(0, 6), tol=1e-4, label=f"jvp_full32 {kind}")
+    blockwise = np.zeros_like(U1)
+    for b, f in ((CH, slice(0, 2)), (NS, slice(2, 6))):
+        blockwise[:, f] = om.jvp(po, b, U1, U0, dU)[:, f]
+    if pm.n_leaves > 1:
+        assert np.linalg.norm(ref - blockwise) > 1e-6 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("kind", KINDS)
 def test_cached_linearisation_jvp(torch, chns, orc, kind):
     """chns_jvp_lin after chns_linearize matches the oracle to 1e-12 and
     chns_jvp to rounding (the two kernels may contract multiply-adds across
