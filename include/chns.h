@@ -226,6 +226,14 @@ typedef struct {
   int32_t mg_levels;        /* 0: automatic                                 */
   int32_t mg_smooth;        /* 2                                            */
   int32_t mg_coarse_sweeps; /* 8                                            */
+  int32_t coupled;          /* 0: block iteration of Fig. 1 (a Newton solve
+                               per block, sweeps until the fields settle);
+                               1: one Newton solve of the whole 6-field
+                               system with the coupled Jacobian
+                               (chns_jvp_full) and the two blocks'
+                               preconditioners side by side; newton_max_it_ns
+                               bounds its iterations, and newton_its[1] /
+                               gmres_its[1] of chns_step_stats count them  */
 } chns_solver_opts;
 
 typedef struct {

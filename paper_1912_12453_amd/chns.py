@@ -67,7 +67,7 @@ class chns_solver_opts(C.Structure):
                 ("block_max_it", C.c_int32), ("block_min_it", C.c_int32),
                 ("precision", C.c_int32), ("precond", C.c_int32),
                 ("graphs", C.c_int32), ("mg_omega", C.c_double), ("mg_levels", C.c_int32),
-                ("mg_smooth", C.c_int32), ("mg_coarse_sweeps", C.c_int32)]
+                ("mg_smooth", C.c_int32), ("mg_coarse_sweeps", C.c_int32), ("coupled", C.c_int32)]
 
 
 class chns_step_stats(C.Structure):
@@ -171,11 +171,11 @@ def make_params(physics):
 def make_opts(newton_rtol=1e-8, newton_atol=1e-12, block_tol=1e-4, gmres_rtol=1e-7,
               newton_max_it_ch=20, newton_max_it_ns=40, gmres_restart=120, gmres_max_it=1000,
               block_max_it=10, block_min_it=1, precision=0, precond=1, graphs=1, mg_omega=0.6,
-              mg_levels=0, mg_smooth=2, mg_coarse_sweeps=8):
+              mg_levels=0, mg_smooth=2, mg_coarse_sweeps=8, coupled=0):
     return chns_solver_opts(newton_rtol, newton_atol, block_tol, gmres_rtol, newton_max_it_ch,
                             newton_max_it_ns, gmres_restart, gmres_max_it, block_max_it,
                             block_min_it, precision, precond, graphs, mg_omega, mg_levels, mg_smooth,
-                            mg_coarse_sweeps)
+                            mg_coarse_sweeps, coupled)
 
 
 # ------------------------------------------------ C ABI, same names ------

@@ -77,8 +77,11 @@ struct Workspace {
   int restart64 = 0, restart32 = 0;  // basis length allocated per precision
   double *U1 = nullptr;              // the step's iterate U^{k+1}
   double *Uk = nullptr, *Uprev = nullptr, *r = nullptr, *x = nullptr;
-  double *D = nullptr, *Di = nullptr;
-  float *Di32 = nullptr, *U1f = nullptr, *U0f = nullptr;
+  double *D = nullptr, *Di = nullptr, *DiC = nullptr;  // Di: NS blocks, DiC: CH blocks
+  float *Di32 = nullptr, *DiC32 = nullptr, *U1f = nullptr, *U0f = nullptr;
+  double *pk64 = nullptr, *pz64 = nullptr;  // coupled solve: one block's part of a vector
+  float *pk32 = nullptr, *pz32 = nullptr;
+  int nfw = 4;                              // values per node of the Krylov vectors
   double *V64 = nullptr, *Z64 = nullptr, *w64 = nullptr, *b64 = nullptr;
   float *V32 = nullptr, *Z32 = nullptr, *w32 = nullptr, *b32 = nullptr;
   double *part = nullptr, *dots = nullptr;
@@ -101,7 +104,7 @@ void drop_graphs(Workspace& w) {
 
 void free_basis(Workspace& w, int precision) {
   drop_graphs(w);
-  const int64_t N = w.n * 4;
+  const int64_t N = w.n * w.nfw;
   if (precision == 0) {
     if (w.V64) w.bytes -= (N * (2 * w.restart64 + 3)) * (int64_t)sizeof(double);
     void* ptrs[] = {w.V64, w.Z64, w.w64, w.b64};
@@ -123,7 +126,8 @@ void free_basis(Workspace& w, int precision) {
 void free_workspace(Workspace& w) {
   free_basis(w, 0);
   free_basis(w, 1);
-  void* ptrs[] = {w.U1, w.Uk, w.Uprev, w.r, w.x, w.D, w.Di, w.Di32, w.part, w.dots, w.flag, w.ctl};
+  void* ptrs[] = {w.U1, w.Uk, w.Uprev, w.r, w.x, w.D, w.Di, w.Di32, w.DiC, w.DiC32, w.pk64, w.pz64, w.pk32,
+                  w.pz32, w.part, w.dots, w.flag, w.ctl};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (w.hdots) (void)hipHostFree(w.hdots);
@@ -140,8 +144,8 @@ struct MGLevel {
   int64_t n = 0;
   int32_t *p_off = nullptr, *p_idx = nullptr, *r_off = nullptr, *r_idx = nullptr, *inj = nullptr;
   double *p_w = nullptr, *r_w = nullptr;
-  double *U1 = nullptr, *U0 = nullptr, *D = nullptr, *Di = nullptr;  // levels >= 1
-  float *U1f = nullptr, *U0f = nullptr, *Di32 = nullptr;
+  double *U1 = nullptr, *U0 = nullptr, *D = nullptr, *Di = nullptr, *DiC = nullptr;  // levels >= 1
+  float *U1f = nullptr, *U0f = nullptr, *Di32 = nullptr, *DiC32 = nullptr;
   double *b64 = nullptr, *x64 = nullptr, *r64 = nullptr;
   float *b32 = nullptr, *x32 = nullptr, *r32 = nullptr;
 };
@@ -347,7 +351,8 @@ int check_mesh(chns_mesh* m, hipStream_t s) {
 // Element kernel (one workgroup per chunk of 32 leaves) writing the chunk's
 // target partials, then the node gather writing every row of the output.
 int launch_residual(chns_mesh* m, const dev::PhysView& pv, int block, const double* U1,
-                    const double* U0, double* R, int ld, int off, hipStream_t s, bool check_tau) {
+                    const double* U0, double* R, int ld, int off, hipStream_t s, bool check_tau,
+                    bool keep = false) {
   const int64_t n = (int64_t)m->h.node_key.size();
   const auto mv = view(m);
   const auto pl = plan_view(m);
@@ -365,8 +370,12 @@ int launch_residual(chns_mesh* m, const dev::PhysView& pv, int block, const doub
   hipLaunchKernelGGL(dev::k_fill<int>, dim3(1), dim3(64), 0, s, m->d_flag, (int64_t)1, 0);
   hipLaunchKernelGGL(dev::k_ns_residual<double>, g, b, (dev::ChunkLDS<double, 6, 0, 4>::bytes(cc)), s, mv,
                      pl, pv, cc, U1, U0, part, m->d_flag);
-  hipLaunchKernelGGL((dev::k_gather<4, double, double, 1>), dim3(grid_stride(n)), dim3(256), 0, s, pl,
-                     n, part, R, ld, off, U1, U0, (const double*)nullptr, 0, 0, (const int*)nullptr);
+  if (keep)  // the CH entries of R are left as they are
+    hipLaunchKernelGGL((dev::k_gather<4, double, double, 1, true>), dim3(grid_stride(n)), dim3(256), 0, s, pl,
+                       n, part, R, ld, off, U1, U0, (const double*)nullptr, 0, 0, (const int*)nullptr);
+  else
+    hipLaunchKernelGGL((dev::k_gather<4, double, double, 1>), dim3(grid_stride(n)), dim3(256), 0, s, pl,
+                       n, part, R, ld, off, U1, U0, (const double*)nullptr, 0, 0, (const int*)nullptr);
   HIPCHK(hipGetLastError());
   if (check_tau) {
     HIPCHK(hipMemcpyAsync(m->h_flag, m->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -516,7 +525,8 @@ int mg_alloc_level(MGLevel& L, bool coarse) {
   if ((rc = dalloc(&L.U1, 6 * n, nullptr)) || (rc = dalloc(&L.U0, 6 * n, nullptr)) ||
       (rc = dalloc(&L.U1f, 6 * n, nullptr)) || (rc = dalloc(&L.U0f, 6 * n, nullptr)) ||
       (rc = dalloc(&L.D, 16 * n, nullptr)) || (rc = dalloc(&L.Di, 16 * n, nullptr)) ||
-      (rc = dalloc(&L.Di32, 16 * n, nullptr)) || (rc = dalloc(&L.b64, 4 * n, nullptr)) ||
+      (rc = dalloc(&L.Di32, 16 * n, nullptr)) || (rc = dalloc(&L.DiC, 4 * n, nullptr)) ||
+      (rc = dalloc(&L.DiC32, 4 * n, nullptr)) || (rc = dalloc(&L.b64, 4 * n, nullptr)) ||
       (rc = dalloc(&L.x64, 4 * n, nullptr)) || (rc = dalloc(&L.b32, 4 * n, nullptr)) ||
       (rc = dalloc(&L.x32, 4 * n, nullptr)))
     return rc;
@@ -600,6 +610,11 @@ int build_mg(chns_mesh* m, int levels, hipStream_t s) {
 }
 
 // --------------------------------------------------------------- solver ----
+// The whole 6-field system of the fully coupled Newton solve (an internal
+// block id next to CHNS_BLOCK_CH and CHNS_BLOCK_NS).
+constexpr int kCoupled = 2;
+inline int nf_of(int block) { return block == CHNS_BLOCK_CH ? 2 : (block == CHNS_BLOCK_NS ? 4 : 6); }
+
 struct Solver {
   const std::atomic<bool>* cancel = nullptr;  // set by a server that is shutting down
   chns_mesh* m;
@@ -617,14 +632,19 @@ struct Solver {
     std::lock_guard<std::mutex> lk(g_struct_mu);
     int rc;
     int64_t& B = w.bytes;
-    const size_t N = (size_t)n * 4;
-    if (w.n != n) {
+    const int nfw = o.coupled ? 6 : 4;
+    const size_t N = (size_t)n * std::max(nfw, w.n == n ? w.nfw : 0);
+    if (w.n != n || w.nfw < nfw) {
       free_workspace(w);
+      w.nfw = nfw;
       w.nb_part = (int)grid_stride((int64_t)N, 256, 1024);
       if ((rc = dalloc(&w.U1, n * 6, &B)) || (rc = dalloc(&w.Uk, n * 6, &B)) ||
           (rc = dalloc(&w.Uprev, n * 6, &B)) || (rc = dalloc(&w.r, N, &B)) || (rc = dalloc(&w.x, N, &B)) ||
           (rc = dalloc(&w.D, n * 16, &B)) || (rc = dalloc(&w.Di, n * 16, &B)) ||
-          (rc = dalloc(&w.Di32, n * 16, &B)) ||
+          (rc = dalloc(&w.Di32, n * 16, &B)) || (rc = dalloc(&w.DiC, n * 4, &B)) ||
+          (rc = dalloc(&w.DiC32, n * 4, &B)) || (rc = dalloc(&w.pk64, n * 4, &B)) ||
+          (rc = dalloc(&w.pz64, n * 4, &B)) || (rc = dalloc(&w.pk32, n * 4, &B)) ||
+          (rc = dalloc(&w.pz32, n * 4, &B)) ||
           (rc = dalloc(&w.part, (size_t)w.nb_part * (dev::kMaxBasis + 1), &B)) ||
           (rc = dalloc(&w.dots, dev::kMaxBasis + 1, &B)) || (rc = dalloc(&w.flag, 1, &B)) ||
           (rc = dalloc(&w.ctl, 1, &B))) {
@@ -683,6 +703,11 @@ struct Solver {
   template <class TV>
   int apply(int block, const TV* x, TV* y, const double* U1, const double* U0, const int* skip) {
     const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+    if (block == kCoupled) {
+      if (std::is_same<TV, double>::value)
+        return launch_jvp_full<double, double, TV>(m, pv, (const double*)U1, (const double*)U0, x, y, s, skip);
+      return launch_jvp_full<float, float, TV>(m, pv, w.U1f, w.U0f, x, y, s, skip);
+    }
     if (block == CHNS_BLOCK_NS) return launch_jvp_lin<TV, TV>(m, pv, x, nf, 0, y, nf, 0, s, skip);
     if (std::is_same<TV, double>::value)
       return launch_jvp<double, double, TV>(m, pv, block, U1, U0, x, nf, 0, y, nf, 0, s, skip);
@@ -691,6 +716,7 @@ struct Solver {
 
   template <class TV>
   int precondition(int block, const TV* v, TV* z, const int* skip, const double* U1, const double* U0) {
+    if (block == kCoupled) return precondition_coupled<TV>(v, z, skip, U1, U0);
     if (o.precond == 2) {
       if (block == CHNS_BLOCK_CH) return vcycle<TV, 2>(block, 0, v, z, skip, U1, U0);
       return vcycle<TV, 4>(block, 0, v, z, skip, U1, U0);
@@ -698,14 +724,33 @@ struct Solver {
     const dim3 g(grid_stride(n)), b(256);
     if (block == CHNS_BLOCK_CH) {
       if (std::is_same<TV, double>::value)
-        hipLaunchKernelGGL((dev::k_precond<2, TV, double>), g, b, 0, s, w.Di, v, z, n, skip);
+        hipLaunchKernelGGL((dev::k_precond<2, TV, double>), g, b, 0, s, w.DiC, v, z, n, skip);
       else
-        hipLaunchKernelGGL((dev::k_precond<2, TV, float>), g, b, 0, s, w.Di32, v, z, n, skip);
+        hipLaunchKernelGGL((dev::k_precond<2, TV, float>), g, b, 0, s, w.DiC32, v, z, n, skip);
     } else {
       if (std::is_same<TV, double>::value)
         hipLaunchKernelGGL((dev::k_precond<4, TV, double>), g, b, 0, s, w.Di, v, z, n, skip);
       else
         hipLaunchKernelGGL((dev::k_precond<4, TV, float>), g, b, 0, s, w.Di32, v, z, n, skip);
+    }
+    HIPCHK(hipGetLastError());
+    return CHNS_OK;
+  }
+
+  // Coupled system: the two blocks' preconditioners side by side (the cross
+  // blocks of the Jacobian are left out of the preconditioner).
+  template <class TV>
+  int precondition_coupled(const TV* v, TV* z, const int* skip, const double* U1, const double* U0) {
+    const bool dbl = std::is_same<TV, double>::value;
+    TV* pk = dbl ? (TV*)w.pk64 : (TV*)w.pk32;
+    TV* pz = dbl ? (TV*)w.pz64 : (TV*)w.pz32;
+    const dim3 g(grid_stride(n)), b(256);
+    int rc;
+    for (int blk : {CHNS_BLOCK_CH, CHNS_BLOCK_NS}) {
+      const int nf = blk == CHNS_BLOCK_CH ? 2 : 4, off = blk == CHNS_BLOCK_CH ? 0 : 2;
+      hipLaunchKernelGGL(dev::k_pack<TV>, g, b, 0, s, v, 6, off, nf, n, pk, skip);
+      if ((rc = precondition<TV>(blk, pk, pz, skip, U1, U0))) return rc;
+      hipLaunchKernelGGL(dev::k_unpack<TV>, g, b, 0, s, pz, nf, n, z, 6, off, skip);
     }
     HIPCHK(hipGetLastError());
     return CHNS_OK;
@@ -722,7 +767,9 @@ struct Solver {
     const int64_t nl = L.n, N = nl * NF;
     const bool dbl = std::is_same<TV, double>::value;
     TV* r = dbl ? (TV*)L.r64 : (TV*)L.r32;
-    const TM* Di = l == 0 ? (dbl ? (const TM*)w.Di : (const TM*)w.Di32) : (dbl ? (const TM*)L.Di : (const TM*)L.Di32);
+    const bool ch = block == CHNS_BLOCK_CH;
+    const TM* Di = l == 0 ? (dbl ? (const TM*)(ch ? w.DiC : w.Di) : (const TM*)(ch ? w.DiC32 : w.Di32))
+                          : (dbl ? (const TM*)(ch ? L.DiC : L.Di) : (const TM*)(ch ? L.DiC32 : L.Di32));
     const TV* S1 = l == 0 ? (dbl ? (const TV*)U1 : (const TV*)w.U1f) : (dbl ? (const TV*)L.U1 : (const TV*)L.U1f);
     const TV* S0 = l == 0 ? (dbl ? (const TV*)U0 : (const TV*)w.U0f) : (dbl ? (const TV*)L.U0 : (const TV*)L.U0f);
     const dim3 g(grid_stride(nl)), gs(grid_stride(N)), bl(256);
@@ -784,7 +831,7 @@ struct Solver {
         if (rc) return rc;
       }
       if (nf == 2)
-        hipLaunchKernelGGL(dev::k_invert_blocks<2>, dim3(grid_for(C.n)), b, 0, s, C.D, C.Di, C.Di32, C.n, 0,
+        hipLaunchKernelGGL(dev::k_invert_blocks<2>, dim3(grid_for(C.n)), b, 0, s, C.D, C.DiC, C.DiC32, C.n, 0,
                            w.flag);
       else
         hipLaunchKernelGGL(dev::k_invert_blocks<4>, dim3(grid_for(C.n)), b, 0, s, C.D, C.Di, C.Di32, C.n, 0,
@@ -805,7 +852,7 @@ struct Solver {
   template <class TV>
   int enqueue_steps(int block, TV* V, TV* Z, TV* wv, const double* U1, const double* U0, int k0,
                     int k1) {
-    const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+    const int nf = nf_of(block);
     const int64_t N = n * nf;
     dev::GmresCtl* C = w.ctl;
     const int* idle = &C->idle;
@@ -834,7 +881,7 @@ struct Solver {
 
   template <class TV>
   int enqueue_tail(int block, TV* V, TV* Z, TV* wv, const TV* bvec, const double* U1, const double* U0) {
-    const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+    const int nf = nf_of(block);
     const int64_t N = n * nf;
     dev::GmresCtl* C = w.ctl;
     const int* fin = &C->finished;
@@ -924,7 +971,7 @@ struct Solver {
   template <class TV>
   int gmres(int block, TV* V, TV* Z, TV* wv, TV* bvec, const double* U1, const double* U0,
             int* its) {
-    const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
+    const int nf = nf_of(block);
     const int64_t N = n * nf;
     const int mres = std::max(1, std::min(o.gmres_restart, dev::kMaxBasis - 1));
     const int nseg = (mres + kSegment - 1) / kSegment;
@@ -955,9 +1002,15 @@ struct Solver {
   }
 
   int residual_norm(int block, double* U, double* rn) {
-    const int nf = block == CHNS_BLOCK_CH ? 2 : 4;
-    int rc = launch_residual(m, pv, block, U, w.Uk, w.r, nf, 0, s, block == CHNS_BLOCK_NS);
-    if (rc) return rc;
+    const int nf = nf_of(block);
+    int rc;
+    if (block == kCoupled) {  // both blocks' rows, node-major 6 per node
+      if ((rc = launch_residual(m, pv, CHNS_BLOCK_CH, U, w.Uk, w.r, 6, 0, s, false)) ||
+          (rc = launch_residual(m, pv, CHNS_BLOCK_NS, U, w.Uk, w.r, 6, 2, s, true, true)))
+        return rc;
+    } else if ((rc = launch_residual(m, pv, block, U, w.Uk, w.r, nf, 0, s, block == CHNS_BLOCK_NS))) {
+      return rc;
+    }
     double d;
     if ((rc = dots<double>(w.r, 0, 1, w.r, n * nf, &d))) return rc;
     *rn = std::sqrt(d);
@@ -984,7 +1037,7 @@ struct Solver {
       if ((rc = launch_diag(m, pv, block, U, w.Uk, w.D, s))) return rc;
       hipLaunchKernelGGL(dev::k_fill<int>, dim3(1), dim3(64), 0, s, w.flag, (int64_t)1, 0);
       if (nf == 2)
-        hipLaunchKernelGGL(dev::k_invert_blocks<2>, dim3(grid_for(n)), dim3(256), 0, s, w.D, w.Di, w.Di32,
+        hipLaunchKernelGGL(dev::k_invert_blocks<2>, dim3(grid_for(n)), dim3(256), 0, s, w.D, w.DiC, w.DiC32,
                            n, o.precond == 0 ? 1 : 0, w.flag);
       else
         hipLaunchKernelGGL(dev::k_invert_blocks<4>, dim3(grid_for(n)), dim3(256), 0, s, w.D, w.Di, w.Di32,
@@ -1017,6 +1070,60 @@ struct Solver {
     return CHNS_OK;
   }
 
+  // Newton on the whole 6-field system R(U^{k+1}) = [R_CH; R_NS] = 0 with the
+  // coupled Jacobian (no block iteration); the preconditioner is the two
+  // blocks' own (node-block Jacobi or the multigrid V-cycle), side by side.
+  int newton_coupled(double* U, int* nits, int* gits, double* relres, bool* conv) {
+    const int64_t N = n * 6;
+    double r0, rn;
+    int rc = residual_norm(kCoupled, U, &r0);
+    if (rc) return rc;
+    rn = r0;
+    *conv = false;
+    for (;;) {
+      if (!std::isfinite(rn)) return fail(CHNS_ENONFINITE, "non-finite Newton residual");
+      if (rn <= std::max(o.newton_rtol * r0, o.newton_atol)) {
+        *conv = true;
+        break;
+      }
+      if (*nits >= o.newton_max_it_ns) break;
+      if (cancelled()) return fail(CHNS_ECANCELED, "step cancelled");
+      hipLaunchKernelGGL(dev::k_fill<int>, dim3(1), dim3(64), 0, s, w.flag, (int64_t)1, 0);
+      if ((rc = launch_diag(m, pv, CHNS_BLOCK_CH, U, w.Uk, w.D, s))) return rc;
+      hipLaunchKernelGGL(dev::k_invert_blocks<2>, dim3(grid_for(n)), dim3(256), 0, s, w.D, w.DiC, w.DiC32, n,
+                         o.precond == 0 ? 1 : 0, w.flag);
+      if ((rc = launch_diag(m, pv, CHNS_BLOCK_NS, U, w.Uk, w.D, s))) return rc;
+      hipLaunchKernelGGL(dev::k_invert_blocks<4>, dim3(grid_for(n)), dim3(256), 0, s, w.D, w.Di, w.Di32, n,
+                         o.precond == 0 ? 1 : 0, w.flag);
+      HIPCHK(hipGetLastError());
+      if (o.precond == 2 && ((rc = mg_setup(CHNS_BLOCK_CH, U, w.Uk)) || (rc = mg_setup(CHNS_BLOCK_NS, U, w.Uk))))
+        return rc;
+      int its = 0;
+      if (o.precision == 0) {
+        hipLaunchKernelGGL((dev::k_scale<double, double>), dim3(grid_stride(N)), dim3(256), 0, s, w.b64, w.r,
+                           -1.0, N);
+        if (o.precond == 2 && (rc = launch_ns_lin<double, double>(m, pv, U, w.Uk, s))) return rc;
+        rc = gmres<double>(kCoupled, w.V64, w.Z64, w.w64, w.b64, U, w.Uk, &its);
+      } else {
+        hipLaunchKernelGGL((dev::k_convert<double, float>), dim3(grid_stride(n * 6)), dim3(256), 0, s, U,
+                           w.U1f, n * 6, (const int*)nullptr);
+        hipLaunchKernelGGL((dev::k_convert<double, float>), dim3(grid_stride(n * 6)), dim3(256), 0, s, w.Uk,
+                           w.U0f, n * 6, (const int*)nullptr);
+        hipLaunchKernelGGL((dev::k_scale<double, float>), dim3(grid_stride(N)), dim3(256), 0, s, w.b32, w.r,
+                           -1.0, N);
+        if (o.precond == 2 && (rc = launch_ns_lin<float, float>(m, pv, w.U1f, w.U0f, s))) return rc;
+        rc = gmres<float>(kCoupled, w.V32, w.Z32, w.w32, w.b32, U, w.Uk, &its);
+      }
+      if (rc) return rc;
+      *gits += its;
+      hipLaunchKernelGGL(dev::k_add_block<double>, dim3(grid_stride(N)), dim3(256), 0, s, U, w.x, n, 0, 6, 1.0);
+      ++*nits;
+      if ((rc = residual_norm(kCoupled, U, &rn))) return rc;
+    }
+    *relres = r0 > 0 ? rn / r0 : 0.0;
+    return CHNS_OK;
+  }
+
   int max_change(const double* a, const double* b, double* out) {
     const int64_t N = n * 6;
     hipLaunchKernelGGL(dev::k_maxabs_diff, dim3(w.nb_part), dim3(256), 0, s, a, b, N, w.part);
@@ -1041,7 +1148,18 @@ struct Solver {
     for (int b : {CHNS_BLOCK_CH, CHNS_BLOCK_NS})
       if ((rc = residual_norm(b, U, &r_init[b]))) return rc;
     bool all_conv = true, block_conv = false;
-    for (int l = 0; l < o.block_max_it; ++l) {
+    if (o.coupled) {  // one Newton solve of the whole system replaces the block iteration
+      int nits = 0, gits = 0;
+      double rr = 0;
+      bool conv = false;
+      if ((rc = newton_coupled(U, &nits, &gits, &rr, &conv))) return rc;
+      st->block_its = 1;
+      st->newton_its[CHNS_BLOCK_NS] = nits;
+      st->gmres_its[CHNS_BLOCK_NS] = gits;
+      all_conv = conv;
+      block_conv = true;
+    }
+    for (int l = 0; !o.coupled && l < o.block_max_it; ++l) {
       HIPCHK(hipMemcpyAsync(w.Uprev, U, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
       for (int b : {CHNS_BLOCK_NS, CHNS_BLOCK_CH}) {
         int nits = 0, gits = 0;
@@ -1082,6 +1200,7 @@ int check_opts(const chns_solver_opts* opts) {
     return fail(CHNS_EINVAL, "gmres_restart must be in [1, " + std::to_string(dev::kMaxBasis - 1) + "]");
   if (opts->precision != 0 && opts->precision != 1) return fail(CHNS_EINVAL, "precision must be 0 or 1");
   if (opts->precond < 0 || opts->precond > 2) return fail(CHNS_EINVAL, "precond must be 0, 1 or 2");
+  if (opts->coupled != 0 && opts->coupled != 1) return fail(CHNS_EINVAL, "coupled must be 0 or 1");
   if (opts->precond == 2) {
     if (!(opts->mg_omega > 0.0 && opts->mg_omega < 2.0)) return fail(CHNS_EINVAL, "mg_omega must be in (0, 2)");
     if (opts->mg_smooth < 1 || opts->mg_smooth > 16 || opts->mg_coarse_sweeps < 1 ||
@@ -1354,7 +1473,7 @@ void free_mg_locked(chns_mesh* m) {
   for (size_t l = 0; l < m->mg.size(); ++l) {
     MGLevel& L = m->mg[l];
     void* ptrs[] = {L.p_off, L.p_idx, L.r_off, L.r_idx, L.inj, L.p_w, L.r_w, L.U1, L.U0, L.D, L.Di,
-                    L.U1f, L.U0f, L.Di32, L.b64, L.x64, L.r64, L.b32, L.x32, L.r32};
+                    L.DiC, L.U1f, L.U0f, L.Di32, L.DiC32, L.b64, L.x64, L.r64, L.b32, L.x32, L.r32};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     if (l > 0 && L.mesh) free_mesh_locked(L.mesh);

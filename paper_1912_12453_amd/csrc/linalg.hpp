@@ -340,6 +340,30 @@ __global__ void k_gmres_restart(GmresCtl* __restrict__ C, const double* __restri
   C->idle = 0;
 }
 
+// out[i*nf + f] = v[i*ld + off + f]: one block's part of a node-major vector
+template <class TV>
+__global__ void k_pack(const TV* __restrict__ v, int ld, int off, int nf, int64_t n, TV* __restrict__ out,
+                       const int* skip) {
+  if (skipped(skip)) return;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * nf;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t / nf;
+    out[t] = v[i * ld + off + (t - i * nf)];
+  }
+}
+
+// z[i*ld + off + f] = in[i*nf + f]
+template <class TV>
+__global__ void k_unpack(const TV* __restrict__ in, int nf, int64_t n, TV* __restrict__ z, int ld, int off,
+                         const int* skip) {
+  if (skipped(skip)) return;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * nf;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t / nf;
+    z[i * ld + off + (t - i * nf)] = in[t];
+  }
+}
+
 // y = a * x
 template <class TA, class TB>
 __global__ void k_scale(TB* __restrict__ y, const TA* __restrict__ x, double a, int64_t n) {
