@@ -19,10 +19,11 @@ cached linearisation points), timed live with HIP events on the stream it is
 launched on, against the roof it is closer to (HBM bytes or VALU flops).  The CPU baseline is the FP64 oracle
 (test infrastructure) computing the same 6-DoF JVP on the same mesh and state.
 
-The cn_steps object times full Crank-Nicolson steps (block iteration,
-Newton to 1e-8, GMRES(120) preconditioned by the octree multigrid V-cycle),
-FP64 and mixed precision, on the 16^3 drop and on the workload itself
-(bubble: v = 0 start), with the mixed trajectory's error against FP64.
+The cn_steps object times full Crank-Nicolson steps (Newton to 1e-8,
+GMRES(120) preconditioned by the octree multigrid V-cycle), FP64 and mixed
+precision, on the 16^3 drop and on the workload itself (bubble: v = 0 start),
+with the mixed trajectory's error against FP64: once with the block
+iteration of Fig. 1 and once with the fully coupled Newton solve.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
                        [--workload bubble_l9|bubble_l8|drop16|rt_l10] [--no-cpu-baseline]
@@ -57,7 +58,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cn_steps(chns, W, torch, dev, name, nsteps, precond, restart=120):
+def cn_steps(chns, W, torch, dev, name, nsteps, precond, restart=120, coupled=0):
     """Consecutive Crank-Nicolson steps to the 1e-8 relative Newton residual,
     FP64 and mixed precision from the same U^0: steps/s, p50/p99 step
     latency, solver counts, energy trace, mass drift, and the field error of
@@ -75,10 +76,12 @@ def cn_steps(chns, W, torch, dev, name, nsteps, precond, restart=120):
     p = chns.make_params(w.physics)
     out = {"workload": name, "nodes": mesh.n_nodes, "leaves": mesh.n_leaves, "newton_rtol": 1e-8,
            "gmres_restart": restart,
+           "newton": "fully coupled" if coupled else "block iteration (Fig. 1)",
            "precond": {1: "node-block Jacobi", 2: "octree multigrid V-cycle"}[precond], "steps": nsteps}
     finals = {}
     for prec, pname, grtol in ((0, "fp64", 1e-7), (1, "mixed", 1e-5)):
-        opts = chns.make_opts(precision=prec, gmres_rtol=grtol, gmres_restart=restart, precond=precond)
+        opts = chns.make_opts(precision=prec, gmres_rtol=grtol, gmres_restart=restart, precond=precond,
+                              coupled=coupled)
         U = torch.tensor(U0, device=dev)
         rc, st = mesh.step(p, opts, U)  # warm-up: workspace, hierarchy and graph capture
         log(f"[bench] cn warm-up {name} {pname}: rc {rc}, gmres {list(st.gmres_its)}")
@@ -323,8 +326,11 @@ def main():
     # ---- full Crank-Nicolson steps at the 1e-8 Newton tolerance, FP64 vs mixed
     steps = None
     if not args.no_steps:
-        steps = {"drop16": cn_steps(chns, W, torch, dev, "drop16", args.cn_steps, 2),
-                 name: cn_steps(chns, W, torch, dev, name, args.cn_steps_large, 2, args.cn_restart)}
+        steps = {}
+        for coupled, tag in ((0, ""), (1, "_coupled")):
+            steps["drop16" + tag] = cn_steps(chns, W, torch, dev, "drop16", args.cn_steps, 2, 120, coupled)
+            steps[name + tag] = cn_steps(chns, W, torch, dev, name, args.cn_steps_large, 2, args.cn_restart,
+                                         coupled)
 
     # ---- CPU baseline: the oracle's 6-DoF JVP on the same mesh and state
     cpu = None
