@@ -139,7 +139,7 @@ def serving_main(args):
     # for minutes: such steps end NOT_CONVERGED and are counted as such
     opts = chns.make_opts(precision=1, gmres_rtol=1e-5, gmres_restart=60, precond=2,
                           gmres_max_it=args.serve_gmres_max_it, newton_max_it_ch=8,
-                          newton_max_it_ns=8, block_max_it=3)
+                          newton_max_it_ns=8, block_max_it=3, coupled=args.serve_coupled)
     srv = chns.Server(args.serve_budget_gib << 30, args.serve_max_resident, opts)
     summ, per = serving.run_stream(srv, reqs, log=log, max_wall_s=args.serve_max_wall_s)
     srv.close()
@@ -152,7 +152,8 @@ def serving_main(args):
                       "levels": [args.serve_level_min, args.serve_level_max],
                       "steps_per_request": args.serve_steps, "budget_gib": args.serve_budget_gib,
                       "max_resident": args.serve_max_resident,
-                      "gmres_max_it": args.serve_gmres_max_it},
+                      "gmres_max_it": args.serve_gmres_max_it,
+                      "newton": "fully coupled" if args.serve_coupled else "block iteration"},
            "serving": summ,
            "largest_requests": sorted(({"nodes": p["nodes"], "latency_ms": [round(x, 1) for x in p["latency_ms"]]}
                                        for p in per), key=lambda d: -d["nodes"])[:3],
@@ -186,6 +187,7 @@ def main():
     ap.add_argument("--serve-max-resident", type=int, default=16)
     ap.add_argument("--serve-gmres-max-it", type=int, default=60)
     ap.add_argument("--serve-max-wall-s", type=float, default=900.0)
+    ap.add_argument("--serve-coupled", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
