@@ -168,10 +168,11 @@ int chns_jvp_full(chns_mesh* mesh, const chns_params* params, const double* U_ne
 
 /* Cached linearisation of the NS block.  Within one Newton iteration the
  * state is fixed, so the quantities of Def. 2 that the JVP differentiates
- * around (rho, eta, v~ and its gradient, the mass flux J, the transport
- * velocity of R_m, R_m, R_c, tau_m, tau_c: 27 values per Gauss point) can be
- * evaluated once.  chns_linearize does that for (U_new, U_old) and keeps the
- * values with the mesh (device memory, 27 * 8 values per element in the
+ * around can be evaluated once: phi^{k+1} pulled back to [-1,1], v~ and its
+ * gradient, the mass flux J, the transport velocity of R_m and R_m, 22 values
+ * per Gauss point, from which rho, eta, R_c, tau_m and tau_c follow in a few
+ * operations.  chns_linearize does that for (U_new, U_old) and keeps the
+ * values with the mesh (device memory, 22 * 8 values per element in the
  * arithmetic of prec, allocated on first use); chns_jvp_lin then applies
  * the chns_jvp of that state and prec to dU (same layout; same results up
  * to rounding, since the compiler may contract multiply-adds differently in

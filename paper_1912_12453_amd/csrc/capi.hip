@@ -162,6 +162,7 @@ struct chns_mesh {
   uint8_t* d_level = nullptr;
   // scatter plan
   int32_t *d_tgt_off = nullptr, *d_tgt = nullptr, *d_inc_off = nullptr, *d_node_off = nullptr, *d_node_slot = nullptr;
+  int32_t* d_chunk_inc = nullptr;
   uint8_t *d_inc_corner = nullptr, *d_bflags = nullptr;
   float* d_inc_w = nullptr;
   int64_t *d_touch_off = nullptr, *d_ntouch_off = nullptr, *d_ntouch_slot = nullptr;
@@ -210,6 +211,7 @@ dev::PlanView plan_view(const chns_mesh* m) {
   v.tgt_off = m->d_tgt_off;
   v.tgt = m->d_tgt;
   v.inc_off = m->d_inc_off;
+  v.chunk_inc = m->d_chunk_inc;
   v.inc_corner = m->d_inc_corner;
   v.inc_w = m->d_inc_w;
   v.node_off = m->d_node_off;
@@ -304,6 +306,7 @@ int upload(chns_mesh* m, hipStream_t s) {
       (rc = dalloc(&m->d_part, E * 2, &B)) || (rc = dalloc(&m->d_sum, 2, &B)) ||
       (rc = dalloc(&m->d_tgt_off, P.tgt_off.size(), &B)) || (rc = dalloc(&m->d_tgt, P.tgt.size(), &B)) ||
       (rc = dalloc(&m->d_inc_off, P.inc_off.size(), &B)) ||
+      (rc = dalloc(&m->d_chunk_inc, P.chunk_inc.size(), &B)) ||
       (rc = dalloc(&m->d_inc_corner, P.inc_corner.size(), &B)) ||
       (rc = dalloc(&m->d_inc_w, P.inc_w.size(), &B)) ||
       (rc = dalloc(&m->d_node_off, P.node_off.size(), &B)) ||
@@ -320,7 +323,8 @@ int upload(chns_mesh* m, hipStream_t s) {
       (rc = h2d(m->d_anchor, anchor, s)) || (rc = h2d(m->d_hoff, h.hang_off, s)) ||
       (rc = h2d(m->d_hids, h.hang_ids, s)) || (rc = h2d(m->d_hw, h.hang_w, s)) ||
       (rc = h2d(m->d_hw32, w32, s)) || (rc = h2d(m->d_tgt_off, P.tgt_off, s)) || (rc = h2d(m->d_tgt, P.tgt, s)) ||
-      (rc = h2d(m->d_inc_off, P.inc_off, s)) || (rc = h2d(m->d_inc_corner, P.inc_corner, s)) ||
+      (rc = h2d(m->d_inc_off, P.inc_off, s)) || (rc = h2d(m->d_chunk_inc, P.chunk_inc, s)) ||
+      (rc = h2d(m->d_inc_corner, P.inc_corner, s)) ||
       (rc = h2d(m->d_inc_w, P.inc_w, s)) || (rc = h2d(m->d_node_off, P.node_off, s)) ||
       (rc = h2d(m->d_node_slot, P.node_slot, s)) || (rc = h2d(m->d_touch_off, P.touch_off, s)) ||
       (rc = h2d(m->d_ntouch_off, P.ntouch_off, s)) ||
@@ -471,7 +475,7 @@ int launch_jvp_lin(chns_mesh* m, const dev::PhysView& pv, const TD* dU, int ldD,
   T* part = (T*)m->d_partial;
   hipLaunchKernelGGL((dev::k_ns_jvp_lin<T, TD>), dim3((unsigned)m->n_chunks), dim3(dev::kChunkThreads),
                      (dev::ChunkLDS<T, 0, 4, 4>::bytes(cc)), s, view(m), pl, pv, cc, lin, dU, ldD, offD, part,
-                     skip);
+                     m->n_chunks, skip);
   hipLaunchKernelGGL((dev::k_gather<4, T, TD, 2>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part, out, ldO,
                      offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD, skip);
   HIPCHK(hipGetLastError());
@@ -1487,7 +1491,8 @@ void free_mesh_locked(chns_mesh* m) {
   free_workspace(m->ws);
   void* ptrs[] = {m->d_elem, m->d_hoff, m->d_hids, m->d_anchor, m->d_level,
                   m->d_hw, m->d_hw32, m->d_flag, m->d_part, m->d_sum,
-                  m->d_tgt_off, m->d_tgt, m->d_inc_off, m->d_node_off, m->d_node_slot, m->d_inc_corner,
+                  m->d_tgt_off, m->d_tgt, m->d_inc_off, m->d_chunk_inc, m->d_node_off, m->d_node_slot,
+                  m->d_inc_corner,
                   m->d_bflags, m->d_inc_w, m->d_touch_off, m->d_ntouch_off, m->d_ntouch_slot,
                   m->d_partial, m->d_tbuf, m->d_lin[0], m->d_lin[1]};
   for (void* p : ptrs)
@@ -1667,7 +1672,7 @@ int chns_launch_element_loop(chns_mesh* m, const chns_params* params, int block,
       if (block != CHNS_BLOCK_NS || !m->d_lin[0]) return fail(CHNS_EINVAL, "op 4 needs op 5 first (NS)");
       hipLaunchKernelGGL((dev::k_ns_jvp_lin<double, double>), g, b, (dev::ChunkLDS<double, 0, 4, 4>::bytes(cc)),
                          s, mv, pl, pv, cc, (const double*)m->d_lin[0], (const double*)dU, 6, off, p64,
-                         (const int*)nullptr);
+                         m->n_chunks, (const int*)nullptr);
     } else if (op == 5) {
       if (block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "op 5 is for the NS block");
       if ((rc = ensure_lin<double>(m))) return rc;
@@ -1677,7 +1682,7 @@ int chns_launch_element_loop(chns_mesh* m, const chns_params* params, int block,
       if (block != CHNS_BLOCK_NS || !m->d_lin[1]) return fail(CHNS_EINVAL, "op 6 needs op 7 first (NS)");
       hipLaunchKernelGGL((dev::k_ns_jvp_lin<float, float>), g, b, (dev::ChunkLDS<float, 0, 4, 4>::bytes(cc)),
                          s, mv, pl, pv, cc, (const float*)m->d_lin[1], (const float*)dU, 6, off, p32,
-                         (const int*)nullptr);
+                         m->n_chunks, (const int*)nullptr);
     } else if (op == 7) {
       if (block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "op 7 is for the NS block");
       if ((rc = ensure_lin<float>(m))) return rc;

@@ -50,13 +50,15 @@ struct Lane {
   int c;          // corner index i + 2j + 4k
   T sxh, syh, szh;  // corner sign along each axis divided by h
   T h, wdet;      // side and Gauss weight * det J = h^3/8
+  T ih, Gh;       // 1/h and 4/h^2 (exact: h is a power of two)
   __device__ void init(int lane8, int level) {
     const int bz = lane8 >> 2;
     const int t = bz ? (lane8 ^ 7) : lane8;
     const int bx = t & 1, by = (t >> 1) & 1;
     c = bx + 2 * by + 4 * bz;
     h = (T)ldexp(1.0, -level);
-    const T ih = (T)1 / h;
+    ih = (T)ldexp(1.0, level);
+    Gh = (T)ldexp(1.0, 2 * level + 2);
     sxh = bx ? ih : -ih;
     syh = by ? ih : -ih;
     szh = bz ? ih : -ih;
@@ -173,6 +175,7 @@ struct PlanView {
   const int32_t* tgt_off;     // per chunk
   const int32_t* tgt;         // per target slot: node id
   const int32_t* inc_off;     // per target slot
+  const int32_t* chunk_inc;   // per chunk: inc_off of its first target
   const uint8_t* inc_corner;  // local element * 8 + corner
   const float* inc_w;
   const int32_t* node_off;    // per node

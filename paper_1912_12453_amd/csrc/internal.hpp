@@ -73,6 +73,7 @@ std::string build_host_mesh(const chns_mesh_spec& spec, HostMesh& out);
 constexpr int kChunk = 32;
 struct ScatterPlan {
   std::vector<int32_t> tgt_off, tgt, inc_off;
+  std::vector<int32_t> chunk_inc;  // per chunk: inc_off at its first target
   std::vector<uint8_t> inc_corner;
   std::vector<float> inc_w;
   std::vector<int32_t> node_off, node_slot;

@@ -91,8 +91,14 @@ struct ChunkLDS {
   template <class TS, class TD>
   __device__ __forceinline__ void stage(const PlanView& pl, const TS* __restrict__ U1, const TS* __restrict__ U0,
                         const TD* __restrict__ dU, int ldD, int offD) {
-    s0 = pl.tgt_off[blockIdx.x];
-    cnt = pl.tgt_off[blockIdx.x + 1] - s0;
+    stage_chunk(pl, (int)blockIdx.x, U1, U0, dU, ldD, offD);
+  }
+  template <class TS, class TD>
+  __device__ __forceinline__ void stage_chunk(const PlanView& pl, int chunk, const TS* __restrict__ U1,
+                                              const TS* __restrict__ U0, const TD* __restrict__ dU, int ldD,
+                                              int offD) {
+    s0 = pl.tgt_off[chunk];
+    cnt = pl.tgt_off[chunk + 1] - s0;
     const int i0 = pl.inc_off[s0];
     const int ni = pl.inc_off[s0 + cnt] - i0;
     for (int i = threadIdx.x; i < cnt; i += blockDim.x) tgt[i] = pl.tgt[s0 + i];
@@ -249,6 +255,7 @@ __global__ __launch_bounds__(256) void k_ch_jvp(MeshView m, PlanView pl, PhysVie
 // Quantities of the linearisation point at one Gauss point.
 template <class T>
 struct NSPoint {
+  T ps;              // phi^{k+1} pulled back to [-1,1]
   T rho, eta, inv_rho;
   T vt[3], G[3][3];  // v~ and its gradient G[i][j] = dv~_i/dx_j
   T J[3];            // mass flux kappa grad mu~
@@ -256,10 +263,39 @@ struct NSPoint {
   T tg[3];           // rho (v^{k+1}-v^k)_i/dt - rho g_i/Fr
   T Rm[3], Rc;       // strong residuals
   T tau_m, tau_c, Gh;  // Gh = 4/h^2 (G_ij = Gh delta_ij)
+  T sbr;               // 1/tau_m, the square root of the bracket
   T gpht[3];         // grad phi~
   T pt;              // p~
   bool ok;           // tau_m bracket positive
 };
+
+// rho, eta (linear in the pulled-back phi) and 1/rho.  The point evaluation
+// and the cached linearisation share this code, so both get the same values.
+template <class T>
+__device__ __forceinline__ void ns_material(const PhysView& p, T ps, NSPoint<T>& P) {
+  P.ps = ps;
+  P.rho = (T)p.alpha * ps + (T)p.beta;
+  P.eta = (T)p.gamma * ps + (T)p.xi;
+  P.inv_rho = (T)1 / P.rho;
+}
+
+// R_c, the metric Gh = 4/h^2 and the stabilisation parameters tau_m, tau_c
+// from v~, its gradient, J, rho and eta (shared as ns_material is).
+template <class T>
+__device__ __forceinline__ void ns_stab(const PhysView& p, const Lane<T>& L, NSPoint<T>& P) {
+  const T iPe = (T)p.inv_Pe, iRe = (T)p.inv_Re, idt = (T)p.inv_dt;
+  P.Rc = P.G[0][0] + P.G[1][1] + P.G[2][2];
+  P.Gh = L.Gh;
+  const T vv = P.vt[0] * P.vt[0] + P.vt[1] * P.vt[1] + P.vt[2] * P.vt[2];
+  const T vJ = P.vt[0] * P.J[0] + P.vt[1] * P.J[1] + P.vt[2] * P.J[2];
+  const T nu = P.eta * P.inv_rho * iRe;
+  const T br = (T)4 * idt * idt + P.Gh * vv + P.Gh * vJ * P.inv_rho * iPe +
+               (T)p.C_I * nu * nu * (T)3 * P.Gh * P.Gh;
+  P.ok = br > (T)0;
+  P.sbr = sqrt(br);
+  P.tau_m = (T)1 / P.sbr;
+  P.tau_c = (T)1 / ((T)3 * P.Gh * P.tau_m);
+}
 
 // Linearisation point from the lane's corner values of U^{k+1} (a) and U^k (b),
 // 6 fields each (phi, mu, u, v, w, p).
@@ -280,10 +316,7 @@ __device__ __forceinline__ void ns_point(const PhysView& p, const Lane<T>& L, co
     P.G[i][2] = v.dz;
     dv[i] = eval_v<T>(a[2 + i] - b[2 + i]);
   }
-  const T ps = clamp1(ph1.v);
-  P.rho = (T)p.alpha * ps + (T)p.beta;
-  P.eta = (T)p.gamma * ps + (T)p.xi;
-  P.inv_rho = (T)1 / P.rho;
+  ns_material<T>(p, clamp1(ph1.v), P);
   const bool inside = ph1.v <= (T)1 && ph1.v >= (T)-1;
   const T gg = inside ? (T)p.gamma : (T)0;  // grad eta, zero where phi* is pulled back
   const T kap = (T)p.kappa;
@@ -312,16 +345,7 @@ __device__ __forceinline__ void ns_point(const PhysView& p, const Lane<T>& L, co
     P.Rm[i] = P.tg[i] + P.adv[0] * P.G[i][0] + P.adv[1] * P.G[i][1] + P.adv[2] * P.G[i][2] +
               cap[i] + iWe * gpt[i];
   }
-  P.Rc = P.G[0][0] + P.G[1][1] + P.G[2][2];
-  P.Gh = (T)4 / (L.h * L.h);
-  const T vv = P.vt[0] * P.vt[0] + P.vt[1] * P.vt[1] + P.vt[2] * P.vt[2];
-  const T vJ = P.vt[0] * P.J[0] + P.vt[1] * P.J[1] + P.vt[2] * P.J[2];
-  const T nu = P.eta * P.inv_rho * iRe;
-  const T br = (T)4 * idt * idt + P.Gh * vv + P.Gh * vJ * P.inv_rho * iPe +
-               (T)p.C_I * nu * nu * (T)3 * P.Gh * P.Gh;
-  P.ok = br > (T)0;
-  P.tau_m = (T)1 / sqrt(br);
-  P.tau_c = (T)1 / ((T)3 * P.Gh * P.tau_m);
+  ns_stab<T>(p, L, P);
 }
 
 // Residual rows of the NS block (momentum i = 0..2, continuity 3) at the point,
@@ -382,7 +406,7 @@ __device__ __forceinline__ void ns_jvp_coef(const PhysView& p, const NSPoint<T>&
   const T Jdv = P.J[0] * dvt[0].v + P.J[1] * dvt[1].v + P.J[2] * dvt[2].v;
   const T dbr = (T)2 * P.Gh * vdv + P.Gh * Jdv * ir * iPe;
   const T dtm = (T)-0.5 * tm * tm * tm * dbr;
-  const T dtc = -P.tau_c * dtm / tm;
+  const T dtc = -P.tau_c * dtm * P.sbr;  // tau_c' = -tau_c tau_m' / tau_m
   T W[3], dW[3], dTR[3];  // dTR_j = d(tau_m R_m,j)
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -491,18 +515,20 @@ __global__ __launch_bounds__(256) void k_ns_jvp(MeshView m, PlanView pl, PhysVie
 
 // ------------------------------------------- cached linearisation point ----
 // Within one Newton iteration the state is fixed, so the NS linearisation
-// point at every Gauss point (the 27 values ns_jvp_coef reads) can be
-// computed once and reused by every Jacobian-vector product of the linear
-// solve.  Layout (structure of arrays per chunk, coalesced for the 256 lanes
-// of the chunk's workgroup): lin[(chunk * kNSLin + k) * 256 + lane].
-constexpr int kNSLin = 27;
+// point at every Gauss point can be computed once and reused by every
+// Jacobian-vector product of the linear solve.  22 values are kept: phi^{k+1}
+// pulled back to [-1,1], v~, its gradient, J, the transport velocity and R_m.
+// rho, eta, 1/rho, R_c, tau_m and tau_c are recomputed from them by the same
+// code the point evaluation runs (ns_material, ns_stab), which costs a few
+// divisions and a square root per point instead of 5 more loads.  Layout
+// (structure of arrays per chunk, coalesced for the 256 lanes of the chunk's
+// workgroup): lin[(chunk * kNSLin + k) * 256 + lane].
+constexpr int kNSLin = 22;
 
 template <class T>
 __device__ __forceinline__ void ns_lin_store(const NSPoint<T>& P, T* __restrict__ q) {
   int k = 0;
-  q[(k++) * kChunkThreads] = P.rho;
-  q[(k++) * kChunkThreads] = P.inv_rho;
-  q[(k++) * kChunkThreads] = P.eta;
+  q[(k++) * kChunkThreads] = P.ps;
 #pragma unroll
   for (int i = 0; i < 3; ++i) q[(k++) * kChunkThreads] = P.vt[i];
 #pragma unroll
@@ -515,33 +541,39 @@ __device__ __forceinline__ void ns_lin_store(const NSPoint<T>& P, T* __restrict_
   for (int i = 0; i < 3; ++i) q[(k++) * kChunkThreads] = P.adv[i];
 #pragma unroll
   for (int i = 0; i < 3; ++i) q[(k++) * kChunkThreads] = P.Rm[i];
-  q[(k++) * kChunkThreads] = P.Rc;
-  q[(k++) * kChunkThreads] = P.tau_m;
-  q[(k++) * kChunkThreads] = P.tau_c;
+}
+
+// the cached values of one lane, as loaded
+template <class T>
+struct NSLin {
+  T v[kNSLin];
+};
+
+template <class T>
+__device__ __forceinline__ void ns_lin_fetch(const T* __restrict__ q, NSLin<T>& out) {
+#pragma unroll
+  for (int k = 0; k < kNSLin; ++k) out.v[k] = q[k * kChunkThreads];
 }
 
 template <class T>
-__device__ __forceinline__ void ns_lin_load(const T* __restrict__ q, const Lane<T>& L, NSPoint<T>& P) {
+__device__ __forceinline__ void ns_lin_unpack(const PhysView& p, const NSLin<T>& q, const Lane<T>& L,
+                                              NSPoint<T>& P) {
   int k = 0;
-  P.rho = q[(k++) * kChunkThreads];
-  P.inv_rho = q[(k++) * kChunkThreads];
-  P.eta = q[(k++) * kChunkThreads];
+  const T ps = q.v[k++];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) P.vt[i] = q[(k++) * kChunkThreads];
+  for (int i = 0; i < 3; ++i) P.vt[i] = q.v[k++];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) P.G[i][j] = q[(k++) * kChunkThreads];
+    for (int j = 0; j < 3; ++j) P.G[i][j] = q.v[k++];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) P.J[i] = q[(k++) * kChunkThreads];
+  for (int i = 0; i < 3; ++i) P.J[i] = q.v[k++];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) P.adv[i] = q[(k++) * kChunkThreads];
+  for (int i = 0; i < 3; ++i) P.adv[i] = q.v[k++];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) P.Rm[i] = q[(k++) * kChunkThreads];
-  P.Rc = q[(k++) * kChunkThreads];
-  P.tau_m = q[(k++) * kChunkThreads];
-  P.tau_c = q[(k++) * kChunkThreads];
-  P.Gh = (T)4 / (L.h * L.h);
+  for (int i = 0; i < 3; ++i) P.Rm[i] = q.v[k++];
+  ns_material<T>(p, ps, P);
+  ns_stab<T>(p, L, P);
 }
 
 // Linearisation points of every Gauss point of the mesh (one workgroup per
@@ -571,28 +603,125 @@ __global__ __launch_bounds__(256) void k_ns_lin(MeshView m, PlanView pl, PhysVie
 }
 
 // The NS Jacobian-vector product from the cached linearisation points: only
-// the direction is staged.
+// the direction is staged.  Vector memory counters retire in the order the
+// loads were issued, so the prologue issues them in the order they are
+// needed: (1) the chunk's target and incidence lists and the lane's
+// hanging-node record, (2) the cached values, which carry most of the bytes,
+// (3) what depends on (1): the direction records of the targets and the
+// parents of a hanging corner.  The LDS stores of (1) and (3) wait only for
+// their own loads and (2) streams meanwhile.  The fixed per-thread counts
+// cover chunks of up to 128 targets and 512 incidences and hanging nodes of up
+// to 4 parents; loops take anything beyond.
 template <class T, class TD>
 __global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
                                                     const T* __restrict__ lin, const TD* __restrict__ dU,
                                                     int ldD, int offD, T* __restrict__ partial,
-                                                    const int* skip) {
+                                                    int64_t n_chunks, const int* skip) {
   if (skip && *skip) return;  // GMRES control: this step is not needed
   extern __shared__ double smem_d[];
   using CL = ChunkLDS<T, 0, 4, 4>;
+  constexpr int SV = CL::SV, KD = 2, KI = 2, KH = 4;
   CL S;
   S.carve((char*)smem_d, caps);
-  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int t = threadIdx.x;
+  const int ch = blockIdx.x;
+  const int64_t e0 = ((int64_t)ch * kChunkThreads + t) >> 3;
   const int64_t e = e0 < m.E ? e0 : m.E - 1;
   Lane<T> L;
-  L.init(threadIdx.x & 7, m.level[e]);
+  L.init(t & 7, m.level[e]);
   const int ref = m.elem[e * 8 + L.c];
-  S.stage(pl, (const TD*)nullptr, (const TD*)nullptr, dU, ldD, offD);
-  NSPoint<T> P;
-  ns_lin_load<T>(lin + (int64_t)blockIdx.x * kNSLin * kChunkThreads + threadIdx.x, L, P);
+  const int s0 = pl.tgt_off[ch], cnt = pl.tgt_off[ch + 1] - s0;
+  const int i0 = pl.chunk_inc[ch], ni = pl.chunk_inc[ch + 1] - i0;
+  S.s0 = s0;
+  S.cnt = cnt;
+  // (1) lists; indices past the end are clamped and their values dropped
+  const int tg = pl.tgt[s0 + min(t, cnt - 1)];
+  const int io = pl.inc_off[s0 + min(t, cnt)];
+  int gd[KD], icv[KI];
+  float iwv[KI];
+#pragma unroll
+  for (int k = 0; k < KD; ++k) gd[k] = pl.tgt[s0 + min((t + k * kChunkThreads) >> 2, cnt - 1)];
+#pragma unroll
+  for (int k = 0; k < KI; ++k) {
+    const int i = i0 + min(t + k * kChunkThreads, ni - 1);
+    iwv[k] = pl.inc_w[i];
+    icv[k] = pl.inc_corner[i];
+  }
+  int h0 = 0, h1 = 0;
+  if (ref < 0) {
+    h0 = m.hoff[-1 - ref];
+    h1 = m.hoff[-ref];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // (2)
+  NSLin<T> q;
+  ns_lin_fetch<T>(lin + (int64_t)ch * kNSLin * kChunkThreads + t, q);
+  __builtin_amdgcn_sched_barrier(0);
+  // (3)
+  TD dv[KD];
+#pragma unroll
+  for (int k = 0; k < KD; ++k) dv[k] = dU[(int64_t)gd[k] * ldD + offD + ((t + k * kChunkThreads) & 3)];
+  int hid[KH];
+  T hwt[KH];
+  if (ref < 0) {
+    const auto* w = weights<T>(m);
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int j = min(h0 + k, h1 - 1);
+      hid[k] = m.hids[j];
+      hwt[k] = w[j];
+    }
+  }
+  if (t < cnt) S.tgt[t] = tg;
+  if (t <= cnt) S.ioff[t] = io - i0;
+#pragma unroll
+  for (int k = 0; k < KI; ++k)
+    if (t + k * kChunkThreads < ni) {
+      S.iw[t + k * kChunkThreads] = iwv[k];
+      S.icor[t + k * kChunkThreads] = (uint8_t)icv[k];
+    }
+#pragma unroll
+  for (int k = 0; k < KD; ++k) {
+    const int i = t + k * kChunkThreads;
+    if (i < cnt * 4) S.val[(i >> 2) * SV + (i & 3)] = (T)dv[k];
+  }
+  // chunks beyond the fixed counts
+  for (int i = t + kChunkThreads; i <= cnt; i += kChunkThreads) {
+    if (i < cnt) S.tgt[i] = pl.tgt[s0 + i];
+    S.ioff[i] = pl.inc_off[s0 + i] - i0;
+  }
+  for (int i = t + KI * kChunkThreads; i < ni; i += kChunkThreads) {
+    S.iw[i] = pl.inc_w[i0 + i];
+    S.icor[i] = pl.inc_corner[i0 + i];
+  }
+  for (int i = t + KD * kChunkThreads; i < cnt * 4; i += kChunkThreads)
+    S.val[(i >> 2) * SV + (i & 3)] = (T)dU[(int64_t)pl.tgt[s0 + (i >> 2)] * ldD + offD + (i & 3)];
   __syncthreads();
-  T c[CL::NV];
-  S.corner(m, ref, c);
+  // the lane's corner: its node, or its constraint's parents in list order
+  T c[4];
+  if (ref >= 0) {
+    const T* v = S.val + S.find(ref) * SV;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) c[f] = v[f];
+  } else {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) c[f] = (T)0;
+#pragma unroll
+    for (int k = 0; k < KH; ++k)
+      if (h0 + k < h1) {
+        const T* v = S.val + S.find(hid[k]) * SV;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) c[f] += hwt[k] * v[f];
+      }
+    const auto* w = weights<T>(m);
+    for (int j = h0 + KH; j < h1; ++j) {
+      const T* v = S.val + S.find(m.hids[j]) * SV;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) c[f] += w[j] * v[f];
+    }
+  }
+  NSPoint<T> P;
+  ns_lin_unpack<T>(p, q, L, P);
   VG<T> dvt[3];
   T ddv[3];
 #pragma unroll
@@ -607,7 +736,7 @@ __global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, Phy
   const VG<T> dpt = eval_vg<T>((T)0.5 * c[3], L);
   T r[4];
   ns_jvp_point<T>(p, L, P, dvt, ddv, dpt, r);
-  S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
+  S.finish((t >> 3) * 8 + L.c, r, partial);
 }
 
 // ---------------------------------------------- coupled Jacobian rows ----
@@ -786,7 +915,7 @@ __device__ __forceinline__ void diag_regular(const PhysView& p, const Lane<T>& L
   constexpr int NF = BLOCK == 0 ? 2 : 4;
   const T A = (T)kA, B = (T)kB;
   const bool qx = L.sxh > (T)0, qy = L.syh > (T)0, qz = L.szh > (T)0;
-  const T ih = (T)1 / L.h, w = L.wdet;
+  const T ih = L.ih, w = L.wdet;
 #pragma unroll 1
   for (int a = 0; a < 8; ++a) {
     // seed N_a at this Gauss point: shape factor A on an axis where the corner

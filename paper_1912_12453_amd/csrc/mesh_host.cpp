@@ -438,6 +438,8 @@ std::string build_scatter_plan(const HostMesh& m, ScatterPlan& P) {
     P.max_inc = std::max(P.max_inc, (int)tmp.size());
     if ((int64_t)P.inc_corner.size() > INT32_MAX) return "scatter plan too large";
   }
+  P.chunk_inc.resize(C + 1);
+  for (int64_t c = 0; c <= C; ++c) P.chunk_inc[c] = P.inc_off[P.tgt_off[c]];
   // node -> slots (counting sort keeps slots ascending)
   const int64_t S = (int64_t)P.tgt.size();
   P.node_off.assign(n + 1, 0);

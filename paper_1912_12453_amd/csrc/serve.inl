@@ -30,10 +30,18 @@ int64_t mesh_footprint(const chns_mesh* m) {
   const size_t E = h.leaf_key.size(), NH = h.hang_key.size(), NC = h.hang_ids.size();
   return sz(E * 8, 4) + sz(E, 1) + sz(E * 3, 4) + sz(NH + 1, 4) + sz(NC, 4) + sz(NC, 8) + sz(NC, 4) +
          sz(1, 4) + sz(E * 2, 8) + sz(2, 8) + sz(P.tgt_off.size(), 4) + sz(P.tgt.size(), 4) +
-         sz(P.inc_off.size(), 4) + sz(P.inc_corner.size(), 1) + sz(P.inc_w.size(), 4) +
+         sz(P.inc_off.size(), 4) + sz(P.chunk_inc.size(), 4) + sz(P.inc_corner.size(), 1) +
+         sz(P.inc_w.size(), 4) +
          sz(P.node_off.size(), 4) + sz(P.node_slot.size(), 4) + sz(P.touch_off.size(), 8) +
          sz(P.ntouch_off.size(), 8) + sz(P.ntouch_slot.size(), 8) + sz(h.bflags.size(), 1) +
          sz(P.tgt.size() * 4, 8) + sz(P.ntouch_slot.size() * 16, 8);
+}
+
+// Device bytes of the cached NS linearisation points of a mesh (ensure_lin),
+// at the precision of the inner solve.
+int64_t lin_footprint(const chns_mesh* m, const chns_solver_opts& o) {
+  const int64_t chunks = std::max<int64_t>((int64_t)m->plan.tgt_off.size() - 1, 1);
+  return chunks * dev::kNSLin * dev::kChunkThreads * (o.precision == 0 ? 8 : 4);
 }
 
 // Device bytes of Solver::ensure_workspace() for n nodes under opts.
@@ -139,9 +147,10 @@ void build_request(chns_server* S, Request* r) {
   if (err.empty()) {
     r->n_leaves = (int64_t)m->h.leaf_key.size();
     r->n_nodes = (int64_t)m->h.node_key.size();
-    r->footprint = mesh_footprint(m) + workspace_footprint((int64_t)m->h.node_key.size(), S->opts);
+    r->footprint = mesh_footprint(m) + workspace_footprint((int64_t)m->h.node_key.size(), S->opts) +
+                   lin_footprint(m, S->opts);
     if (S->opts.precond == 2)  // coarse levels: at most the fine level's size again, plus V-cycle buffers
-      r->footprint += mesh_footprint(m) + 656 * (int64_t)m->h.node_key.size();
+      r->footprint += mesh_footprint(m) + lin_footprint(m, S->opts) + 656 * (int64_t)m->h.node_key.size();
     if (r->footprint > S->budget) err = "request needs " + std::to_string(r->footprint) +
                                         " device bytes, above the server budget";
   }
