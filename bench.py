@@ -282,15 +282,16 @@ def main():
             ev1.record(stream)
             ev1.synchronize()
             kern[f"{bname}_{oname}_ms"] = ev0.elapsed_time(ev1) / 5
-    for o, oname in ((5, "lin_f64"), (4, "jvp_lin_f64"), (7, "lin_f32"), (6, "jvp_lin_f32")):
-        dd = dU if o in (4, 5) else dU.float()
-        chns.chns_launch_element_loop(mesh.h, p, chns.CHNS_BLOCK_NS, o, U1, U0, dd, None, 1)
-        ev0.record(stream)
-        chns.chns_launch_element_loop(mesh.h, p, chns.CHNS_BLOCK_NS, o, U1, U0, dd, None, 5)
-        ev1.record(stream)
-        ev1.synchronize()
-        kern[f"ns_{oname}_ms"] = ev0.elapsed_time(ev1) / 5
-    for bname, nf, names in (("ch", 2, ("jvp_f64", "jvp_f32")),
+    for blk, bname in ((chns.CHNS_BLOCK_CH, "ch"), (chns.CHNS_BLOCK_NS, "ns")):
+        for o, oname in ((5, "lin_f64"), (4, "jvp_lin_f64"), (7, "lin_f32"), (6, "jvp_lin_f32")):
+            dd = dU if o in (4, 5) else dU.float()
+            chns.chns_launch_element_loop(mesh.h, p, blk, o, U1, U0, dd, None, 1)
+            ev0.record(stream)
+            chns.chns_launch_element_loop(mesh.h, p, blk, o, U1, U0, dd, None, 5)
+            ev1.record(stream)
+            ev1.synchronize()
+            kern[f"{bname}_{oname}_ms"] = ev0.elapsed_time(ev1) / 5
+    for bname, nf, names in (("ch", 2, ("jvp_f64", "jvp_f32", "jvp_lin_f64", "jvp_lin_f32")),
                              ("ns", 4, ("jvp_f64", "jvp_f32", "jvp_lin_f64", "jvp_lin_f32"))):
         for oname in names:
             kern[f"{bname}_{oname}_gdofs"] = n * nf / kern[f"{bname}_{oname}_ms"] / 1e6

@@ -166,19 +166,21 @@ int chns_jvp(chns_mesh* mesh, const chns_params* params, int block, const double
 int chns_jvp_full(chns_mesh* mesh, const chns_params* params, const double* U_new, const double* U_old,
                   const void* dU, void* JdU, int prec, void* stream);
 
-/* Cached linearisation of the NS block.  Within one Newton iteration the
- * state is fixed, so the quantities of Def. 2 that the JVP differentiates
- * around can be evaluated once: phi^{k+1} pulled back to [-1,1], v~ and its
- * gradient, the mass flux J, the transport velocity of R_m and R_m, 22 values
- * per Gauss point, from which rho, eta, R_c, tau_m and tau_c follow in a few
- * operations.  chns_linearize does that for (U_new, U_old) and keeps the
- * values with the mesh (device memory, 22 * 8 values per element in the
- * arithmetic of prec, allocated on first use); chns_jvp_lin then applies
- * the chns_jvp of that state and prec to dU (same layout; same results up
- * to rounding, since the compiler may contract multiply-adds differently in
- * the two kernels) reading only the direction.  block must be
- * CHNS_BLOCK_NS.  The cache holds the last chns_linearize, or the last
- * Newton iteration of chns_step, on this mesh. */
+/* Cached linearisation points.  Within one Newton iteration the state is
+ * fixed, so the quantities of the block's weak form (Def. 1 and 2) that the
+ * JVP differentiates around can be evaluated once per Gauss point:
+ *   NS: phi^{k+1} pulled back to [-1,1], v~ and its gradient, the mass flux
+ *       J, the transport velocity of R_m and R_m, 22 values, from which rho,
+ *       eta, R_c, tau_m and tau_c follow in a few operations;
+ *   CH: psi''(phi~) = 3 phi~^2 - 1 and v~, 4 values.
+ * chns_linearize does that for (U_new, U_old) and keeps the values with the
+ * mesh (device memory, 22 or 4 times 8 values per element in the arithmetic
+ * of prec, allocated on first use, one cache per block and precision);
+ * chns_jvp_lin then applies the chns_jvp of that state, block and prec to dU
+ * (same layout; same results up to rounding, since the compiler may contract
+ * multiply-adds differently in the two kernels) reading only the direction.
+ * A cache holds the last chns_linearize, or the last Newton iteration of
+ * chns_step, on this mesh. */
 int chns_linearize(chns_mesh* mesh, const chns_params* params, int block, const double* U_new,
                    const double* U_old, int prec, void* stream);
 int chns_jvp_lin(chns_mesh* mesh, const chns_params* params, int block, const void* dU, void* JdU,
@@ -265,9 +267,9 @@ int chns_step(chns_mesh* mesh, const chns_params* params, const chns_solver_opts
  * them with its own HIP events on that stream.  The kernels write the mesh's
  * internal partial buffers; `out` is not used and may be NULL.  op: 0 residual
  * (FP64), 1 JVP FP64 (dU: n_nodes*6 doubles), 2 JVP FP32 (dU: n_nodes*6
- * floats), 3 node-block diagonal; NS block only: 5 cached linearisation
- * points of (U_new, U_old) in FP64, 4 the JVP from them (FP64 dU), 7 and 6
- * the same in FP32 (4 and 6 fail unless 5 or 7 ran before on the mesh).
+ * floats), 3 node-block diagonal, 5 cached linearisation points of
+ * (U_new, U_old) in FP64, 4 the JVP from them (FP64 dU), 7 and 6 the same in
+ * FP32 (4 and 6 fail unless 5 or 7 ran before on the mesh and block).
  * *grid (may be NULL) receives the number of workgroups of one launch. */
 int chns_launch_element_loop(chns_mesh* mesh, const chns_params* params, int block, int op,
                              const double* U_new, const double* U_old, const void* dU, void* out,

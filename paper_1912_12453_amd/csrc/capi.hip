@@ -178,7 +178,7 @@ struct chns_mesh {
   double* h_sum = nullptr;
   int64_t device_bytes = 0;
   Workspace ws;
-  void* d_lin[2] = {nullptr, nullptr};  // cached NS linearisation points (FP64, FP32)
+  void* d_lin[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // cached linearisation points [block][FP64, FP32]
   std::vector<MGLevel> mg;  // multigrid hierarchy, built on first use
   int mg_key = -1;          // mg_levels it was built for
 };
@@ -439,45 +439,60 @@ int launch_jvp_full(chns_mesh* m, const dev::PhysView& pv, const TS* U1, const T
   return CHNS_OK;
 }
 
-// Cached NS linearisation points (k_ns_lin) and the JVP that reads them.
+// Cached linearisation points (k_ns_lin, k_ch_lin) and the JVPs that read
+// them, per block and precision.
+int lin_values(int block) { return block == CHNS_BLOCK_CH ? dev::kCHLin : dev::kNSLin; }
+
 template <class T>
-int ensure_lin(chns_mesh* m) {
-  const int k = std::is_same<T, double>::value ? 0 : 1;
-  if (m->d_lin[k]) return CHNS_OK;
+int ensure_lin(chns_mesh* m, int block) {
+  void*& slot = m->d_lin[block][std::is_same<T, double>::value ? 0 : 1];
+  if (slot) return CHNS_OK;
   std::lock_guard<std::mutex> lk(g_struct_mu);
   T* p = nullptr;
-  const int rc = dalloc(&p, (size_t)m->n_chunks * dev::kNSLin * dev::kChunkThreads, &m->device_bytes);
+  const int rc = dalloc(&p, (size_t)m->n_chunks * lin_values(block) * dev::kChunkThreads, &m->device_bytes);
   if (rc) return rc;
-  m->d_lin[k] = p;
+  slot = p;
   return CHNS_OK;
 }
 
 template <class T, class TS>
-int launch_ns_lin(chns_mesh* m, const dev::PhysView& pv, const TS* U1, const TS* U0, hipStream_t s) {
-  int rc = ensure_lin<T>(m);
+int launch_lin(chns_mesh* m, const dev::PhysView& pv, int block, const TS* U1, const TS* U0, hipStream_t s) {
+  int rc = ensure_lin<T>(m, block);
   if (rc) return rc;
   const dev::ChunkCaps cc = caps(m);
-  hipLaunchKernelGGL((dev::k_ns_lin<T, TS>), dim3((unsigned)m->n_chunks), dim3(dev::kChunkThreads),
-                     (dev::ChunkLDS<T, 6, 0, 4>::bytes(cc)), s, view(m), plan_view(m), pv, cc, U1, U0,
-                     (T*)m->d_lin[std::is_same<T, double>::value ? 0 : 1]);
+  T* lin = (T*)m->d_lin[block][std::is_same<T, double>::value ? 0 : 1];
+  const dim3 g((unsigned)m->n_chunks), b(dev::kChunkThreads);
+  if (block == CHNS_BLOCK_CH)
+    hipLaunchKernelGGL((dev::k_ch_lin<T, TS>), g, b, (dev::ChunkLDS<T, 5, 0, 2>::bytes(cc)), s, view(m),
+                       plan_view(m), pv, cc, U1, U0, lin);
+  else
+    hipLaunchKernelGGL((dev::k_ns_lin<T, TS>), g, b, (dev::ChunkLDS<T, 6, 0, 4>::bytes(cc)), s, view(m),
+                       plan_view(m), pv, cc, U1, U0, lin);
   HIPCHK(hipGetLastError());
   return CHNS_OK;
 }
 
 template <class T, class TD>
-int launch_jvp_lin(chns_mesh* m, const dev::PhysView& pv, const TD* dU, int ldD, int offD, TD* out, int ldO,
-                   int offO, hipStream_t s, const int* skip = nullptr) {
-  const T* lin = (const T*)m->d_lin[std::is_same<T, double>::value ? 0 : 1];
+int launch_jvp_lin(chns_mesh* m, const dev::PhysView& pv, int block, const TD* dU, int ldD, int offD, TD* out,
+                   int ldO, int offO, hipStream_t s, const int* skip = nullptr) {
+  const T* lin = (const T*)m->d_lin[block][std::is_same<T, double>::value ? 0 : 1];
   if (!lin) return fail(CHNS_EINVAL, "no linearisation point: call chns_linearize first");
   const int64_t n = (int64_t)m->h.node_key.size();
   const dev::ChunkCaps cc = caps(m);
   const auto pl = plan_view(m);
   T* part = (T*)m->d_partial;
-  hipLaunchKernelGGL((dev::k_ns_jvp_lin<T, TD>), dim3((unsigned)m->n_chunks), dim3(dev::kChunkThreads),
-                     (dev::ChunkLDS<T, 0, 4, 4>::bytes(cc)), s, view(m), pl, pv, cc, lin, dU, ldD, offD, part,
-                     m->n_chunks, skip);
-  hipLaunchKernelGGL((dev::k_gather<4, T, TD, 2>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part, out, ldO,
-                     offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD, skip);
+  const dim3 g((unsigned)m->n_chunks), b(dev::kChunkThreads);
+  if (block == CHNS_BLOCK_CH) {
+    hipLaunchKernelGGL((dev::k_ch_jvp_lin<T, TD>), g, b, (dev::ChunkLDS<T, 0, 2, 2>::bytes(cc)), s, view(m), pl,
+                       pv, cc, lin, dU, ldD, offD, part, skip);
+    hipLaunchKernelGGL((dev::k_gather<2, T, TD, 0>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part, out,
+                       ldO, offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD, skip);
+  } else {
+    hipLaunchKernelGGL((dev::k_ns_jvp_lin<T, TD>), g, b, (dev::ChunkLDS<T, 0, 4, 4>::bytes(cc)), s, view(m), pl,
+                       pv, cc, lin, dU, ldD, offD, part, skip);
+    hipLaunchKernelGGL((dev::k_gather<4, T, TD, 2>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part, out,
+                       ldO, offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD, skip);
+  }
   HIPCHK(hipGetLastError());
   return CHNS_OK;
 }
@@ -712,10 +727,7 @@ struct Solver {
         return launch_jvp_full<double, double, TV>(m, pv, (const double*)U1, (const double*)U0, x, y, s, skip);
       return launch_jvp_full<float, float, TV>(m, pv, w.U1f, w.U0f, x, y, s, skip);
     }
-    if (block == CHNS_BLOCK_NS) return launch_jvp_lin<TV, TV>(m, pv, x, nf, 0, y, nf, 0, s, skip);
-    if (std::is_same<TV, double>::value)
-      return launch_jvp<double, double, TV>(m, pv, block, U1, U0, x, nf, 0, y, nf, 0, s, skip);
-    return launch_jvp<float, float, TV>(m, pv, block, w.U1f, w.U0f, x, nf, 0, y, nf, 0, s, skip);
+    return launch_jvp_lin<TV, TV>(m, pv, block, x, nf, 0, y, nf, 0, s, skip);
   }
 
   template <class TV>
@@ -774,12 +786,9 @@ struct Solver {
     const bool ch = block == CHNS_BLOCK_CH;
     const TM* Di = l == 0 ? (dbl ? (const TM*)(ch ? w.DiC : w.Di) : (const TM*)(ch ? w.DiC32 : w.Di32))
                           : (dbl ? (const TM*)(ch ? L.DiC : L.Di) : (const TM*)(ch ? L.DiC32 : L.Di32));
-    const TV* S1 = l == 0 ? (dbl ? (const TV*)U1 : (const TV*)w.U1f) : (dbl ? (const TV*)L.U1 : (const TV*)L.U1f);
-    const TV* S0 = l == 0 ? (dbl ? (const TV*)U0 : (const TV*)w.U0f) : (dbl ? (const TV*)L.U0 : (const TV*)L.U0f);
     const dim3 g(grid_stride(nl)), gs(grid_stride(N)), bl(256);
     auto A = [&](const TV* in, TV* out) {
-      if (block == CHNS_BLOCK_NS) return launch_jvp_lin<TV, TV>(mm, pv, in, NF, 0, out, NF, 0, s, skip);
-      return launch_jvp<TV, TV, TV>(mm, pv, block, S1, S0, in, NF, 0, out, NF, 0, s, skip);
+      return launch_jvp_lin<TV, TV>(mm, pv, block, in, NF, 0, out, NF, 0, s, skip);
     };
     auto jac = [&](const TV* Ax) {
       hipLaunchKernelGGL((dev::k_jacobi<NF, TV, TM>), g, bl, 0, s, Di, b, Ax, x, mm->d_bflags, block,
@@ -829,11 +838,9 @@ struct Solver {
       hipLaunchKernelGGL(dev::k_inject6, g, b, 0, s, s0, F.inj, C.n, C.U0, C.U0f);
       int rc = launch_diag(C.mesh, pv, block, C.U1, C.U0, C.D, s);
       if (rc) return rc;
-      if (block == CHNS_BLOCK_NS) {
-        rc = o.precision == 0 ? launch_ns_lin<double, double>(C.mesh, pv, C.U1, C.U0, s)
-                              : launch_ns_lin<float, float>(C.mesh, pv, C.U1f, C.U0f, s);
-        if (rc) return rc;
-      }
+      rc = o.precision == 0 ? launch_lin<double, double>(C.mesh, pv, block, C.U1, C.U0, s)
+                            : launch_lin<float, float>(C.mesh, pv, block, C.U1f, C.U0f, s);
+      if (rc) return rc;
       if (nf == 2)
         hipLaunchKernelGGL(dev::k_invert_blocks<2>, dim3(grid_for(C.n)), b, 0, s, C.D, C.DiC, C.DiC32, C.n, 0,
                            w.flag);
@@ -1052,7 +1059,7 @@ struct Solver {
       if (o.precision == 0) {
         hipLaunchKernelGGL((dev::k_scale<double, double>), dim3(grid_stride(N)), dim3(256), 0, s, w.b64,
                            w.r, -1.0, N);
-        if (block == CHNS_BLOCK_NS && (rc = launch_ns_lin<double, double>(m, pv, U, w.Uk, s))) return rc;
+        if ((rc = launch_lin<double, double>(m, pv, block, U, w.Uk, s))) return rc;
         rc = gmres<double>(block, w.V64, w.Z64, w.w64, w.b64, U, w.Uk, &its);
       } else {
         hipLaunchKernelGGL((dev::k_convert<double, float>), dim3(grid_stride(n * 6)), dim3(256), 0, s, U,
@@ -1061,7 +1068,7 @@ struct Solver {
                            w.Uk, w.U0f, n * 6, (const int*)nullptr);
         hipLaunchKernelGGL((dev::k_scale<double, float>), dim3(grid_stride(N)), dim3(256), 0, s, w.b32,
                            w.r, -1.0, N);
-        if (block == CHNS_BLOCK_NS && (rc = launch_ns_lin<float, float>(m, pv, w.U1f, w.U0f, s))) return rc;
+        if ((rc = launch_lin<float, float>(m, pv, block, w.U1f, w.U0f, s))) return rc;
         rc = gmres<float>(block, w.V32, w.Z32, w.w32, w.b32, U, w.Uk, &its);
       }
       if (rc) return rc;
@@ -1106,7 +1113,9 @@ struct Solver {
       if (o.precision == 0) {
         hipLaunchKernelGGL((dev::k_scale<double, double>), dim3(grid_stride(N)), dim3(256), 0, s, w.b64, w.r,
                            -1.0, N);
-        if (o.precond == 2 && (rc = launch_ns_lin<double, double>(m, pv, U, w.Uk, s))) return rc;
+        if (o.precond == 2 && ((rc = launch_lin<double, double>(m, pv, CHNS_BLOCK_CH, U, w.Uk, s)) ||
+                               (rc = launch_lin<double, double>(m, pv, CHNS_BLOCK_NS, U, w.Uk, s))))
+          return rc;
         rc = gmres<double>(kCoupled, w.V64, w.Z64, w.w64, w.b64, U, w.Uk, &its);
       } else {
         hipLaunchKernelGGL((dev::k_convert<double, float>), dim3(grid_stride(n * 6)), dim3(256), 0, s, U,
@@ -1115,7 +1124,9 @@ struct Solver {
                            w.U0f, n * 6, (const int*)nullptr);
         hipLaunchKernelGGL((dev::k_scale<double, float>), dim3(grid_stride(N)), dim3(256), 0, s, w.b32, w.r,
                            -1.0, N);
-        if (o.precond == 2 && (rc = launch_ns_lin<float, float>(m, pv, w.U1f, w.U0f, s))) return rc;
+        if (o.precond == 2 && ((rc = launch_lin<float, float>(m, pv, CHNS_BLOCK_CH, w.U1f, w.U0f, s)) ||
+                               (rc = launch_lin<float, float>(m, pv, CHNS_BLOCK_NS, w.U1f, w.U0f, s))))
+          return rc;
         rc = gmres<float>(kCoupled, w.V32, w.Z32, w.w32, w.b32, U, w.Uk, &its);
       }
       if (rc) return rc;
@@ -1494,7 +1505,7 @@ void free_mesh_locked(chns_mesh* m) {
                   m->d_tgt_off, m->d_tgt, m->d_inc_off, m->d_chunk_inc, m->d_node_off, m->d_node_slot,
                   m->d_inc_corner,
                   m->d_bflags, m->d_inc_w, m->d_touch_off, m->d_ntouch_off, m->d_ntouch_slot,
-                  m->d_partial, m->d_tbuf, m->d_lin[0], m->d_lin[1]};
+                  m->d_partial, m->d_tbuf, m->d_lin[0][0], m->d_lin[0][1], m->d_lin[1][0], m->d_lin[1][1]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (m->h_flag) (void)hipHostFree(m->h_flag);
@@ -1559,10 +1570,10 @@ int chns_linearize(chns_mesh* m, const chns_params* params, int block, const dou
   if (rc) return rc;
   dev::PhysView pv;
   if ((rc = phys_view(params, pv))) return rc;
-  if (block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "the cached linearisation is for the NS block");
+  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "unknown block");
   if (!U_new || !U_old) return fail(CHNS_EINVAL, "pointers must not be NULL");
-  if (prec == CHNS_F64) return launch_ns_lin<double, double>(m, pv, U_new, U_old, s);
-  if (prec == CHNS_F32) return launch_ns_lin<float, double>(m, pv, U_new, U_old, s);
+  if (prec == CHNS_F64) return launch_lin<double, double>(m, pv, block, U_new, U_old, s);
+  if (prec == CHNS_F32) return launch_lin<float, double>(m, pv, block, U_new, U_old, s);
   return fail(CHNS_EINVAL, "prec must be CHNS_F64 or CHNS_F32");
 }
 
@@ -1573,12 +1584,13 @@ int chns_jvp_lin(chns_mesh* m, const chns_params* params, int block, const void*
   if (rc) return rc;
   dev::PhysView pv;
   if ((rc = phys_view(params, pv))) return rc;
-  if (block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "the cached linearisation is for the NS block");
+  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "unknown block");
   if (!dU || !JdU) return fail(CHNS_EINVAL, "pointers must not be NULL");
+  const int off = block == CHNS_BLOCK_CH ? 0 : 2;
   if (prec == CHNS_F64)
-    return launch_jvp_lin<double, double>(m, pv, (const double*)dU, 6, 2, (double*)JdU, 6, 2, s);
+    return launch_jvp_lin<double, double>(m, pv, block, (const double*)dU, 6, off, (double*)JdU, 6, off, s);
   if (prec == CHNS_F32)
-    return launch_jvp_lin<float, float>(m, pv, (const float*)dU, 6, 2, (float*)JdU, 6, 2, s);
+    return launch_jvp_lin<float, float>(m, pv, block, (const float*)dU, 6, off, (float*)JdU, 6, off, s);
   return fail(CHNS_EINVAL, "prec must be CHNS_F64 or CHNS_F32");
 }
 
@@ -1668,26 +1680,29 @@ int chns_launch_element_loop(chns_mesh* m, const chns_params* params, int block,
         hipLaunchKernelGGL((dev::k_ns_jvp<float, double, float>), g, b,
                            (dev::ChunkLDS<float, 6, 4, 4>::bytes(cc)), s, mv, pl, pv, cc, U_new, U_old,
                            (const float*)dU, 6, off, p32, (const int*)nullptr);
-    } else if (op == 4) {
-      if (block != CHNS_BLOCK_NS || !m->d_lin[0]) return fail(CHNS_EINVAL, "op 4 needs op 5 first (NS)");
-      hipLaunchKernelGGL((dev::k_ns_jvp_lin<double, double>), g, b, (dev::ChunkLDS<double, 0, 4, 4>::bytes(cc)),
-                         s, mv, pl, pv, cc, (const double*)m->d_lin[0], (const double*)dU, 6, off, p64,
-                         m->n_chunks, (const int*)nullptr);
+    } else if (op == 4 || op == 6) {  // JVP from the cached linearisation points (FP64 / FP32)
+      const int k = op == 4 ? 0 : 1;
+      if (!m->d_lin[block][k]) return fail(CHNS_EINVAL, "ops 4 and 6 need ops 5 and 7 first");
+      if (block == CHNS_BLOCK_CH && k == 0)
+        hipLaunchKernelGGL((dev::k_ch_jvp_lin<double, double>), g, b, (dev::ChunkLDS<double, 0, 2, 2>::bytes(cc)),
+                           s, mv, pl, pv, cc, (const double*)m->d_lin[block][0], (const double*)dU, 6, off, p64,
+                           (const int*)nullptr);
+      else if (block == CHNS_BLOCK_CH)
+        hipLaunchKernelGGL((dev::k_ch_jvp_lin<float, float>), g, b, (dev::ChunkLDS<float, 0, 2, 2>::bytes(cc)),
+                           s, mv, pl, pv, cc, (const float*)m->d_lin[block][1], (const float*)dU, 6, off, p32,
+                           (const int*)nullptr);
+      else if (k == 0)
+        hipLaunchKernelGGL((dev::k_ns_jvp_lin<double, double>), g, b, (dev::ChunkLDS<double, 0, 4, 4>::bytes(cc)),
+                           s, mv, pl, pv, cc, (const double*)m->d_lin[block][0], (const double*)dU, 6, off, p64,
+                           (const int*)nullptr);
+      else
+        hipLaunchKernelGGL((dev::k_ns_jvp_lin<float, float>), g, b, (dev::ChunkLDS<float, 0, 4, 4>::bytes(cc)),
+                           s, mv, pl, pv, cc, (const float*)m->d_lin[block][1], (const float*)dU, 6, off, p32,
+                           (const int*)nullptr);
     } else if (op == 5) {
-      if (block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "op 5 is for the NS block");
-      if ((rc = ensure_lin<double>(m))) return rc;
-      hipLaunchKernelGGL((dev::k_ns_lin<double, double>), g, b, (dev::ChunkLDS<double, 6, 0, 4>::bytes(cc)), s,
-                         mv, pl, pv, cc, U_new, U_old, (double*)m->d_lin[0]);
-    } else if (op == 6) {
-      if (block != CHNS_BLOCK_NS || !m->d_lin[1]) return fail(CHNS_EINVAL, "op 6 needs op 7 first (NS)");
-      hipLaunchKernelGGL((dev::k_ns_jvp_lin<float, float>), g, b, (dev::ChunkLDS<float, 0, 4, 4>::bytes(cc)),
-                         s, mv, pl, pv, cc, (const float*)m->d_lin[1], (const float*)dU, 6, off, p32,
-                         m->n_chunks, (const int*)nullptr);
+      if ((rc = launch_lin<double, double>(m, pv, block, U_new, U_old, s))) return rc;
     } else if (op == 7) {
-      if (block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "op 7 is for the NS block");
-      if ((rc = ensure_lin<float>(m))) return rc;
-      hipLaunchKernelGGL((dev::k_ns_lin<float, double>), g, b, (dev::ChunkLDS<float, 6, 0, 4>::bytes(cc)), s,
-                         mv, pl, pv, cc, U_new, U_old, (float*)m->d_lin[1]);
+      if ((rc = launch_lin<float, double>(m, pv, block, U_new, U_old, s))) return rc;
     } else if (op == 3) {
       if (block == CHNS_BLOCK_CH)
         hipLaunchKernelGGL((dev::k_diag<double, 0>), g, b, 0, s, mv, pl, pv, U_new, U_old, m->d_tbuf);

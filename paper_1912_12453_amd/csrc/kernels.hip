@@ -217,6 +217,25 @@ __global__ __launch_bounds__(256) void k_ch_residual(MeshView m, PlanView pl, Ph
   S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
 }
 
+// psi''(phi~) = 3 phi~^2 - 1, the derivative of phi~^3 - phi~
+template <class T>
+__device__ __forceinline__ T ch_dpsi(T pt) {
+  return (T)3 * pt * pt - (T)1;
+}
+
+// CH Jacobian rows at the lane's Gauss point in the direction (dp, dm) of
+// (phi^{k+1}, mu^{k+1}) (values and gradients; the midpoint fields move by
+// half of them).  The linearisation point enters through psi''(phi~) and v~.
+template <class T>
+__device__ __forceinline__ void ch_jvp_point(const PhysView& p, const Lane<T>& L, T dpsi, T vx, T vy, T vz,
+                                             const VG<T>& dp, const VG<T>& dm, T (&r)[2]) {
+  const T w = L.wdet, hk = (T)0.5 * (T)p.inv_PeCn, hc = (T)0.5 * (T)p.Cn2, hp = (T)0.5 * dp.v;
+  r[0] = test_contract<T>(w * dp.v * (T)p.inv_dt, w * (hk * dm.dx - vx * hp),
+                          w * (hk * dm.dy - vy * hp), w * (hk * dm.dz - vz * hp), L);
+  r[1] = test_contract<T>(w * dpsi * hp - w * (T)0.5 * dm.v, w * hc * dp.dx, w * hc * dp.dy,
+                          w * hc * dp.dz, L);
+}
+
 template <class T, class TS, class TD>
 __global__ __launch_bounds__(256) void k_ch_jvp(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
                                                 const TS* __restrict__ U1, const TS* __restrict__ U0,
@@ -242,12 +261,8 @@ __global__ __launch_bounds__(256) void k_ch_jvp(MeshView m, PlanView pl, PhysVie
   const T vz = eval_v<T>((T)0.5 * (c[4] + c[9]));
   const VG<T> dp = eval_vg<T>(c[10], L);  // d phi^{k+1}; d phi~ = dp/2
   const VG<T> dm = eval_vg<T>(c[11], L);  // d mu^{k+1};  d mu~  = dm/2
-  const T w = L.wdet, hk = (T)0.5 * (T)p.inv_PeCn, hc = (T)0.5 * (T)p.Cn2, hp = (T)0.5 * dp.v;
   T r[2];
-  r[0] = test_contract<T>(w * dp.v * (T)p.inv_dt, w * (hk * dm.dx - vx * hp),
-                          w * (hk * dm.dy - vy * hp), w * (hk * dm.dz - vz * hp), L);
-  r[1] = test_contract<T>(w * ((T)3 * pt * pt - (T)1) * hp - w * (T)0.5 * dm.v, w * hc * dp.dx,
-                          w * hc * dp.dy, w * hc * dp.dz, L);
+  ch_jvp_point<T>(p, L, ch_dpsi<T>(pt), vx, vy, vz, dp, dm, r);
   S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
 }
 
@@ -513,17 +528,21 @@ __global__ __launch_bounds__(256) void k_ns_jvp(MeshView m, PlanView pl, PhysVie
   S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
 }
 
-// ------------------------------------------- cached linearisation point ----
-// Within one Newton iteration the state is fixed, so the NS linearisation
-// point at every Gauss point can be computed once and reused by every
-// Jacobian-vector product of the linear solve.  22 values are kept: phi^{k+1}
-// pulled back to [-1,1], v~, its gradient, J, the transport velocity and R_m.
-// rho, eta, 1/rho, R_c, tau_m and tau_c are recomputed from them by the same
-// code the point evaluation runs (ns_material, ns_stab), which costs a few
-// divisions and a square root per point instead of 5 more loads.  Layout
-// (structure of arrays per chunk, coalesced for the 256 lanes of the chunk's
-// workgroup): lin[(chunk * kNSLin + k) * 256 + lane].
+// ------------------------------------------ cached linearisation points ----
+// Within one Newton iteration the state is fixed, so the quantities of the
+// linearisation point at every Gauss point can be computed once and reused by
+// every Jacobian-vector product of the linear solve.  Layout (structure of
+// arrays per chunk, coalesced for the 256 lanes of the chunk's workgroup):
+// lin[(chunk * NL + k) * 256 + lane] for the NL values of a block.
+//
+// NS block: 22 values, phi^{k+1} pulled back to [-1,1], v~, its gradient, J,
+// the transport velocity and R_m.  rho, eta, 1/rho, R_c, tau_m and tau_c are
+// recomputed from them by the code the point evaluation runs (ns_material,
+// ns_stab): a division, a square root and two divisions per point instead of
+// 5 more loads.
+// CH block: 4 values, psi''(phi~) and v~.
 constexpr int kNSLin = 22;
+constexpr int kCHLin = 4;
 
 template <class T>
 __device__ __forceinline__ void ns_lin_store(const NSPoint<T>& P, T* __restrict__ q) {
@@ -543,35 +562,23 @@ __device__ __forceinline__ void ns_lin_store(const NSPoint<T>& P, T* __restrict_
   for (int i = 0; i < 3; ++i) q[(k++) * kChunkThreads] = P.Rm[i];
 }
 
-// the cached values of one lane, as loaded
 template <class T>
-struct NSLin {
-  T v[kNSLin];
-};
-
-template <class T>
-__device__ __forceinline__ void ns_lin_fetch(const T* __restrict__ q, NSLin<T>& out) {
-#pragma unroll
-  for (int k = 0; k < kNSLin; ++k) out.v[k] = q[k * kChunkThreads];
-}
-
-template <class T>
-__device__ __forceinline__ void ns_lin_unpack(const PhysView& p, const NSLin<T>& q, const Lane<T>& L,
+__device__ __forceinline__ void ns_lin_unpack(const PhysView& p, const T (&q)[kNSLin], const Lane<T>& L,
                                               NSPoint<T>& P) {
   int k = 0;
-  const T ps = q.v[k++];
+  const T ps = q[k++];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) P.vt[i] = q.v[k++];
+  for (int i = 0; i < 3; ++i) P.vt[i] = q[k++];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) P.G[i][j] = q.v[k++];
+    for (int j = 0; j < 3; ++j) P.G[i][j] = q[k++];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) P.J[i] = q.v[k++];
+  for (int i = 0; i < 3; ++i) P.J[i] = q[k++];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) P.adv[i] = q.v[k++];
+  for (int i = 0; i < 3; ++i) P.adv[i] = q[k++];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) P.Rm[i] = q.v[k++];
+  for (int i = 0; i < 3; ++i) P.Rm[i] = q[k++];
   ns_material<T>(p, ps, P);
   ns_stab<T>(p, L, P);
 }
@@ -602,34 +609,50 @@ __global__ __launch_bounds__(256) void k_ns_lin(MeshView m, PlanView pl, PhysVie
   ns_lin_store<T>(P, lin + (int64_t)blockIdx.x * kNSLin * kChunkThreads + threadIdx.x);
 }
 
-// The NS Jacobian-vector product from the cached linearisation points: only
-// the direction is staged.  Vector memory counters retire in the order the
-// loads were issued, so the prologue issues them in the order they are
-// needed: (1) the chunk's target and incidence lists and the lane's
-// hanging-node record, (2) the cached values, which carry most of the bytes,
-// (3) what depends on (1): the direction records of the targets and the
-// parents of a hanging corner.  The LDS stores of (1) and (3) wait only for
-// their own loads and (2) streams meanwhile.  The fixed per-thread counts
-// cover chunks of up to 128 targets and 512 incidences and hanging nodes of up
-// to 4 parents; loops take anything beyond.
-template <class T, class TD>
-__global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
-                                                    const T* __restrict__ lin, const TD* __restrict__ dU,
-                                                    int ldD, int offD, T* __restrict__ partial,
-                                                    int64_t n_chunks, const int* skip) {
-  if (skip && *skip) return;  // GMRES control: this step is not needed
+template <class T, class TS>
+__global__ __launch_bounds__(256) void k_ch_lin(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
+                                                const TS* __restrict__ U1, const TS* __restrict__ U0,
+                                                T* __restrict__ lin) {
   extern __shared__ double smem_d[];
-  using CL = ChunkLDS<T, 0, 4, 4>;
-  constexpr int SV = CL::SV, KD = 2, KI = 2, KH = 4;
+  using CL = ChunkLDS<T, 5, 0, 2>;
   CL S;
   S.carve((char*)smem_d, caps);
-  const int t = threadIdx.x;
-  const int ch = blockIdx.x;
-  const int64_t e0 = ((int64_t)ch * kChunkThreads + t) >> 3;
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const int64_t e = e0 < m.E ? e0 : m.E - 1;
   Lane<T> L;
-  L.init(t & 7, m.level[e]);
+  L.init(threadIdx.x & 7, m.level[e]);
   const int ref = m.elem[e * 8 + L.c];
+  S.stage(pl, U1, U0, (const TS*)nullptr, 0, 0);
+  __syncthreads();
+  T c[CL::NV];  // phi, mu, u, v, w at k+1 and at k
+  S.corner(m, ref, c);
+  T* q = lin + (int64_t)blockIdx.x * kCHLin * kChunkThreads + threadIdx.x;
+  q[0] = ch_dpsi<T>(eval_v<T>((T)0.5 * (c[0] + c[5])));
+  q[kChunkThreads] = eval_v<T>((T)0.5 * (c[2] + c[7]));
+  q[2 * kChunkThreads] = eval_v<T>((T)0.5 * (c[3] + c[8]));
+  q[3 * kChunkThreads] = eval_v<T>((T)0.5 * (c[4] + c[9]));
+}
+
+// Prologue of the JVPs from cached linearisation points: stages the ND-field
+// direction of the chunk's targets and its lists, loads the lane's NL cached
+// values and returns the lane's corner direction (after the barrier).
+// Vector memory counters retire in the order the loads were issued, so they
+// are issued in the order they are needed: (1) the chunk's target and
+// incidence lists and the lane's hanging-node record, (2) the cached values,
+// which carry most of the bytes, (3) what depends on (1): the direction
+// records of the targets and the parents of a hanging corner.  The LDS stores
+// of (1) and (3) wait only for their own loads and (2) streams meanwhile.  The
+// fixed per-thread counts cover chunks of up to 128 targets and 512
+// incidences and hanging nodes of up to 4 parents; loops take anything
+// beyond.
+template <class T, class TD, int ND, int NL>
+__device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND, ND>& S, const MeshView& m, const PlanView& pl,
+                                             int ch, int ref, const T* __restrict__ lin,
+                                             const TD* __restrict__ dU, int ldD, int offD, T (&q)[NL],
+                                             T (&c)[ND]) {
+  constexpr int SV = ChunkLDS<T, 0, ND, ND>::SV, KI = 2, KH = 4;
+  constexpr int KD = (128 * ND + kChunkThreads - 1) / kChunkThreads;
+  const int t = threadIdx.x;
   const int s0 = pl.tgt_off[ch], cnt = pl.tgt_off[ch + 1] - s0;
   const int i0 = pl.chunk_inc[ch], ni = pl.chunk_inc[ch + 1] - i0;
   S.s0 = s0;
@@ -640,7 +663,7 @@ __global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, Phy
   int gd[KD], icv[KI];
   float iwv[KI];
 #pragma unroll
-  for (int k = 0; k < KD; ++k) gd[k] = pl.tgt[s0 + min((t + k * kChunkThreads) >> 2, cnt - 1)];
+  for (int k = 0; k < KD; ++k) gd[k] = pl.tgt[s0 + min((t + k * kChunkThreads) / ND, cnt - 1)];
 #pragma unroll
   for (int k = 0; k < KI; ++k) {
     const int i = i0 + min(t + k * kChunkThreads, ni - 1);
@@ -654,13 +677,14 @@ __global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, Phy
   }
   __builtin_amdgcn_sched_barrier(0);
   // (2)
-  NSLin<T> q;
-  ns_lin_fetch<T>(lin + (int64_t)ch * kNSLin * kChunkThreads + t, q);
+  const T* ql = lin + (int64_t)ch * NL * kChunkThreads + t;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) q[k] = ql[k * kChunkThreads];
   __builtin_amdgcn_sched_barrier(0);
   // (3)
   TD dv[KD];
 #pragma unroll
-  for (int k = 0; k < KD; ++k) dv[k] = dU[(int64_t)gd[k] * ldD + offD + ((t + k * kChunkThreads) & 3)];
+  for (int k = 0; k < KD; ++k) dv[k] = dU[(int64_t)gd[k] * ldD + offD + (t + k * kChunkThreads) % ND];
   int hid[KH];
   T hwt[KH];
   if (ref < 0) {
@@ -683,7 +707,7 @@ __global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, Phy
 #pragma unroll
   for (int k = 0; k < KD; ++k) {
     const int i = t + k * kChunkThreads;
-    if (i < cnt * 4) S.val[(i >> 2) * SV + (i & 3)] = (T)dv[k];
+    if (i < cnt * ND) S.val[(i / ND) * SV + i % ND] = (T)dv[k];
   }
   // chunks beyond the fixed counts
   for (int i = t + kChunkThreads; i <= cnt; i += kChunkThreads) {
@@ -694,32 +718,50 @@ __global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, Phy
     S.iw[i] = pl.inc_w[i0 + i];
     S.icor[i] = pl.inc_corner[i0 + i];
   }
-  for (int i = t + KD * kChunkThreads; i < cnt * 4; i += kChunkThreads)
-    S.val[(i >> 2) * SV + (i & 3)] = (T)dU[(int64_t)pl.tgt[s0 + (i >> 2)] * ldD + offD + (i & 3)];
+  for (int i = t + KD * kChunkThreads; i < cnt * ND; i += kChunkThreads)
+    S.val[(i / ND) * SV + i % ND] = (T)dU[(int64_t)pl.tgt[s0 + i / ND] * ldD + offD + i % ND];
   __syncthreads();
   // the lane's corner: its node, or its constraint's parents in list order
-  T c[4];
   if (ref >= 0) {
     const T* v = S.val + S.find(ref) * SV;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) c[f] = v[f];
+    for (int f = 0; f < ND; ++f) c[f] = v[f];
   } else {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) c[f] = (T)0;
+    for (int f = 0; f < ND; ++f) c[f] = (T)0;
 #pragma unroll
     for (int k = 0; k < KH; ++k)
       if (h0 + k < h1) {
         const T* v = S.val + S.find(hid[k]) * SV;
 #pragma unroll
-        for (int f = 0; f < 4; ++f) c[f] += hwt[k] * v[f];
+        for (int f = 0; f < ND; ++f) c[f] += hwt[k] * v[f];
       }
     const auto* w = weights<T>(m);
     for (int j = h0 + KH; j < h1; ++j) {
       const T* v = S.val + S.find(m.hids[j]) * SV;
 #pragma unroll
-      for (int f = 0; f < 4; ++f) c[f] += w[j] * v[f];
+      for (int f = 0; f < ND; ++f) c[f] += w[j] * v[f];
     }
   }
+}
+
+// The NS Jacobian-vector product from the cached linearisation points.
+template <class T, class TD>
+__global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
+                                                    const T* __restrict__ lin, const TD* __restrict__ dU,
+                                                    int ldD, int offD, T* __restrict__ partial,
+                                                    const int* skip) {
+  if (skip && *skip) return;  // GMRES control: this step is not needed
+  extern __shared__ double smem_d[];
+  ChunkLDS<T, 0, 4, 4> S;
+  S.carve((char*)smem_d, caps);
+  const int64_t e0 = ((int64_t)blockIdx.x * kChunkThreads + threadIdx.x) >> 3;
+  const int64_t e = e0 < m.E ? e0 : m.E - 1;
+  Lane<T> L;
+  L.init(threadIdx.x & 7, m.level[e]);
+  const int ref = m.elem[e * 8 + L.c];
+  T q[kNSLin], c[4];
+  lin_prologue<T, TD, 4, kNSLin>(S, m, pl, blockIdx.x, ref, lin, dU, ldD, offD, q, c);
   NSPoint<T> P;
   ns_lin_unpack<T>(p, q, L, P);
   VG<T> dvt[3];
@@ -736,7 +778,31 @@ __global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, Phy
   const VG<T> dpt = eval_vg<T>((T)0.5 * c[3], L);
   T r[4];
   ns_jvp_point<T>(p, L, P, dvt, ddv, dpt, r);
-  S.finish((t >> 3) * 8 + L.c, r, partial);
+  S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
+}
+
+// The CH Jacobian-vector product from the cached linearisation points.
+template <class T, class TD>
+__global__ __launch_bounds__(256) void k_ch_jvp_lin(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
+                                                    const T* __restrict__ lin, const TD* __restrict__ dU,
+                                                    int ldD, int offD, T* __restrict__ partial,
+                                                    const int* skip) {
+  if (skip && *skip) return;  // GMRES control: this step is not needed
+  extern __shared__ double smem_d[];
+  ChunkLDS<T, 0, 2, 2> S;
+  S.carve((char*)smem_d, caps);
+  const int64_t e0 = ((int64_t)blockIdx.x * kChunkThreads + threadIdx.x) >> 3;
+  const int64_t e = e0 < m.E ? e0 : m.E - 1;
+  Lane<T> L;
+  L.init(threadIdx.x & 7, m.level[e]);
+  const int ref = m.elem[e * 8 + L.c];
+  T q[kCHLin], c[2];
+  lin_prologue<T, TD, 2, kCHLin>(S, m, pl, blockIdx.x, ref, lin, dU, ldD, offD, q, c);
+  const VG<T> dp = eval_vg<T>(c[0], L);
+  const VG<T> dm = eval_vg<T>(c[1], L);
+  T r[2];
+  ch_jvp_point<T>(p, L, q[0], q[1], q[2], q[3], dp, dm, r);
+  S.finish((threadIdx.x >> 3) * 8 + L.c, r, partial);
 }
 
 // ---------------------------------------------- coupled Jacobian rows ----

@@ -37,11 +37,11 @@ int64_t mesh_footprint(const chns_mesh* m) {
          sz(P.tgt.size() * 4, 8) + sz(P.ntouch_slot.size() * 16, 8);
 }
 
-// Device bytes of the cached NS linearisation points of a mesh (ensure_lin),
-// at the precision of the inner solve.
+// Device bytes of the cached linearisation points of a mesh, both blocks
+// (ensure_lin), at the precision of the inner solve.
 int64_t lin_footprint(const chns_mesh* m, const chns_solver_opts& o) {
   const int64_t chunks = std::max<int64_t>((int64_t)m->plan.tgt_off.size() - 1, 1);
-  return chunks * dev::kNSLin * dev::kChunkThreads * (o.precision == 0 ? 8 : 4);
+  return chunks * (dev::kNSLin + dev::kCHLin) * dev::kChunkThreads * (o.precision == 0 ? 8 : 4);
 }
 
 // Device bytes of Solver::ensure_workspace() for n nodes under opts.

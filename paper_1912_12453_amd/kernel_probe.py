@@ -2,7 +2,7 @@
 size, for hardware counter collection (rocprofv3 --pmc).
 
 Usage: python kernel_probe.py [--workload bubble_l9] [--reps 5] KIND...
-KIND: ns64 ns32 ch64 ch32 nsres chres nsdiag chdiag nslin64 nslin32 copy
+KIND: ns64 ns32 ch64 ch32 nsres chres nsdiag chdiag nslin64 nslin32 chlin64 chlin32 copy
 
 The copy kernel reads and writes 1 GiB; its FETCH_SIZE and WRITE_SIZE give
 the factors that turn the counters into HBM bytes.
@@ -44,11 +44,12 @@ def main():
         "nsres": (1, 0, None), "ns64": (1, 1, dU), "ns32": (1, 2, dU32), "nsdiag": (1, 3, None),
     }
     for k in a.kinds:
-        if k in ("nslin64", "nslin32"):  # linearise once, then the cached JVP
-            op = 4 if k == "nslin64" else 6
-            d = dU if k == "nslin64" else dU32
-            chns.chns_launch_element_loop(m.h, p, 1, op + 1, U1, U0, None, None, 1)
-            chns.chns_launch_element_loop(m.h, p, 1, op, U1, U0, d, None, a.reps)
+        if k in ("nslin64", "nslin32", "chlin64", "chlin32"):  # linearise once, then the cached JVP
+            blk = 1 if k.startswith("ns") else 0
+            op = 4 if k.endswith("64") else 6
+            d = dU if k.endswith("64") else dU32
+            chns.chns_launch_element_loop(m.h, p, blk, op + 1, U1, U0, None, None, 1)
+            chns.chns_launch_element_loop(m.h, p, blk, op, U1, U0, d, None, a.reps)
         elif k == "copy":
             src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
             dst = torch.empty_like(src)

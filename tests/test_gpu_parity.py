@@ -144,35 +144,39 @@ def test_coupled_jacobian_rows(torch, chns, orc, kind):
 def test_cached_linearisation_jvp(torch, chns, orc, kind):
     """chns_jvp_lin after chns_linearize matches the oracle to 1e-12 and
     chns_jvp to rounding (the two kernels may contract multiply-adds across
-    the point/derivative boundary differently); the cache follows the last
-    linearize."""
+    the point/derivative boundary differently), for both blocks; each cache
+    follows the last linearize of its block."""
     pm, om = mesh_pair(chns, orc, kind)
     print(f"case jvp_lin {kind} E={pm.n_leaves}", flush=True)
     ph = W.moderate_physics()
     p = chns.make_params(ph)
+    po = orc.Params.make(**vars(ph))
     U1, U0 = W.random_state(pm.n_nodes, 210)
     dU = W.direction(pm.n_nodes, 310)
     d1, d0, ddU = to_dev(torch, U1), to_dev(torch, U0), to_dev(torch, dU)
-    ref = om.jvp(orc.Params.make(**vars(ph)), NS, U1, U0, dU)
-    pm.linearize(p, NS, d1, d0)
-    J = pm.jvp_lin(p, NS, ddU).cpu().numpy()
-    compare(J, ref, slice(2, 6), label=f"jvp_lin64 {kind}")
-    compare(J, pm.jvp(p, NS, d1, d0, ddU).cpu().numpy(), slice(2, 6), tol=1e-14,
-            label=f"jvp_lin64 vs jvp64 {kind}")
     ddU32 = to_dev(torch, dU, torch.float32)
-    pm.linearize(p, NS, d1, d0, prec=chns.CHNS_F32)
-    J32 = pm.jvp_lin(p, NS, ddU32, prec=chns.CHNS_F32).cpu().numpy().astype(np.float64)
-    compare(J32, pm.jvp(p, NS, d1, d0, ddU32, prec=chns.CHNS_F32).cpu().numpy().astype(np.float64),
-            slice(2, 6), tol=1e-5, label=f"jvp_lin32 vs jvp32 {kind}")
-    compare(J32, ref, slice(2, 6), tol=1e-4, label=f"jvp_lin32 {kind}")
-    # a new linearisation point replaces the cache
+    for blk, f in ((CH, slice(0, 2)), (NS, slice(2, 6))):
+        name = "ch" if blk == CH else "ns"
+        ref = om.jvp(po, blk, U1, U0, dU)
+        pm.linearize(p, blk, d1, d0)
+        J = pm.jvp_lin(p, blk, ddU).cpu().numpy()
+        compare(J, ref, f, label=f"{name} jvp_lin64 {kind}")
+        compare(J, pm.jvp(p, blk, d1, d0, ddU).cpu().numpy(), f, tol=1e-14,
+                label=f"{name} jvp_lin64 vs jvp64 {kind}")
+        pm.linearize(p, blk, d1, d0, prec=chns.CHNS_F32)
+        J32 = pm.jvp_lin(p, blk, ddU32, prec=chns.CHNS_F32).cpu().numpy().astype(np.float64)
+        compare(J32, pm.jvp(p, blk, d1, d0, ddU32, prec=chns.CHNS_F32).cpu().numpy().astype(np.float64),
+                f, tol=1e-5, label=f"{name} jvp_lin32 vs jvp32 {kind}")
+        compare(J32, ref, f, tol=1e-4, label=f"{name} jvp_lin32 {kind}")
+    # a new linearisation point replaces the cache of its block only
     U1b, U0b = W.random_state(pm.n_nodes, 211)
     pm.linearize(p, NS, to_dev(torch, U1b), to_dev(torch, U0b))
     Jb = pm.jvp_lin(p, NS, ddU).cpu().numpy()
-    refb = om.jvp(orc.Params.make(**vars(ph)), NS, U1b, U0b, dU)
-    compare(Jb, refb, slice(2, 6), label=f"jvp_lin64 relinearised {kind}")
+    compare(Jb, om.jvp(po, NS, U1b, U0b, dU), slice(2, 6), label=f"ns jvp_lin64 relinearised {kind}")
+    Jc = pm.jvp_lin(p, CH, ddU).cpu().numpy()
+    compare(Jc, om.jvp(po, CH, U1, U0, dU), slice(0, 2), label=f"ch jvp_lin64 kept {kind}")
     with pytest.raises(chns.ChnsError):
-        pm.linearize(p, CH, d1, d0)
+        pm.linearize(p, 7, d1, d0)
 
 
 @pytest.mark.parametrize("kind", ["single", "adaptive", "brick", "drop16"])
