@@ -166,6 +166,7 @@ struct chns_mesh {
   uint8_t *d_inc_corner = nullptr, *d_bflags = nullptr;
   float* d_inc_w = nullptr;
   int64_t *d_touch_off = nullptr, *d_ntouch_off = nullptr, *d_ntouch_slot = nullptr;
+  int32_t* d_touch_node = nullptr;
   double* d_partial = nullptr;  // target slots x 4 (FP64), or x 8 FP32 values
   double* d_tbuf = nullptr;     // element touches x 16, allocated on first diagonal
   int64_t n_chunks = 0;
@@ -217,6 +218,7 @@ dev::PlanView plan_view(const chns_mesh* m) {
   v.node_off = m->d_node_off;
   v.node_slot = m->d_node_slot;
   v.touch_off = m->d_touch_off;
+  v.touch_node = m->d_touch_node;
   v.ntouch_off = m->d_ntouch_off;
   v.ntouch_slot = m->d_ntouch_slot;
   v.bflags = m->d_bflags;
@@ -312,6 +314,7 @@ int upload(chns_mesh* m, hipStream_t s) {
       (rc = dalloc(&m->d_node_off, P.node_off.size(), &B)) ||
       (rc = dalloc(&m->d_node_slot, P.node_slot.size(), &B)) ||
       (rc = dalloc(&m->d_touch_off, P.touch_off.size(), &B)) ||
+      (rc = dalloc(&m->d_touch_node, P.touch_node.size(), &B)) ||
       (rc = dalloc(&m->d_ntouch_off, P.ntouch_off.size(), &B)) ||
       (rc = dalloc(&m->d_ntouch_slot, P.ntouch_slot.size(), &B)) ||
       (rc = dalloc(&m->d_bflags, h.bflags.size(), &B)) ||
@@ -327,6 +330,7 @@ int upload(chns_mesh* m, hipStream_t s) {
       (rc = h2d(m->d_inc_corner, P.inc_corner, s)) ||
       (rc = h2d(m->d_inc_w, P.inc_w, s)) || (rc = h2d(m->d_node_off, P.node_off, s)) ||
       (rc = h2d(m->d_node_slot, P.node_slot, s)) || (rc = h2d(m->d_touch_off, P.touch_off, s)) ||
+      (rc = h2d(m->d_touch_node, P.touch_node, s)) ||
       (rc = h2d(m->d_ntouch_off, P.ntouch_off, s)) ||
       (rc = h2d(m->d_ntouch_slot, P.ntouch_slot, s)) || (rc = h2d(m->d_bflags, h.bflags, s)))
     return rc;
@@ -1504,7 +1508,7 @@ void free_mesh_locked(chns_mesh* m) {
                   m->d_hw, m->d_hw32, m->d_flag, m->d_part, m->d_sum,
                   m->d_tgt_off, m->d_tgt, m->d_inc_off, m->d_chunk_inc, m->d_node_off, m->d_node_slot,
                   m->d_inc_corner,
-                  m->d_bflags, m->d_inc_w, m->d_touch_off, m->d_ntouch_off, m->d_ntouch_slot,
+                  m->d_bflags, m->d_inc_w, m->d_touch_off, m->d_touch_node, m->d_ntouch_off, m->d_ntouch_slot,
                   m->d_partial, m->d_tbuf, m->d_lin[0][0], m->d_lin[0][1], m->d_lin[1][0], m->d_lin[1][1]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);

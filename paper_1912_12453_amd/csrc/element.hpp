@@ -181,6 +181,7 @@ struct PlanView {
   const int32_t* node_off;    // per node
   const int32_t* node_slot;
   const int64_t* touch_off;   // per element
+  const int32_t* touch_node;  // per element touch: the node
   const int64_t* ntouch_off;  // per node
   const int64_t* ntouch_slot;
   const uint8_t* bflags;      // per node

@@ -78,6 +78,7 @@ struct ScatterPlan {
   std::vector<float> inc_w;
   std::vector<int32_t> node_off, node_slot;
   std::vector<int64_t> touch_off;
+  std::vector<int32_t> touch_node;  // per element touch: the node
   std::vector<int64_t> ntouch_off, ntouch_slot;
   int max_targets = 0;  // targets of the largest chunk
   int max_inc = 0;      // incidences of the largest chunk

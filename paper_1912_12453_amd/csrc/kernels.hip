@@ -955,90 +955,146 @@ __global__ void k_gather_diag(PlanView pl, int64_t n, const double* __restrict__
 // ------------------------------------------------- node-block diagonal ----
 // Diagonal block of node n: sum over elements of sum_{c,c'} P_cn P_c'n J_e[c][c'],
 // where P_cn is 1 when corner c is node n, the constraint weight of n when c
-// hangs on n, and 0 otherwise.  Each element visits the nodes it touches (its
-// own corners, then the parents of its hanging corners not seen before); for
-// each node and each block field the seed P_.n e_f goes through the same
-// linearised integrand as the JVP.
-template <class T>
-__device__ __forceinline__ T seed_weight(const MeshView& m, int ref, int n) {
-  if (ref >= 0) return ref == n ? (T)1 : (T)0;
-  const int h = -1 - ref;
-  const auto* w = weights<T>(m);
-  for (int t = m.hoff[h]; t < m.hoff[h + 1]; ++t)
-    if (m.hids[t] == n) return w[t];
-  return (T)0;
-}
+// hangs on n, and 0 otherwise.  The element Jacobian is bilinear in (test,
+// trial) function, so an element's share is the linearised integrand with
+// the element's restriction of node n's shape function, s_n = sum_c P_cn N_c,
+// as both the seed of field f and the test function of row i.  Each element
+// visits the nodes it touches in the plan's order (touch_node); the lane
+// evaluates s_n and its gradient at its Gauss point from its own corner's
+// weight, and the 8 lanes sum.
 
-__device__ __forceinline__ int lane_of_corner(int c) {
-  const int bx = c & 1, by = (c >> 1) & 1, bz = c >> 2;
-  return bx ^ (by ? 2 : 0) ^ (bz ? 7 : 0);
-}
-
-template <class T, int BLOCK>
-__device__ __forceinline__ void diag_regular(const PhysView& p, const Lane<T>& L,
-                                             const NSPoint<T>& P, T ch_pt, const T (&ch_v)[3],
-                                             double* __restrict__ out, bool valid) {
-  constexpr int NF = BLOCK == 0 ? 2 : 4;
-  const T A = (T)kA, B = (T)kB;
-  const bool qx = L.sxh > (T)0, qy = L.syh > (T)0, qz = L.szh > (T)0;
-  const T ih = L.ih, w = L.wdet;
-#pragma unroll 1
-  for (int a = 0; a < 8; ++a) {
-    // seed N_a at this Gauss point: shape factor A on an axis where the corner
-    // and the point share a side, B otherwise
-    const bool ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-    const T mx = ax == qx ? A : B, my = ay == qy ? A : B, mz = az == qz ? A : B;
-    const T N = mx * my * mz;
-    const T gx = (ax ? ih : -ih) * my * mz, gy = (ay ? ih : -ih) * mx * mz,
-            gz = (az ? ih : -ih) * mx * my;
-#pragma unroll 1
-    for (int f = 0; f < NF; ++f) {
-      T c[NF], F[NF][3];
-      if (BLOCK == 1) {
-        VG<T> dvt[3];
-        T ddv[3];
+// The NS linearised integrand (ns_jvp_coef) for a seed s in field FLD only
+// (velocity component FLD < 3: dvt_FLD = s/2, ddv_FLD = s.v; pressure FLD == 3:
+// dpt = s/2).  The terms of the other fields, which are zero, are left out.
+template <class T, int FLD>
+__device__ __forceinline__ void ns_seed_coef(const PhysView& p, const NSPoint<T>& P, const VG<T>& s,
+                                             T (&c)[4], T (&F)[4][3]) {
+  const T iPe = (T)p.inv_Pe, iWe = (T)p.inv_We, tm = P.tau_m, ir = P.inv_rho;
+  const T er = P.eta * (T)p.inv_Re, idt = (T)p.inv_dt;
+  const T g[3] = {s.dx, s.dy, s.dz};
+  const T hv = (T)0.5 * s.v;
+  T W[3], dTR[3], dW[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const T sd = f == i ? (T)1 : (T)0;
-          ddv[i] = sd * N;
-          dvt[i].v = (T)0.5 * sd * N;
-          dvt[i].dx = (T)0.5 * sd * gx;
-          dvt[i].dy = (T)0.5 * sd * gy;
-          dvt[i].dz = (T)0.5 * sd * gz;
-        }
-        const T sp = f == 3 ? (T)0.5 : (T)0;
-        VG<T> dpt;
-        dpt.v = sp * N;
-        dpt.dx = sp * gx;
-        dpt.dy = sp * gy;
-        dpt.dz = sp * gz;
-        T c4[4], F4[4][3];
-        ns_jvp_coef<T>(p, P, dvt, ddv, dpt, c4, F4);
+  for (int j = 0; j < 3; ++j) W[j] = P.vt[j] + (P.J[j] * iPe - tm * P.Rm[j]) * ir;
+  if constexpr (FLD < 3) {
+    constexpr int f = FLD;
+    T dRm[3];
 #pragma unroll
-        for (int i = 0; i < NF; ++i) {
-          c[i] = c4[i];
-          F[i][0] = F4[i][0];
-          F[i][1] = F4[i][1];
-          F[i][2] = F4[i][2];
-        }
-      } else {
-        const T dp = f == 0 ? (T)1 : (T)0, dm = f == 1 ? (T)1 : (T)0;
-        const T hk = (T)0.5 * (T)p.inv_PeCn, hc = (T)0.5 * (T)p.Cn2, hp = (T)0.5 * dp * N;
-        c[0] = dp * N * (T)p.inv_dt;
-        F[0][0] = hk * dm * gx - ch_v[0] * hp;
-        F[0][1] = hk * dm * gy - ch_v[1] * hp;
-        F[0][2] = hk * dm * gz - ch_v[2] * hp;
-        c[1] = ((T)3 * ch_pt * ch_pt - (T)1) * hp - (T)0.5 * dm * N;
-        F[1][0] = hc * dp * gx;
-        F[1][1] = hc * dp * gy;
-        F[1][2] = hc * dp * gz;
-      }
+    for (int i = 0; i < 3; ++i) dRm[i] = P.rho * hv * P.G[i][f];
+    dRm[f] += P.rho * s.v * idt + (T)0.5 * (P.adv[0] * g[0] + P.adv[1] * g[1] + P.adv[2] * g[2]);
+    const T dRc = (T)0.5 * g[f];
+    const T dbr = (T)2 * P.Gh * (P.vt[f] * hv) + P.Gh * (P.J[f] * hv) * ir * iPe;
+    const T dtm = (T)-0.5 * tm * tm * tm * dbr;
+    const T dtc = -P.tau_c * dtm * P.sbr;
 #pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        const T t = group_sum<T>(w * (N * c[i] + gx * F[i][0] + gy * F[i][1] + gz * F[i][2]));
-        if (valid && L.c == a) out[a * NF * NF + i * NF + f] = (double)t;
-      }
+    for (int j = 0; j < 3; ++j) {
+      dTR[j] = dtm * P.Rm[j] + tm * dRm[j];
+      dW[j] = -dTR[j] * ir;
     }
+    dW[f] += hv;
+    const T dgl = iWe * (P.rho * (dtc * P.Rc + P.tau_c * dRc));
+    const T A[3] = {P.rho * P.vt[0] + iPe * P.J[0] - tm * P.Rm[0], P.rho * P.vt[1] + iPe * P.J[1] - tm * P.Rm[1],
+                    P.rho * P.vt[2] + iPe * P.J[2] - tm * P.Rm[2]};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T ci = P.rho * hv * P.G[i][f] - (dTR[0] * P.G[i][0] + dTR[1] * P.G[i][1] + dTR[2] * P.G[i][2]);
+      if (i == f) ci += P.rho * s.v * idt + (T)0.5 * (A[0] * g[0] + A[1] * g[1] + A[2] * g[2]);
+      c[i] = ci;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) F[i][j] = dTR[i] * W[j] + P.Rm[i] * tm * dW[j];
+      if (i == f)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) F[i][j] += er * (T)0.5 * g[j];
+      F[i][i] += dgl;
+    }
+    c[3] = dRc;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      dTR[j] = tm * (iWe * (T)0.5 * g[j]);
+      dW[j] = -dTR[j] * ir;
+    }
+    const T dgl = -iWe * hv;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      c[i] = -(dTR[0] * P.G[i][0] + dTR[1] * P.G[i][1] + dTR[2] * P.G[i][2]);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) F[i][j] = dTR[i] * W[j] + P.Rm[i] * tm * dW[j];
+      F[i][i] += dgl;
+    }
+    c[3] = (T)0;
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) F[3][j] = dTR[j] * ir;
+}
+
+// The CH linearised integrand (ch_jvp_point before the test functions) for a
+// seed s in phi (FLD 0) or in mu (FLD 1) only.
+template <class T, int FLD>
+__device__ __forceinline__ void ch_seed_coef(const PhysView& p, T dpsi, const T (&v)[3], const VG<T>& s,
+                                             T (&c)[2], T (&F)[2][3]) {
+  const T g[3] = {s.dx, s.dy, s.dz};
+  if constexpr (FLD == 0) {
+    const T hp = (T)0.5 * s.v, hc = (T)0.5 * (T)p.Cn2;
+    c[0] = s.v * (T)p.inv_dt;
+    c[1] = dpsi * hp;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      F[0][j] = -v[j] * hp;
+      F[1][j] = hc * g[j];
+    }
+  } else {
+    const T hk = (T)0.5 * (T)p.inv_PeCn;
+    c[0] = (T)0;
+    c[1] = (T)-0.5 * s.v;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      F[0][j] = hk * g[j];
+      F[1][j] = (T)0;
+    }
+  }
+}
+
+// Column FF of the NS node block at the lane's Gauss point: the seed s_n in
+// field FF tested against s_n in every row i, v[i * 4 + FF].
+template <class T, int FF>
+__device__ __forceinline__ void ns_diag_column(const PhysView& p, const NSPoint<T>& P, const VG<T>& s, T w,
+                                               T (&v)[16]) {
+  T c[4], F[4][3];
+  ns_seed_coef<T, FF>(p, P, s, c, F);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i * 4 + FF] = w * (s.v * c[i] + s.dx * F[i][0] + s.dy * F[i][1] + s.dz * F[i][2]);
+}
+
+// Sum of 16 values over the 8 lanes of an element, scattered: lane l gets the
+// sums of values 2l and 2l+1.  Three exchange stages (partners l^7, l^2, l^1)
+// each halve the values a lane keeps; the order of the additions is fixed.
+template <class T>
+__device__ __forceinline__ void group_reduce_scatter16(T (&v)[16], int lane8, T& out0, T& out1) {
+  T a[8], b[4];
+  const bool u2 = (lane8 >> 2) & 1, u1 = (lane8 >> 1) & 1, u0 = lane8 & 1;
+  // value k belongs to lane k >> 1: values 0..7 to lanes 0..3 (bit 2 clear),
+  // 8..15 to lanes 4..7; each lane keeps the half its bit 2 selects
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const T send = u2 ? v[j] : v[j + 8];
+    const T keep = u2 ? v[j + 8] : v[j];
+    a[j] = keep + xchg<kXor7>(send);
+  }
+  // a[j]: value (u2 ? 8 : 0) + j; owners differ in bit 1 for j >> 2
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const T send = u1 ? a[j] : a[j + 4];
+    const T keep = u1 ? a[j + 4] : a[j];
+    b[j] = keep + xchg<kXor2>(send);
+  }
+  // b[j]: value (u2 ? 8 : 0) + (u1 ? 4 : 0) + j; owners differ in bit 0 for j >> 1
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const T send = u0 ? b[j] : b[j + 2];
+    const T keep = u0 ? b[j + 2] : b[j];
+    const T r = keep + xchg<kXor1>(send);
+    if (j == 0) out0 = r; else out1 = r;
   }
 }
 
@@ -1048,11 +1104,11 @@ __global__ __launch_bounds__(256) void k_diag(MeshView m, PlanView pl, PhysView 
                                               const double* __restrict__ U0,
                                               double* __restrict__ tbuf) {
   constexpr int NF = BLOCK == 0 ? 2 : 4;
+  constexpr int KH = 4;
   const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const bool valid = e0 < m.E;
   const int64_t e = valid ? e0 : m.E - 1;
   const int lane8 = threadIdx.x & 7;
-  const int base = threadIdx.x & ~7;
   Lane<T> L;
   L.init(lane8, m.level[e]);
   const int ref = m.elem[e * 8 + L.c];
@@ -1060,100 +1116,77 @@ __global__ __launch_bounds__(256) void k_diag(MeshView m, PlanView pl, PhysView 
   gather<double, T, 6>(m, ref, U1, 6, 0, a);
   gather<double, T, 6>(m, ref, U0, 6, 0, b);
   NSPoint<T> P;
-  T ch_pt = 0, ch_v[3] = {0, 0, 0};
+  T dpsi = 0, ch_v[3] = {0, 0, 0};
   if (BLOCK == 1) {
     ns_point<T>(p, L, a, b, P);
   } else {
-    ch_pt = eval_v<T>((T)0.5 * (a[0] + b[0]));
+    dpsi = ch_dpsi<T>(eval_v<T>((T)0.5 * (a[0] + b[0])));
 #pragma unroll
     for (int d = 0; d < 3; ++d) ch_v[d] = eval_v<T>((T)0.5 * (a[2 + d] + b[2 + d]));
   }
-  // Elements without hanging corners: the diagonal block of corner a is
-  // sum_q wdet [N_a(q) dc(N_a) + grad N_a(q) . dF(N_a)], with the seed N_a e_f
-  // known in closed form at the lane's Gauss point.  Each lane evaluates the
-  // linearised integrand for all 8 corners and NF fields; sums over the
-  // element's lanes give corner a's block, which lane a writes to the element's
-  // touch slot a (direct corners come first, in corner order).
-  const bool hanging = group_sum<float>(ref < 0 ? 1.f : 0.f) > 0.f;
-  if (!hanging) {
-    diag_regular<T, BLOCK>(p, L, P, ch_pt, ch_v, tbuf + pl.touch_off[e] * NF * NF, valid);
-    return;
+  // the lane's corner: its node, or the parents and weights of its constraint
+  int hid[KH];
+  T hwt[KH];
+  int h0 = 0, h1 = 0;
+#pragma unroll
+  for (int k = 0; k < KH; ++k) {
+    hid[k] = -1;
+    hwt[k] = (T)0;
   }
-  // General elements: slot k < 8 is corner k's node when direct; slot
-  // 8 + 8*k + t is parent t of hanging corner k.  The visited nodes are numbered
-  // in visiting order, the order in which the scatter plan lists the element's
-  // touches.
-  const int max_t = 8;
-  int64_t touch = pl.touch_off[e];
-  for (int slot = 0; slot < 8 + 8 * max_t; ++slot) {
-    int n = -1;
-    if (slot < 8) {
-      const int r = __shfl(ref, base + lane_of_corner(slot), 64);
-      n = r >= 0 ? r : -1;
+  const auto* wts = weights<T>(m);
+  if (ref < 0) {
+    h0 = m.hoff[-1 - ref];
+    h1 = m.hoff[-ref];
+#pragma unroll
+    for (int k = 0; k < KH; ++k)
+      if (h0 + k < h1) {
+        hid[k] = m.hids[h0 + k];
+        hwt[k] = wts[h0 + k];
+      }
+  }
+  const T w = L.wdet;
+  const int64_t t0 = pl.touch_off[e], t1 = pl.touch_off[e + 1];  // the same for the element's 8 lanes
+  for (int64_t t = t0; t < t1; ++t) {
+    const int n = pl.touch_node[t];
+    // P_cn of the lane's corner, then s_n at the lane's Gauss point
+    T pw = (T)0;
+    if (ref >= 0) {
+      pw = ref == n ? (T)1 : (T)0;
     } else {
-      const int k = (slot - 8) / max_t, t = (slot - 8) % max_t;
-      const int r = __shfl(ref, base + lane_of_corner(k), 64);
-      if (r < 0) {
-        const int h = -1 - r;
-        if (m.hoff[h] + t < m.hoff[h + 1]) n = m.hids[m.hoff[h] + t];
+#pragma unroll
+      for (int k = 0; k < KH; ++k)
+        if (hid[k] == n) pw += hwt[k];
+      for (int j = h0 + KH; j < h1; ++j)
+        if (m.hids[j] == n) pw += wts[j];
+    }
+    const VG<T> sg = eval_vg<T>(pw, L);
+    T v[NF * NF];
+    if constexpr (BLOCK == 1) {
+      ns_diag_column<T, 0>(p, P, sg, w, v);
+      ns_diag_column<T, 1>(p, P, sg, w, v);
+      ns_diag_column<T, 2>(p, P, sg, w, v);
+      ns_diag_column<T, 3>(p, P, sg, w, v);
+      T r0, r1;
+      group_reduce_scatter16<T>(v, lane8, r0, r1);
+      if (valid) {
+        tbuf[t * 16 + 2 * lane8] = (double)r0;
+        tbuf[t * 16 + 2 * lane8 + 1] = (double)r1;
       }
-      if (n >= 0) {
-        // skip nodes already visited: a direct corner, or a parent of an earlier
-        // hanging corner
-        int seen = 0;
-        if (ref >= 0 && ref == n) seen = 1;
-        if (ref < 0 && L.c < k) {
-          const int h2 = -1 - ref;
-          for (int t2 = m.hoff[h2]; t2 < m.hoff[h2 + 1]; ++t2)
-            if (m.hids[t2] == n) seen = 1;
-        }
-        if (ref < 0 && L.c == k) {
-          const int h2 = -1 - ref;
-          for (int t2 = m.hoff[h2]; t2 < m.hoff[h2] + t; ++t2)
-            if (m.hids[t2] == n) seen = 1;
-        }
-        seen = (int)group_sum<float>((float)seen);
-        if (seen) n = -1;
+    } else {
+      T c[2], F[2][3];
+      ch_seed_coef<T, 0>(p, dpsi, ch_v, sg, c, F);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) v[i * 2] = w * (sg.v * c[i] + sg.dx * F[i][0] + sg.dy * F[i][1] + sg.dz * F[i][2]);
+      ch_seed_coef<T, 1>(p, dpsi, ch_v, sg, c, F);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        v[i * 2 + 1] = w * (sg.v * c[i] + sg.dx * F[i][0] + sg.dy * F[i][1] + sg.dz * F[i][2]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const T sum = group_sum<T>(v[k]);
+        if (valid && lane8 == k) tbuf[t * 4 + k] = (double)sum;
       }
     }
-    if (n < 0) continue;  // uniform across the 8 lanes of the element
-    const T s = seed_weight<T>(m, ref, n);
-    for (int f = 0; f < NF; ++f) {
-      T r[NF];
-      if (BLOCK == 1) {
-        VG<T> dvt[3];
-        T ddv[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const VG<T> g = eval_vg<T>(f == i ? s : (T)0, L);
-          ddv[i] = g.v;
-          dvt[i].v = (T)0.5 * g.v;
-          dvt[i].dx = (T)0.5 * g.dx;
-          dvt[i].dy = (T)0.5 * g.dy;
-          dvt[i].dz = (T)0.5 * g.dz;
-        }
-        const VG<T> dpt = eval_vg<T>(f == 3 ? (T)0.5 * s : (T)0, L);
-        T rr[4];
-        ns_jvp_point<T>(p, L, P, dvt, ddv, dpt, rr);
-#pragma unroll
-        for (int q = 0; q < NF; ++q) r[q] = rr[q];
-      } else {
-        const VG<T> dp = eval_vg<T>(f == 0 ? s : (T)0, L);
-        const VG<T> dm = eval_vg<T>(f == 1 ? s : (T)0, L);
-        const T w = L.wdet, hk = (T)0.5 * (T)p.inv_PeCn, hc = (T)0.5 * (T)p.Cn2,
-                hp = (T)0.5 * dp.v;
-        r[0] = test_contract<T>(w * dp.v * (T)p.inv_dt, w * (hk * dm.dx - ch_v[0] * hp),
-                                w * (hk * dm.dy - ch_v[1] * hp), w * (hk * dm.dz - ch_v[2] * hp), L);
-        r[1] = test_contract<T>(w * ((T)3 * ch_pt * ch_pt - (T)1) * hp - w * (T)0.5 * dm.v,
-                                w * hc * dp.dx, w * hc * dp.dy, w * hc * dp.dz, L);
-      }
-#pragma unroll
-      for (int q = 0; q < NF; ++q) {
-        const T col = group_sum<T>(s * r[q]);
-        if (valid && lane8 == q) tbuf[touch * NF * NF + q * NF + f] = (double)col;
-      }
-    }
-    ++touch;
   }
 }
 

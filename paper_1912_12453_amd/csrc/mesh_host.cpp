@@ -452,7 +452,7 @@ std::string build_scatter_plan(const HostMesh& m, ScatterPlan& P) {
   }
   // touched nodes per element, in the order the diagonal kernel visits them
   P.touch_off.assign(E + 1, 0);
-  std::vector<int32_t> touch;
+  std::vector<int32_t>& touch = P.touch_node;
   touch.reserve(E * 9);
   for (int64_t e = 0; e < E; ++e) {
     const size_t start = touch.size();

@@ -32,7 +32,7 @@ int64_t mesh_footprint(const chns_mesh* m) {
          sz(1, 4) + sz(E * 2, 8) + sz(2, 8) + sz(P.tgt_off.size(), 4) + sz(P.tgt.size(), 4) +
          sz(P.inc_off.size(), 4) + sz(P.chunk_inc.size(), 4) + sz(P.inc_corner.size(), 1) +
          sz(P.inc_w.size(), 4) +
-         sz(P.node_off.size(), 4) + sz(P.node_slot.size(), 4) + sz(P.touch_off.size(), 8) +
+         sz(P.node_off.size(), 4) + sz(P.node_slot.size(), 4) + sz(P.touch_off.size(), 8) + sz(P.touch_node.size(), 4) +
          sz(P.ntouch_off.size(), 8) + sz(P.ntouch_slot.size(), 8) + sz(h.bflags.size(), 1) +
          sz(P.tgt.size() * 4, 8) + sz(P.ntouch_slot.size() * 16, 8);
 }
