@@ -476,6 +476,25 @@ int launch_lin(chns_mesh* m, const dev::PhysView& pv, int block, const TS* U1, c
   return CHNS_OK;
 }
 
+// The element pass of a cached JVP alone (partials; the caller gathers).
+template <class T, class TD>
+int launch_jvp_lin_elements(chns_mesh* m, const dev::PhysView& pv, int block, const TD* dU, int ldD, int offD,
+                            hipStream_t s, const int* skip) {
+  const T* lin = (const T*)m->d_lin[block][std::is_same<T, double>::value ? 0 : 1];
+  if (!lin) return fail(CHNS_EINVAL, "no linearisation point: call chns_linearize first");
+  const dev::ChunkCaps cc = caps(m);
+  const dim3 g((unsigned)m->n_chunks), b(dev::kChunkThreads);
+  T* part = (T*)m->d_partial;
+  if (block == CHNS_BLOCK_CH)
+    hipLaunchKernelGGL((dev::k_ch_jvp_lin<T, TD>), g, b, (dev::ChunkLDS<T, 0, 2, 2>::bytes(cc)), s, view(m),
+                       plan_view(m), pv, cc, lin, dU, ldD, offD, part, skip);
+  else
+    hipLaunchKernelGGL((dev::k_ns_jvp_lin<T, TD>), g, b, (dev::ChunkLDS<T, 0, 4, 4>::bytes(cc)), s, view(m),
+                       plan_view(m), pv, cc, lin, dU, ldD, offD, part, skip);
+  HIPCHK(hipGetLastError());
+  return CHNS_OK;
+}
+
 template <class T, class TD>
 int launch_jvp_lin(chns_mesh* m, const dev::PhysView& pv, int block, const TD* dU, int ldD, int offD, TD* out,
                    int ldO, int offO, hipStream_t s, const int* skip = nullptr) {
@@ -784,34 +803,40 @@ struct Solver {
     using TM = TV;  // the block inverse is used at the basis precision
     MGLevel& L = m->mg[l];
     chns_mesh* mm = L.mesh;
-    const int64_t nl = L.n, N = nl * NF;
+    const int64_t nl = L.n;
     const bool dbl = std::is_same<TV, double>::value;
     TV* r = dbl ? (TV*)L.r64 : (TV*)L.r32;
     const bool ch = block == CHNS_BLOCK_CH;
     const TM* Di = l == 0 ? (dbl ? (const TM*)(ch ? w.DiC : w.Di) : (const TM*)(ch ? w.DiC32 : w.Di32))
                           : (dbl ? (const TM*)(ch ? L.DiC : L.Di) : (const TM*)(ch ? L.DiC32 : L.Di32));
-    const dim3 g(grid_stride(nl)), gs(grid_stride(N)), bl(256);
-    auto A = [&](const TV* in, TV* out) {
-      return launch_jvp_lin<TV, TV>(mm, pv, block, in, NF, 0, out, NF, 0, s, skip);
-    };
-    auto jac = [&](const TV* Ax) {
-      hipLaunchKernelGGL((dev::k_jacobi<NF, TV, TM>), g, bl, 0, s, Di, b, Ax, x, mm->d_bflags, block,
-                         o.mg_omega, nl, skip);
+    const dim3 g(grid_stride(nl)), bl(256);
+    const TV* part = (const TV*)mm->d_partial;
+    const auto pl = plan_view(mm);
+    // one sweep: the element pass of A x, then the node gather fused with the
+    // Jacobi update (EPI 1) or with the residual b - A x into r (EPI 2)
+    auto sweep = [&](bool residual) -> int {
+      int rc = launch_jvp_lin_elements<TV, TV>(mm, pv, block, x, NF, 0, s, skip);
+      if (rc) return rc;
+      if (residual)
+        hipLaunchKernelGGL((dev::k_gather_vcycle<NF, TV, TM, 2>), g, bl, 0, s, pl, nl, part, block, x, b, Di,
+                           o.mg_omega, r, skip);
+      else
+        hipLaunchKernelGGL((dev::k_gather_vcycle<NF, TV, TM, 1>), g, bl, 0, s, pl, nl, part, block, x, b, Di,
+                           o.mg_omega, r, skip);
+      return CHNS_OK;
     };
     const bool coarsest = l + 1 == m->mg.size();
     const int pre = coarsest ? o.mg_coarse_sweeps : o.mg_smooth;
     int rc;
-    jac(nullptr);
-    for (int i = 1; i < pre; ++i) {
-      if ((rc = A(x, r))) return rc;
-      jac(r);
-    }
+    hipLaunchKernelGGL((dev::k_jacobi<NF, TV, TM>), g, bl, 0, s, Di, b, (const TV*)nullptr, x, mm->d_bflags, block,
+                       o.mg_omega, nl, skip);  // x = omega Di b
+    for (int i = 1; i < pre; ++i)
+      if ((rc = sweep(false))) return rc;
     if (coarsest) {
       HIPCHK(hipGetLastError());
       return CHNS_OK;
     }
-    if ((rc = A(x, r))) return rc;
-    hipLaunchKernelGGL(dev::k_rsub<TV>, gs, bl, 0, s, r, b, N, skip);
+    if ((rc = sweep(true))) return rc;
     MGLevel& C = m->mg[l + 1];
     TV* bc = dbl ? (TV*)C.b64 : (TV*)C.b32;
     TV* xc = dbl ? (TV*)C.x64 : (TV*)C.x32;
@@ -820,10 +845,8 @@ struct Solver {
     if ((rc = vcycle<TV, NF>(block, l + 1, bc, xc, skip, U1, U0))) return rc;
     hipLaunchKernelGGL((dev::k_prolong_add<NF, TV>), g, bl, 0, s, x, mm->d_bflags, L.p_off, L.p_idx, L.p_w, nl,
                        xc, block, skip);
-    for (int i = 0; i < o.mg_smooth; ++i) {
-      if ((rc = A(x, r))) return rc;
-      jac(r);
-    }
+    for (int i = 0; i < o.mg_smooth; ++i)
+      if ((rc = sweep(false))) return rc;
     HIPCHK(hipGetLastError());
     return CHNS_OK;
   }

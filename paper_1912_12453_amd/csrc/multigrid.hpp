@@ -108,6 +108,56 @@ __global__ void k_jacobi(const TM* __restrict__ Di, const TV* __restrict__ b, co
   }
 }
 
+// The node gather of a V-cycle JVP v = A x (block vectors, NF fields per
+// node; NS boundary rows are the identity rows of x) fused with what the
+// cycle does next with v:
+//   EPI 1  damped node-block Jacobi x += omega Di (b - v), omega = 1 on the
+//          Dirichlet rows (as k_jacobi, same arithmetic);
+//   EPI 2  the residual r = b - v (as k_rsub).
+template <int NF, class TV, class TM, int EPI>
+__global__ void k_gather_vcycle(PlanView pl, int64_t n, const TV* __restrict__ partial, int block,
+                                TV* __restrict__ x, const TV* __restrict__ b, const TM* __restrict__ Di,
+                                double omega, TV* __restrict__ r, const int* skip) {
+  if (skip && *skip) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    TV acc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] = 0;
+    for (int k = pl.node_off[i]; k < pl.node_off[i + 1]; ++k) {
+      const int64_t sl = pl.node_slot[k];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) acc[f] += partial[sl * NF + f];
+    }
+    const uint8_t bb = pl.bflags[i];
+    if (NF == 4 && block == 1) {
+      if (bb & 1)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc[d] = x[i * NF + d];
+      if (bb & 2) acc[3] = x[i * NF + 3];
+    }
+    if constexpr (EPI == 1) {
+      TM rr[NF];
+#pragma unroll
+      for (int c = 0; c < NF; ++c) rr[c] = (TM)b[i * NF + c] - (TM)acc[c];
+      TV xn[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        TM sum = 0;
+#pragma unroll
+        for (int c = 0; c < NF; ++c) sum += Di[i * NF * NF + f * NF + c] * rr[c];
+        const TM om = dirichlet_row(bb, block, f) ? (TM)1 : (TM)omega;
+        xn[f] = (TV)((TM)x[i * NF + f] + om * sum);
+      }
+#pragma unroll
+      for (int f = 0; f < NF; ++f) x[i * NF + f] = xn[f];
+    } else {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) r[i * NF + f] = b[i * NF + f] - acc[f];
+    }
+  }
+}
+
 // Ut[i] = sum_k w[k] * Uf[idx[k]] for the 6 fields of node i (intergrid
 // transfer, in the list's fixed order)
 __global__ void k_interp6(const double* __restrict__ Uf, const int32_t* __restrict__ off,
