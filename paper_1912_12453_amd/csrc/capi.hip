@@ -799,7 +799,8 @@ struct Solver {
   // Level 0 is the Krylov system itself: its operator is the Jacobian of
   // (U1, U0) and its block inverse the Newton iteration's w.Di.
   template <class TV, int NF>
-  int vcycle(int block, size_t l, const TV* b, TV* x, const int* skip, const double* U1, const double* U0) {
+  int vcycle(int block, size_t l, const TV* b, TV* x, const int* skip, const double* U1, const double* U0,
+             bool x_ready = false) {
     using TM = TV;  // the block inverse is used at the basis precision
     MGLevel& L = m->mg[l];
     chns_mesh* mm = L.mesh;
@@ -828,8 +829,9 @@ struct Solver {
     const bool coarsest = l + 1 == m->mg.size();
     const int pre = coarsest ? o.mg_coarse_sweeps : o.mg_smooth;
     int rc;
-    hipLaunchKernelGGL((dev::k_jacobi<NF, TV, TM>), g, bl, 0, s, Di, b, (const TV*)nullptr, x, mm->d_bflags, block,
-                       o.mg_omega, nl, skip);  // x = omega Di b
+    if (!x_ready)  // x = omega Di b (coarser levels get it from the restriction)
+      hipLaunchKernelGGL((dev::k_jacobi<NF, TV, TM>), g, bl, 0, s, Di, b, (const TV*)nullptr, x, mm->d_bflags,
+                         block, o.mg_omega, nl, skip);
     for (int i = 1; i < pre; ++i)
       if ((rc = sweep(false))) return rc;
     if (coarsest) {
@@ -840,9 +842,10 @@ struct Solver {
     MGLevel& C = m->mg[l + 1];
     TV* bc = dbl ? (TV*)C.b64 : (TV*)C.b32;
     TV* xc = dbl ? (TV*)C.x64 : (TV*)C.x32;
-    hipLaunchKernelGGL((dev::k_restrict<NF, TV>), dim3(grid_stride(C.n)), bl, 0, s, r, mm->d_bflags, L.r_off,
-                       L.r_idx, L.r_w, C.n, C.mesh->d_bflags, block, bc, skip);
-    if ((rc = vcycle<TV, NF>(block, l + 1, bc, xc, skip, U1, U0))) return rc;
+    const TM* Dic = dbl ? (const TM*)(ch ? C.DiC : C.Di) : (const TM*)(ch ? C.DiC32 : C.Di32);
+    hipLaunchKernelGGL((dev::k_restrict<NF, TV, TM>), dim3(grid_stride(C.n)), bl, 0, s, r, mm->d_bflags, L.r_off,
+                       L.r_idx, L.r_w, C.n, C.mesh->d_bflags, block, bc, Dic, o.mg_omega, xc, skip);
+    if ((rc = vcycle<TV, NF>(block, l + 1, bc, xc, skip, U1, U0, true))) return rc;
     hipLaunchKernelGGL((dev::k_prolong_add<NF, TV>), g, bl, 0, s, x, mm->d_bflags, L.p_off, L.p_idx, L.p_w, nl,
                        xc, block, skip);
     for (int i = 0; i < o.mg_smooth; ++i)

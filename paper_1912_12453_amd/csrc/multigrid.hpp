@@ -30,12 +30,15 @@ __global__ void k_inject6(const double* __restrict__ Uf, const int32_t* __restri
 }
 
 // rc[j] = sum over the fine nodes i of node j's list of w * rf[i], Dirichlet
-// rows (fine and coarse) excluded
-template <int NF, class TV>
+// rows (fine and coarse) excluded.  With xc set, the coarse level's first
+// Jacobi step xc = omega Dic rc follows in the same kernel (as k_jacobi
+// without Ax, same arithmetic).
+template <int NF, class TV, class TM>
 __global__ void k_restrict(const TV* __restrict__ rf, const uint8_t* __restrict__ bf_f,
                            const int32_t* __restrict__ r_off, const int32_t* __restrict__ r_idx,
                            const double* __restrict__ r_w, int64_t nc, const uint8_t* __restrict__ bf_c,
-                           int block, TV* __restrict__ rc, const int* skip) {
+                           int block, TV* __restrict__ rc, const TM* __restrict__ Dic, double omega,
+                           TV* __restrict__ xc, const int* skip) {
   if (skip && *skip) return;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nc;
        j += (int64_t)gridDim.x * blockDim.x) {
@@ -51,8 +54,22 @@ __global__ void k_restrict(const TV* __restrict__ rf, const uint8_t* __restrict_
         if (!dirichlet_row(b, block, f)) acc[f] += w * (double)rf[i * NF + f];
     }
     const uint8_t b = bf_c[j];
+    TV v[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) rc[j * NF + f] = dirichlet_row(b, block, f) ? (TV)0 : (TV)acc[f];
+    for (int f = 0; f < NF; ++f) {
+      v[f] = dirichlet_row(b, block, f) ? (TV)0 : (TV)acc[f];
+      rc[j * NF + f] = v[f];
+    }
+    if (xc) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        TM sum = 0;
+#pragma unroll
+        for (int c = 0; c < NF; ++c) sum += Dic[j * NF * NF + f * NF + c] * (TM)v[c];
+        const TM om = dirichlet_row(b, block, f) ? (TM)1 : (TM)omega;
+        xc[j * NF + f] = (TV)(om * sum);
+      }
+    }
   }
 }
 

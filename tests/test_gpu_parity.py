@@ -44,6 +44,9 @@ def mesh_pair(chns, orc, kind):
     if kind == "adaptive":
         lv = W.random_leaves((1, 1, 1), 4, 7, p_split=0.3, level_min=2)
         return chns.Mesh((1, 1, 1), 0, 4, leaves=lv), orc.Mesh((1, 1, 1), 0, 4, leaves=lv)
+    if kind == "dense":  # densely refined: chunks with more than 512 incidences
+        lv = W.random_leaves((1, 1, 1), 5, 0, p_split=0.6, level_min=1)
+        return chns.Mesh((1, 1, 1), 0, 5, leaves=lv), orc.Mesh((1, 1, 1), 0, 5, leaves=lv)
     if kind == "brick":
         lv = W.random_leaves((1, 1, 3), 3, 9, p_split=0.35, level_min=1)
         return chns.Mesh((1, 1, 3), 0, 3, leaves=lv), orc.Mesh((1, 1, 3), 0, 3, leaves=lv)
@@ -140,7 +143,7 @@ def test_coupled_jacobian_rows(torch, chns, orc, kind):
         assert np.linalg.norm(ref - blockwise) > 1e-6 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("kind", KINDS + ["dense"])
 def test_cached_linearisation_jvp(torch, chns, orc, kind):
     """chns_jvp_lin after chns_linearize matches the oracle to 1e-12 and
     chns_jvp to rounding (the two kernels may contract multiply-adds across
@@ -179,7 +182,7 @@ def test_cached_linearisation_jvp(torch, chns, orc, kind):
         pm.linearize(p, 7, d1, d0)
 
 
-@pytest.mark.parametrize("kind", ["single", "adaptive", "brick", "drop16"])
+@pytest.mark.parametrize("kind", ["single", "adaptive", "brick", "drop16", "dense"])
 @pytest.mark.parametrize("block", [CH, NS])
 def test_diag_blocks_parity(torch, chns, orc, kind, block):
     pm, om = mesh_pair(chns, orc, kind)
