@@ -907,8 +907,13 @@ struct Solver {
       if ((rc = apply<TV>(block, Zk, wv, U1, U0, idle))) return rc;
       hipLaunchKernelGGL(dev::k_multidot<TV>, gp, b, 0, s, V, N, k + 1, wv, N, w.part, idle);
       hipLaunchKernelGGL(dev::k_finish_sum, dim3(k + 1), b, 0, s, w.part, w.nb_part, k + 1, C->h1, idle);
-      hipLaunchKernelGGL(dev::k_multi_axpy<TV>, gs, b, 0, s, wv, V, N, k + 1, C->h1, N, idle);
-      hipLaunchKernelGGL(dev::k_multidot<TV>, gp, b, 0, s, V, N, k + 1, wv, N, w.part, idle);
+      if (k + 1 <= dev::kDotTile) {  // one sweep: w -= V h1 and the second pass's V^T w
+        hipLaunchKernelGGL(dev::k_axpy_multidot<TV>, dim3(w.nb_part), b, 0, s, wv, V, N, k + 1, C->h1, N, w.part,
+                           idle);
+      } else {
+        hipLaunchKernelGGL(dev::k_multi_axpy<TV>, gs, b, 0, s, wv, V, N, k + 1, C->h1, N, idle);
+        hipLaunchKernelGGL(dev::k_multidot<TV>, gp, b, 0, s, V, N, k + 1, wv, N, w.part, idle);
+      }
       hipLaunchKernelGGL(dev::k_finish_sum, dim3(k + 1), b, 0, s, w.part, w.nb_part, k + 1, C->h2, idle);
       hipLaunchKernelGGL(dev::k_axpy_norm<TV>, dim3(w.nb_part), b, 0, s, wv, V, N, k + 1, C->h2, N, w.part,
                          idle);

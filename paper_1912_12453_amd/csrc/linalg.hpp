@@ -104,6 +104,45 @@ __global__ __launch_bounds__(256) void k_multidot(const TV* __restrict__ V, int6
   }
 }
 
+// w -= sum_{j<k} c_j V_j, then part[j * gridDim.x + b] = partial sum over
+// block b of V_j . w (the updated w), for k <= kDotTile: the multi-axpy of
+// one Gram-Schmidt pass and the multi-dot of the next in one sweep over the
+// basis.  Row assignment, rounding of w and summation order are those of
+// k_multi_axpy followed by k_multidot, so the results are the same.
+template <class TV>
+__global__ __launch_bounds__(256) void k_axpy_multidot(TV* __restrict__ w, const TV* __restrict__ V,
+                                                       int64_t stride, int k, const double* __restrict__ c,
+                                                       int64_t n, double* __restrict__ part, const int* skip) {
+  if (skipped(skip)) return;
+  __shared__ double sh[4];
+  __shared__ double cc[kDotTile];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) cc[j] = c[j];
+  __syncthreads();
+  double acc[kDotTile];
+#pragma unroll
+  for (int j = 0; j < kDotTile; ++j) acc[j] = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = (double)w[i];
+#pragma unroll 8
+    for (int j = 0; j < k; ++j) s -= cc[j] * (double)V[j * stride + i];
+    const TV st = (TV)s;
+    w[i] = st;
+    const double wi = (double)st;
+    // the second read of the row's basis entries comes from cache
+#pragma unroll
+    for (int j = 0; j < kDotTile; ++j)
+      if (j < k) acc[j] += (double)V[j * stride + i] * wi;
+  }
+#pragma unroll
+  for (int j = 0; j < kDotTile; ++j) {
+    if (j < k) {
+      const double t = block_reduce_sum(acc[j], sh);
+      if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = t;
+    }
+  }
+}
+
 // out[j] = sum_b part[j * nb + b] in block order
 __global__ void k_finish_sum(const double* __restrict__ part, int nb, int k, double* __restrict__ out,
                              const int* skip) {
