@@ -142,8 +142,10 @@ void free_workspace(Workspace& w) {
 struct MGLevel {
   chns_mesh* mesh = nullptr;  // owned for levels >= 1
   int64_t n = 0;
-  int32_t *p_off = nullptr, *p_idx = nullptr, *r_off = nullptr, *r_idx = nullptr, *inj = nullptr;
-  double *p_w = nullptr, *r_w = nullptr;
+  int32_t *p_off = nullptr, *p_idx = nullptr, *r_off = nullptr, *inj = nullptr;
+  double* p_w = nullptr;
+  int32_t* r_eidx = nullptr;  // restriction lists, padded column-major (k_restrict)
+  float* r_ew = nullptr;
   double *U1 = nullptr, *U0 = nullptr, *D = nullptr, *Di = nullptr, *DiC = nullptr;  // levels >= 1
   float *U1f = nullptr, *U0f = nullptr, *Di32 = nullptr, *DiC32 = nullptr;
   double *b64 = nullptr, *x64 = nullptr, *r64 = nullptr;
@@ -576,18 +578,31 @@ int mg_alloc_level(MGLevel& L, bool coarse) {
 }
 
 int mg_upload_transfer(MGLevel& F, const Transfer& t, hipStream_t s) {
+  // the restriction lists padded column-major, weights in FP32 (dyadic, exact)
+  const int64_t nc = (int64_t)t.r_off.size() - 1;
+  int64_t K = 0;
+  for (int64_t j = 0; j < nc; ++j) K = std::max<int64_t>(K, t.r_off[j + 1] - t.r_off[j]);
+  std::vector<int32_t> eidx((size_t)std::max<int64_t>(K * nc, 1), 0);
+  std::vector<float> ew(eidx.size(), 0.0f);
+  for (int64_t j = 0; j < nc; ++j)
+    for (int64_t k = 0; k < t.r_off[j + 1] - t.r_off[j]; ++k) {
+      const double w = t.r_w[t.r_off[j] + k];
+      if ((double)(float)w != w) return fail(CHNS_EINVAL, "a restriction weight is not exact in FP32");
+      eidx[k * nc + j] = t.r_idx[t.r_off[j] + k];
+      ew[k * nc + j] = (float)w;
+    }
   {
     std::lock_guard<std::mutex> lk(g_struct_mu);
     int rc;
     if ((rc = dalloc(&F.p_off, t.p_off.size(), nullptr)) || (rc = dalloc(&F.p_idx, t.p_idx.size(), nullptr)) ||
         (rc = dalloc(&F.p_w, t.p_w.size(), nullptr)) || (rc = dalloc(&F.r_off, t.r_off.size(), nullptr)) ||
-        (rc = dalloc(&F.r_idx, t.r_idx.size(), nullptr)) || (rc = dalloc(&F.r_w, t.r_w.size(), nullptr)) ||
+        (rc = dalloc(&F.r_eidx, eidx.size(), nullptr)) || (rc = dalloc(&F.r_ew, ew.size(), nullptr)) ||
         (rc = dalloc(&F.inj, t.inj.size(), nullptr)))
       return rc;
   }
   int rc;
   if ((rc = h2d(F.p_off, t.p_off, s)) || (rc = h2d(F.p_idx, t.p_idx, s)) || (rc = h2d(F.p_w, t.p_w, s)) ||
-      (rc = h2d(F.r_off, t.r_off, s)) || (rc = h2d(F.r_idx, t.r_idx, s)) || (rc = h2d(F.r_w, t.r_w, s)) ||
+      (rc = h2d(F.r_off, t.r_off, s)) || (rc = h2d(F.r_eidx, eidx, s)) || (rc = h2d(F.r_ew, ew, s)) ||
       (rc = h2d(F.inj, t.inj, s)))
     return rc;
   HIPCHK(hipStreamSynchronize(s));  // t is released by the caller
@@ -843,8 +858,8 @@ struct Solver {
     TV* bc = dbl ? (TV*)C.b64 : (TV*)C.b32;
     TV* xc = dbl ? (TV*)C.x64 : (TV*)C.x32;
     const TM* Dic = dbl ? (const TM*)(ch ? C.DiC : C.Di) : (const TM*)(ch ? C.DiC32 : C.Di32);
-    hipLaunchKernelGGL((dev::k_restrict<NF, TV, TM>), dim3(grid_stride(C.n)), bl, 0, s, r, mm->d_bflags, L.r_off,
-                       L.r_idx, L.r_w, C.n, C.mesh->d_bflags, block, bc, Dic, o.mg_omega, xc, skip);
+    hipLaunchKernelGGL((dev::k_restrict<NF, TV, TM>), dim3(grid_stride(C.n)), bl, 0, s, r, L.r_off, L.r_eidx,
+                       L.r_ew, C.n, C.mesh->d_bflags, block, bc, Dic, o.mg_omega, xc, skip);
     if ((rc = vcycle<TV, NF>(block, l + 1, bc, xc, skip, U1, U0, true))) return rc;
     hipLaunchKernelGGL((dev::k_prolong_add<NF, TV>), g, bl, 0, s, x, mm->d_bflags, L.p_off, L.p_idx, L.p_w, nl,
                        xc, block, skip);
@@ -1522,7 +1537,7 @@ namespace {
 void free_mg_locked(chns_mesh* m) {
   for (size_t l = 0; l < m->mg.size(); ++l) {
     MGLevel& L = m->mg[l];
-    void* ptrs[] = {L.p_off, L.p_idx, L.r_off, L.r_idx, L.inj, L.p_w, L.r_w, L.U1, L.U0, L.D, L.Di,
+    void* ptrs[] = {L.p_off, L.p_idx, L.r_off, L.r_eidx, L.inj, L.p_w, L.r_ew, L.U1, L.U0, L.D, L.Di,
                     L.DiC, L.U1f, L.U0f, L.Di32, L.DiC32, L.b64, L.x64, L.r64, L.b32, L.x32, L.r32};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);

@@ -29,29 +29,30 @@ __global__ void k_inject6(const double* __restrict__ Uf, const int32_t* __restri
   }
 }
 
-// rc[j] = sum over the fine nodes i of node j's list of w * rf[i], Dirichlet
-// rows (fine and coarse) excluded.  With xc set, the coarse level's first
+// rc[j] = sum over the fine nodes i of node j's list of w * rf[i], coarse
+// Dirichlet rows zero (the fine Dirichlet rows of rf are zero, as the residual
+// gather writes them).  The lists are padded column-major (entry k of node j
+// at k * nc + j) so that the lanes of a wave read consecutive entries; the
+// dyadic weights are exact in FP32.  With xc set, the coarse level's first
 // Jacobi step xc = omega Dic rc follows in the same kernel (as k_jacobi
 // without Ax, same arithmetic).
 template <int NF, class TV, class TM>
-__global__ void k_restrict(const TV* __restrict__ rf, const uint8_t* __restrict__ bf_f,
-                           const int32_t* __restrict__ r_off, const int32_t* __restrict__ r_idx,
-                           const double* __restrict__ r_w, int64_t nc, const uint8_t* __restrict__ bf_c,
-                           int block, TV* __restrict__ rc, const TM* __restrict__ Dic, double omega,
-                           TV* __restrict__ xc, const int* skip) {
+__global__ void k_restrict(const TV* __restrict__ rf, const int32_t* __restrict__ r_off,
+                           const int32_t* __restrict__ r_eidx, const float* __restrict__ r_ew, int64_t nc,
+                           const uint8_t* __restrict__ bf_c, int block, TV* __restrict__ rc,
+                           const TM* __restrict__ Dic, double omega, TV* __restrict__ xc, const int* skip) {
   if (skip && *skip) return;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nc;
        j += (int64_t)gridDim.x * blockDim.x) {
     double acc[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[f] = 0;
-    for (int k = r_off[j]; k < r_off[j + 1]; ++k) {
-      const int64_t i = r_idx[k];
-      const double w = r_w[k];
-      const uint8_t b = bf_f[i];
+    const int cnt = r_off[j + 1] - r_off[j];
+    for (int k = 0; k < cnt; ++k) {
+      const int64_t i = r_eidx[(int64_t)k * nc + j];
+      const double w = (double)r_ew[(int64_t)k * nc + j];
 #pragma unroll
-      for (int f = 0; f < NF; ++f)
-        if (!dirichlet_row(b, block, f)) acc[f] += w * (double)rf[i * NF + f];
+      for (int f = 0; f < NF; ++f) acc[f] += w * (double)rf[i * NF + f];
     }
     const uint8_t b = bf_c[j];
     TV v[NF];
@@ -130,7 +131,7 @@ __global__ void k_jacobi(const TM* __restrict__ Di, const TV* __restrict__ b, co
 // cycle does next with v:
 //   EPI 1  damped node-block Jacobi x += omega Di (b - v), omega = 1 on the
 //          Dirichlet rows (as k_jacobi, same arithmetic);
-//   EPI 2  the residual r = b - v (as k_rsub).
+//   EPI 2  the residual r = b - v (as k_rsub), zero on the Dirichlet rows.
 template <int NF, class TV, class TM, int EPI>
 __global__ void k_gather_vcycle(PlanView pl, int64_t n, const TV* __restrict__ partial, int block,
                                 TV* __restrict__ x, const TV* __restrict__ b, const TM* __restrict__ Di,
@@ -168,9 +169,9 @@ __global__ void k_gather_vcycle(PlanView pl, int64_t n, const TV* __restrict__ p
       }
 #pragma unroll
       for (int f = 0; f < NF; ++f) x[i * NF + f] = xn[f];
-    } else {
+    } else {  // Dirichlet rows take no coarse correction: their residual is zero
 #pragma unroll
-      for (int f = 0; f < NF; ++f) r[i * NF + f] = b[i * NF + f] - acc[f];
+      for (int f = 0; f < NF; ++f) r[i * NF + f] = dirichlet_row(bb, block, f) ? (TV)0 : b[i * NF + f] - acc[f];
     }
   }
 }
