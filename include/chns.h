@@ -225,7 +225,7 @@ typedef struct {
    * Jacobi (mg_smooth sweeps before and after the coarse correction,
    * mg_coarse_sweeps on the coarsest mesh).  The V-cycle is a fixed linear
    * operator, as right preconditioning in GMRES requires. */
-  double mg_omega;          /* damping of the Jacobi sweeps, 0.6            */
+  double mg_omega;          /* damping of the Jacobi sweeps, 0.5            */
   int32_t mg_levels;        /* 0: automatic                                 */
   int32_t mg_smooth;        /* 2                                            */
   int32_t mg_coarse_sweeps; /* 8                                            */

@@ -170,7 +170,7 @@ def make_params(physics):
 
 def make_opts(newton_rtol=1e-8, newton_atol=1e-12, block_tol=1e-4, gmres_rtol=1e-7,
               newton_max_it_ch=20, newton_max_it_ns=40, gmres_restart=120, gmres_max_it=1000,
-              block_max_it=10, block_min_it=1, precision=0, precond=1, graphs=1, mg_omega=0.6,
+              block_max_it=10, block_min_it=1, precision=0, precond=1, graphs=1, mg_omega=0.5,
               mg_levels=0, mg_smooth=2, mg_coarse_sweeps=8, coupled=0):
     return chns_solver_opts(newton_rtol, newton_atol, block_tol, gmres_rtol, newton_max_it_ch,
                             newton_max_it_ns, gmres_restart, gmres_max_it, block_max_it,
