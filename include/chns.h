@@ -102,7 +102,9 @@ typedef struct {
   int64_t n_constraint;   /* entries of the flattened hanging constraints  */
   int32_t level_max;      /* integer unit = 2^-level_max                   */
   int32_t max_fanin;      /* largest number of parents of a hanging node   */
-  int64_t device_bytes;   /* HBM held by the mesh once uploaded            */
+  int64_t device_bytes;   /* HBM held by the mesh now: its arrays, solver
+                           * workspace, cached linearisations and any
+                           * multigrid hierarchy built for it            */
 } chns_mesh_stats;
 
 /* Builds the balanced octree, numbers its nodes and flattens the hanging

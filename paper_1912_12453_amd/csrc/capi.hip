@@ -184,6 +184,7 @@ struct chns_mesh {
   void* d_lin[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // cached linearisation points [block][FP64, FP32]
   std::vector<MGLevel> mg;  // multigrid hierarchy, built on first use
   int mg_key = -1;          // mg_levels it was built for
+  int64_t mg_bytes = 0;     // level buffers and transfers of the hierarchy (coarse meshes count their own)
 };
 
 namespace {
@@ -560,24 +561,25 @@ int launch_diagnostics(chns_mesh* m, const dev::PhysView& pv, const double* U, d
 // ------------------------------------------------------ multigrid setup ----
 constexpr int64_t kMGCoarsest = 4096;  // automatic depth stops at this many nodes
 
-int mg_alloc_level(MGLevel& L, bool coarse) {
+int mg_alloc_level(MGLevel& L, bool coarse, int64_t* bytes) {
   std::lock_guard<std::mutex> lk(g_struct_mu);
   const size_t n = (size_t)L.n;
+  int64_t* B = bytes;
   int rc;
-  if ((rc = dalloc(&L.r64, 4 * n, nullptr)) || (rc = dalloc(&L.r32, 4 * n, nullptr))) return rc;
+  if ((rc = dalloc(&L.r64, 4 * n, B)) || (rc = dalloc(&L.r32, 4 * n, B))) return rc;
   if (!coarse) return CHNS_OK;
-  if ((rc = dalloc(&L.U1, 6 * n, nullptr)) || (rc = dalloc(&L.U0, 6 * n, nullptr)) ||
-      (rc = dalloc(&L.U1f, 6 * n, nullptr)) || (rc = dalloc(&L.U0f, 6 * n, nullptr)) ||
-      (rc = dalloc(&L.D, 16 * n, nullptr)) || (rc = dalloc(&L.Di, 16 * n, nullptr)) ||
-      (rc = dalloc(&L.Di32, 16 * n, nullptr)) || (rc = dalloc(&L.DiC, 4 * n, nullptr)) ||
-      (rc = dalloc(&L.DiC32, 4 * n, nullptr)) || (rc = dalloc(&L.b64, 4 * n, nullptr)) ||
-      (rc = dalloc(&L.x64, 4 * n, nullptr)) || (rc = dalloc(&L.b32, 4 * n, nullptr)) ||
-      (rc = dalloc(&L.x32, 4 * n, nullptr)))
+  if ((rc = dalloc(&L.U1, 6 * n, B)) || (rc = dalloc(&L.U0, 6 * n, B)) ||
+      (rc = dalloc(&L.U1f, 6 * n, B)) || (rc = dalloc(&L.U0f, 6 * n, B)) ||
+      (rc = dalloc(&L.D, 16 * n, B)) || (rc = dalloc(&L.Di, 16 * n, B)) ||
+      (rc = dalloc(&L.Di32, 16 * n, B)) || (rc = dalloc(&L.DiC, 4 * n, B)) ||
+      (rc = dalloc(&L.DiC32, 4 * n, B)) || (rc = dalloc(&L.b64, 4 * n, B)) ||
+      (rc = dalloc(&L.x64, 4 * n, B)) || (rc = dalloc(&L.b32, 4 * n, B)) ||
+      (rc = dalloc(&L.x32, 4 * n, B)))
     return rc;
   return CHNS_OK;
 }
 
-int mg_upload_transfer(MGLevel& F, const Transfer& t, hipStream_t s) {
+int mg_upload_transfer(MGLevel& F, const Transfer& t, hipStream_t s, int64_t* bytes) {
   // the restriction lists padded column-major, weights in FP32 (dyadic, exact)
   const int64_t nc = (int64_t)t.r_off.size() - 1;
   int64_t K = 0;
@@ -594,10 +596,10 @@ int mg_upload_transfer(MGLevel& F, const Transfer& t, hipStream_t s) {
   {
     std::lock_guard<std::mutex> lk(g_struct_mu);
     int rc;
-    if ((rc = dalloc(&F.p_off, t.p_off.size(), nullptr)) || (rc = dalloc(&F.p_idx, t.p_idx.size(), nullptr)) ||
-        (rc = dalloc(&F.p_w, t.p_w.size(), nullptr)) || (rc = dalloc(&F.r_off, t.r_off.size(), nullptr)) ||
-        (rc = dalloc(&F.r_eidx, eidx.size(), nullptr)) || (rc = dalloc(&F.r_ew, ew.size(), nullptr)) ||
-        (rc = dalloc(&F.inj, t.inj.size(), nullptr)))
+    if ((rc = dalloc(&F.p_off, t.p_off.size(), bytes)) || (rc = dalloc(&F.p_idx, t.p_idx.size(), bytes)) ||
+        (rc = dalloc(&F.p_w, t.p_w.size(), bytes)) || (rc = dalloc(&F.r_off, t.r_off.size(), bytes)) ||
+        (rc = dalloc(&F.r_eidx, eidx.size(), bytes)) || (rc = dalloc(&F.r_ew, ew.size(), bytes)) ||
+        (rc = dalloc(&F.inj, t.inj.size(), bytes)))
       return rc;
   }
   int rc;
@@ -626,7 +628,7 @@ int build_mg(chns_mesh* m, int levels, hipStream_t s) {
   m->mg.resize(1);
   m->mg[0].mesh = m;
   m->mg[0].n = (int64_t)m->h.node_key.size();
-  int rc = mg_alloc_level(m->mg[0], false);
+  int rc = mg_alloc_level(m->mg[0], false, &m->mg_bytes);
   if (rc) return bail(rc);
   const int maxl = levels > 0 ? levels : 64;
   while ((int)m->mg.size() < maxl) {
@@ -659,7 +661,8 @@ int build_mg(chns_mesh* m, int levels, hipStream_t s) {
     C.mesh = c;
     C.n = (int64_t)c->h.node_key.size();
     m->mg.push_back(C);
-    if ((rc = mg_alloc_level(m->mg.back(), true)) || (rc = mg_upload_transfer(m->mg[f], t, s)))
+    if ((rc = mg_alloc_level(m->mg.back(), true, &m->mg_bytes)) ||
+        (rc = mg_upload_transfer(m->mg[f], t, s, &m->mg_bytes)))
       return bail(rc);
   }
   m->mg_key = levels;
@@ -1311,7 +1314,10 @@ int chns_mesh_info(const chns_mesh* m, chns_mesh_stats* out) {
   out->n_constraint = (int64_t)m->h.hang_ids.size();
   out->level_max = m->h.D;
   out->max_fanin = m->h.max_fanin;
-  out->device_bytes = m->device_bytes + m->ws.bytes;
+  int64_t b = m->device_bytes + m->ws.bytes + m->mg_bytes;
+  for (size_t l = 1; l < m->mg.size(); ++l)
+    if (m->mg[l].mesh) b += m->mg[l].mesh->device_bytes + m->mg[l].mesh->ws.bytes;
+  out->device_bytes = b;
   return CHNS_OK;
 }
 
@@ -1545,6 +1551,7 @@ void free_mg_locked(chns_mesh* m) {
   }
   m->mg.clear();
   m->mg_key = -1;
+  m->mg_bytes = 0;
 }
 
 void free_mesh_locked(chns_mesh* m) {

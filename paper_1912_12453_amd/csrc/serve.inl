@@ -38,8 +38,10 @@ int64_t mesh_footprint(const chns_mesh* m) {
 }
 
 // Device bytes of the cached linearisation points of a mesh, both blocks
-// (ensure_lin), at the precision of the inner solve.
+// (ensure_lin), at the precision of the inner solve.  The coupled solve
+// builds them only for its multigrid preconditioner.
 int64_t lin_footprint(const chns_mesh* m, const chns_solver_opts& o) {
+  if (o.coupled && o.precond != 2) return 0;
   const int64_t chunks = std::max<int64_t>((int64_t)m->plan.tgt_off.size() - 1, 1);
   return chunks * (dev::kNSLin + dev::kCHLin) * dev::kChunkThreads * (o.precision == 0 ? 8 : 4);
 }

@@ -146,3 +146,41 @@ def test_oversized_request_fails_alone(torch, chns):
     assert "budget" in chns.lib().chns_last_error().decode()
     assert srv.poll(ts)[0].state == chns.CHNS_REQ_DONE
     srv.close()
+
+
+@pytest.mark.parametrize("precision,precond,coupled", [(1, 1, 0), (0, 2, 0), (1, 2, 1), (0, 1, 1)])
+def test_footprint_bounds_device_bytes(torch, chns, precision, precond, coupled):
+    """The footprint reserved at admission is at least what the request's mesh
+    holds on the device after a step under the same options: mesh arrays,
+    solver workspace, cached linearisations and the multigrid hierarchy.
+    Without multigrid it is exactly that."""
+    print(f"case serving footprint precision={precision} precond={precond} coupled={coupled}", flush=True)
+    import time
+    o = chns.make_opts(precision=precision, gmres_rtol=1e-5, gmres_restart=60, precond=precond,
+                       coupled=coupled)
+    reqs = REQS + [request(7, [((0.5, 0.5, 0.5), 0.25)], True, 10.0, 5.0, steps=1)]
+    probe = chns.Server(1 << 36, 4, o)
+    tks = [probe.submit(r.mesh, r.physics, 1) for r in reqs]
+    for _ in range(3000):
+        if all(probe.poll(t)[0].state >= chns.CHNS_REQ_READY for t in tks):
+            break
+        time.sleep(0.01)
+    fps = [probe.poll(t)[0].footprint_bytes for t in tks]
+    probe.close()
+    for r, fp in zip(reqs, fps):
+        m = chns.Mesh.from_spec(r.mesh)
+        xyz, _ = m.nodes()
+        phi = r.mesh.phi0(xyz)
+        U = np.zeros((m.n_nodes, 6))
+        U[:, 0] = phi
+        U[:, 1] = phi * phi * phi - phi
+        d = torch.tensor(U, device="cuda:0")
+        rc, _ = m.step(chns.make_params(r.physics), o, d)
+        torch.cuda.synchronize()
+        assert rc in (chns.CHNS_OK, chns.CHNS_NOT_CONVERGED)
+        held = chns.chns_mesh_info(m.h).device_bytes
+        print(f"  {r.name}: nodes {m.n_nodes} held {held} footprint {fp} ratio {fp / held:.2f}", flush=True)
+        assert 0 < held <= fp
+        if precond != 2:  # no coarse levels to estimate: the reservation is exact
+            assert held == fp
+        m.close()
