@@ -184,7 +184,7 @@ def main():
     ap.add_argument("--workload", default="bubble_l9")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-reps", type=int, default=2)
+    ap.add_argument("--cpu-reps", type=int, default=10)
     ap.add_argument("--cn-steps", type=int, default=10)
     ap.add_argument("--cn-steps-large", type=int, default=5)
     ap.add_argument("--cn-restart", type=int, default=120)
@@ -366,10 +366,21 @@ def main():
             om.jvp(op_, 0, U1h, U0h, dUh)
             om.jvp(op_, 1, U1h, U0h, dUh)
         tc = time.perf_counter() - t0
-        cpu = {"value": round(6 * n * reps / tc / 1e9, 6), "unit": "GDoF/s", "cores": oracle.num_threads(),
+        cores = oracle.num_threads()
+        cpu = {"value": round(6 * n * reps / tc / 1e9, 6), "unit": "GDoF/s", "cores": cores,
                "kind": "oracle",
                "sample": f"{reps} x (CH + NS JVP) over the full {name} mesh ({E} leaves), {tc:.1f}s"}
         log(f"[bench] cpu baseline {cpu}")
+        # the same pass on one thread
+        oracle.set_num_threads(1)
+        t0 = time.perf_counter()
+        om.jvp(op_, 0, U1h, U0h, dUh)
+        om.jvp(op_, 1, U1h, U0h, dUh)
+        t1 = time.perf_counter() - t0
+        oracle.set_num_threads(cores)
+        cpu["value_1thread"] = round(6 * n / t1 / 1e9, 6)
+        cpu["sample_1thread"] = f"1 x (CH + NS JVP) over the same mesh on one thread, {t1:.1f}s"
+        log(f"[bench] cpu baseline, one thread: {cpu['value_1thread']} GDoF/s")
 
     res = {
         "metric": "CHNS JVP GDoF/s (in-solver, FP64 Newton-GMRES pass)",

@@ -88,12 +88,19 @@ def lib():
         L.orc_step.argtypes = [C.c_void_p, C.POINTER(Params), C.POINTER(SolverOpts), dp, dp,
                                C.POINTER(StepStats)]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def _err():

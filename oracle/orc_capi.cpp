@@ -116,4 +116,15 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+// Threads of the following parallel loops (timing only; results do not depend
+// on it, every reduction runs in a fixed order).
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
 }

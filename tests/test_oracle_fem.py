@@ -468,3 +468,23 @@ def test_full_jvp_matches_central_differences(orc, adaptive, block, meshkind):
     assert np.array_equal(m.jvp_full(p, block, U1, U0, dB), m.jvp(p, block, U1, U0, dB))
     cross = Jd[:, f] - m.jvp(p, block, U1, U0, dB)[:, f]
     assert np.linalg.norm(cross) > 1e-3 * np.linalg.norm(Jd[:, f])
+
+
+@pytest.mark.parametrize("block", [CH, NS])
+def test_thread_count_does_not_change_results(orc, adaptive, block):
+    """Element vectors are added in element order after the parallel loop, so
+    the residual, the JVP and the diagonal blocks are bitwise the same on one
+    thread and on all of them (the CPU baseline times both)."""
+    m = adaptive
+    p = P(orc)
+    U1, U0 = random_state(m, 10)
+    d = np.random.default_rng(11).normal(size=U1.shape)
+    cores = orc.num_threads()
+    try:
+        orc.set_num_threads(1)
+        one = (m.residual(p, block, U1, U0), m.jvp(p, block, U1, U0, d), m.diag_blocks(p, block, U1, U0))
+    finally:
+        orc.set_num_threads(cores)
+    many = (m.residual(p, block, U1, U0), m.jvp(p, block, U1, U0, d), m.diag_blocks(p, block, U1, U0))
+    for a, b in zip(one, many):
+        assert np.array_equal(a, b)
