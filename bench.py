@@ -41,15 +41,16 @@ sys.path.insert(0, ROOT)
 
 # Work per element of the NS JVP kernel the solver runs, k_ns_jvp_lin (the
 # JVP from the cached linearisation points): floating-point operations
-# executed per element (8 lanes x the static count of one lane's arithmetic in
-# the kernel's gfx950 code: fma and div_fmas = 2, add, mul, rcp and sqrt = 1;
-# the hanging-corner sums are counted once) and compulsory HBM bytes (per
+# executed per element (the SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 or _F32
+# counters of one launch on the level-9 bubble: 64 x (2 FMA + ADD + MUL +
+# TRANS) / leaves) and compulsory HBM bytes (per
 # element: the NS_LIN cached values at each of the 8 Gauss points, the 8 corner
-# ids and the level byte; per node: the 4-value direction and the 4-value
-# result).
-NS_LIN = 22
-NS_JVP_FLOPS_PER_ELEMENT = {"fp64": 4880, "mixed": 4808}
-NS_JVP_BYTES_PER_NODE = {"fp64": (4 + 4) * 8, "mixed": (4 + 4) * 4}
+# ids and the level byte; per node: the 4-value direction, the 4 cached nodal
+# midpoints and the 4-value result).
+NS_LIN = 7
+NS_MID = 4
+NS_JVP_FLOPS_PER_ELEMENT = {"fp64": 5728, "mixed": 5656}
+NS_JVP_BYTES_PER_NODE = {"fp64": (4 + NS_MID + 4) * 8, "mixed": (4 + NS_MID + 4) * 4}
 NS_JVP_BYTES_PER_ELEMENT = {"fp64": NS_LIN * 8 * 8 + 8 * 4 + 1, "mixed": NS_LIN * 8 * 4 + 8 * 4 + 1}
 
 PEAK_HBM_GBS = 8000.0
@@ -319,12 +320,13 @@ def main():
     ach_gbs = bytes_per_launch / (ns_ms * 1e-3) / 1e9
     tflops = flops_per_launch / (ns_ms * 1e-3) / 1e12
     kname = "k_ns_jvp_lin<double,double>" if precision == 0 else "k_ns_jvp_lin<float,float>"
-    traffic = None
+    traffic = valu_busy = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
         ent = tr.get("kernels", {}).get(kname, {}).get(name)
         if ent and ent.get("leaves") == E:
             traffic = ent["hbm_bytes_per_launch"]
+            valu_busy = ent.get("valu_busy")
     # the roof the kernel is closer to: HBM (algorithmic bytes) or VALU (flops)
     alu_frac, hbm_frac = tflops / PEAK_TFLOPS[prec], ach_gbs / PEAK_HBM_GBS
     if hbm_frac >= alu_frac:
@@ -337,6 +339,8 @@ def main():
                  "flops_per_launch": flops_per_launch, "algorithmic_bytes_per_launch": bytes_per_launch,
                  "achieved_TFLOPs": round(tflops, 3), "alu_frac": round(alu_frac, 4),
                  "algorithmic_GBps": round(ach_gbs, 1), "hbm_frac": round(hbm_frac, 4)})
+    if valu_busy is not None:  # rocprofv3's VALUBusy of the same kernel (counter pass), as a fraction
+        roof["valu_busy"] = valu_busy
 
     # ---- full Crank-Nicolson steps at the 1e-8 Newton tolerance, FP64 vs mixed
     n_hanging = int(mesh.stats.n_hanging)

@@ -170,17 +170,20 @@ int chns_jvp_full(chns_mesh* mesh, const chns_params* params, const double* U_ne
 
 /* Cached linearisation points.  Within one Newton iteration the state is
  * fixed, so the quantities of the block's weak form (Def. 1 and 2) that the
- * JVP differentiates around can be evaluated once per Gauss point:
- *   NS: phi^{k+1} pulled back to [-1,1], v~ and its gradient, the mass flux
- *       J, the transport velocity of R_m and R_m, 22 values, from which rho,
- *       eta, R_c, tau_m and tau_c follow in a few operations;
- *   CH: psi''(phi~) = 3 phi~^2 - 1 and v~, 4 values.
+ * JVP differentiates around can be evaluated once:
+ *   NS: per Gauss point phi^{k+1} pulled back to [-1,1], the transport
+ *       velocity of R_m and R_m (7 values), and per node the midpoints
+ *       u~, v~, w~, mu~ (4 values), from which v~, its gradient, the mass
+ *       flux J, rho, eta, R_c, tau_m and tau_c are rebuilt at the point;
+ *   CH: per Gauss point psi''(phi~) = 3 phi~^2 - 1 and v~ (4 values).
  * chns_linearize does that for (U_new, U_old) and keeps the values with the
- * mesh (device memory, 22 or 4 times 8 values per element in the arithmetic
- * of prec, allocated on first use, one cache per block and precision);
+ * mesh (device memory, 7 or 4 times 8 values per element plus 4 per node
+ * for NS, in the arithmetic of prec, allocated on first use, one cache per
+ * block and precision);
  * chns_jvp_lin then applies the chns_jvp of that state, block and prec to dU
  * (same layout; same results up to rounding, since the compiler may contract
- * multiply-adds differently in the two kernels) reading only the direction.
+ * multiply-adds differently in the two kernels, and a hanging corner's
+ * midpoint is interpolated after averaging the two time levels).
  * A cache holds the last chns_linearize, or the last Newton iteration of
  * chns_step, on this mesh. */
 int chns_linearize(chns_mesh* mesh, const chns_params* params, int block, const double* U_new,

@@ -182,6 +182,7 @@ struct chns_mesh {
   int64_t device_bytes = 0;
   Workspace ws;
   void* d_lin[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // cached linearisation points [block][FP64, FP32]
+  void* d_mid[2] = {nullptr, nullptr};  // nodal midpoints of the NS linearisation point [FP64, FP32]
   std::vector<MGLevel> mg;  // multigrid hierarchy, built on first use
   int mg_key = -1;          // mg_levels it was built for
   int64_t mg_bytes = 0;     // level buffers and transfers of the hierarchy (coarse meshes count their own)
@@ -452,12 +453,21 @@ int lin_values(int block) { return block == CHNS_BLOCK_CH ? dev::kCHLin : dev::k
 
 template <class T>
 int ensure_lin(chns_mesh* m, int block) {
-  void*& slot = m->d_lin[block][std::is_same<T, double>::value ? 0 : 1];
+  const int k = std::is_same<T, double>::value ? 0 : 1;
+  void*& slot = m->d_lin[block][k];
   if (slot) return CHNS_OK;
   std::lock_guard<std::mutex> lk(g_struct_mu);
-  T* p = nullptr;
-  const int rc = dalloc(&p, (size_t)m->n_chunks * lin_values(block) * dev::kChunkThreads, &m->device_bytes);
+  T *p = nullptr, *q = nullptr;
+  int rc = dalloc(&p, (size_t)m->n_chunks * lin_values(block) * dev::kChunkThreads, &m->device_bytes);
   if (rc) return rc;
+  if (block == CHNS_BLOCK_NS && !m->d_mid[k]) {
+    if ((rc = dalloc(&q, m->h.node_key.size() * dev::kNSMid, &m->device_bytes))) {
+      (void)hipFree(p);
+      m->device_bytes -= (int64_t)((size_t)m->n_chunks * lin_values(block) * dev::kChunkThreads * sizeof(T));
+      return rc;
+    }
+    m->d_mid[k] = q;
+  }
   slot = p;
   return CHNS_OK;
 }
@@ -472,11 +482,20 @@ int launch_lin(chns_mesh* m, const dev::PhysView& pv, int block, const TS* U1, c
   if (block == CHNS_BLOCK_CH)
     hipLaunchKernelGGL((dev::k_ch_lin<T, TS>), g, b, (dev::ChunkLDS<T, 5, 0, 2>::bytes(cc)), s, view(m),
                        plan_view(m), pv, cc, U1, U0, lin);
-  else
+  else {
     hipLaunchKernelGGL((dev::k_ns_lin<T, TS>), g, b, (dev::ChunkLDS<T, 6, 0, 4>::bytes(cc)), s, view(m),
                        plan_view(m), pv, cc, U1, U0, lin);
+    const int64_t n = (int64_t)m->h.node_key.size();
+    hipLaunchKernelGGL((dev::k_ns_mid<T, TS>), dim3(grid_stride(n * dev::kNSMid)), dim3(256), 0, s, n, U1, U0,
+                       (T*)m->d_mid[std::is_same<T, double>::value ? 0 : 1]);
+  }
   HIPCHK(hipGetLastError());
   return CHNS_OK;
+}
+
+template <class T>
+const T* ns_mid(const chns_mesh* m) {
+  return (const T*)m->d_mid[std::is_same<T, double>::value ? 0 : 1];
 }
 
 // The element pass of a cached JVP alone (partials; the caller gathers).
@@ -492,8 +511,8 @@ int launch_jvp_lin_elements(chns_mesh* m, const dev::PhysView& pv, int block, co
     hipLaunchKernelGGL((dev::k_ch_jvp_lin<T, TD>), g, b, (dev::ChunkLDS<T, 0, 2, 2>::bytes(cc)), s, view(m),
                        plan_view(m), pv, cc, lin, dU, ldD, offD, part, skip);
   else
-    hipLaunchKernelGGL((dev::k_ns_jvp_lin<T, TD>), g, b, (dev::ChunkLDS<T, 0, 4, 4>::bytes(cc)), s, view(m),
-                       plan_view(m), pv, cc, lin, dU, ldD, offD, part, skip);
+    hipLaunchKernelGGL((dev::k_ns_jvp_lin<T, TD>), g, b, (dev::ChunkLDS<T, 0, 4 + dev::kNSMid, 4>::bytes(cc)), s,
+                       view(m), plan_view(m), pv, cc, lin, ns_mid<T>(m), dU, ldD, offD, part, skip);
   HIPCHK(hipGetLastError());
   return CHNS_OK;
 }
@@ -514,8 +533,8 @@ int launch_jvp_lin(chns_mesh* m, const dev::PhysView& pv, int block, const TD* d
     hipLaunchKernelGGL((dev::k_gather<2, T, TD, 0>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part, out,
                        ldO, offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD, skip);
   } else {
-    hipLaunchKernelGGL((dev::k_ns_jvp_lin<T, TD>), g, b, (dev::ChunkLDS<T, 0, 4, 4>::bytes(cc)), s, view(m), pl,
-                       pv, cc, lin, dU, ldD, offD, part, skip);
+    hipLaunchKernelGGL((dev::k_ns_jvp_lin<T, TD>), g, b, (dev::ChunkLDS<T, 0, 4 + dev::kNSMid, 4>::bytes(cc)), s,
+                       view(m), pl, pv, cc, lin, ns_mid<T>(m), dU, ldD, offD, part, skip);
     hipLaunchKernelGGL((dev::k_gather<4, T, TD, 2>), dim3(grid_stride(n)), dim3(256), 0, s, pl, n, part, out,
                        ldO, offO, (const double*)nullptr, (const double*)nullptr, dU, ldD, offD, skip);
   }
@@ -1562,7 +1581,8 @@ void free_mesh_locked(chns_mesh* m) {
                   m->d_tgt_off, m->d_tgt, m->d_inc_off, m->d_chunk_inc, m->d_node_off, m->d_node_slot,
                   m->d_inc_corner,
                   m->d_bflags, m->d_inc_w, m->d_touch_off, m->d_touch_node, m->d_ntouch_off, m->d_ntouch_slot,
-                  m->d_partial, m->d_tbuf, m->d_lin[0][0], m->d_lin[0][1], m->d_lin[1][0], m->d_lin[1][1]};
+                  m->d_partial, m->d_tbuf, m->d_lin[0][0], m->d_lin[0][1], m->d_lin[1][0], m->d_lin[1][1],
+                  m->d_mid[0], m->d_mid[1]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (m->h_flag) (void)hipHostFree(m->h_flag);
@@ -1749,12 +1769,14 @@ int chns_launch_element_loop(chns_mesh* m, const chns_params* params, int block,
                            s, mv, pl, pv, cc, (const float*)m->d_lin[block][1], (const float*)dU, 6, off, p32,
                            (const int*)nullptr);
       else if (k == 0)
-        hipLaunchKernelGGL((dev::k_ns_jvp_lin<double, double>), g, b, (dev::ChunkLDS<double, 0, 4, 4>::bytes(cc)),
-                           s, mv, pl, pv, cc, (const double*)m->d_lin[block][0], (const double*)dU, 6, off, p64,
+        hipLaunchKernelGGL((dev::k_ns_jvp_lin<double, double>), g, b,
+                           (dev::ChunkLDS<double, 0, 4 + dev::kNSMid, 4>::bytes(cc)), s, mv, pl, pv, cc,
+                           (const double*)m->d_lin[block][0], ns_mid<double>(m), (const double*)dU, 6, off, p64,
                            (const int*)nullptr);
       else
-        hipLaunchKernelGGL((dev::k_ns_jvp_lin<float, float>), g, b, (dev::ChunkLDS<float, 0, 4, 4>::bytes(cc)),
-                           s, mv, pl, pv, cc, (const float*)m->d_lin[block][1], (const float*)dU, 6, off, p32,
+        hipLaunchKernelGGL((dev::k_ns_jvp_lin<float, float>), g, b,
+                           (dev::ChunkLDS<float, 0, 4 + dev::kNSMid, 4>::bytes(cc)), s, mv, pl, pv, cc,
+                           (const float*)m->d_lin[block][1], ns_mid<float>(m), (const float*)dU, 6, off, p32,
                            (const int*)nullptr);
     } else if (op == 5) {
       if ((rc = launch_lin<double, double>(m, pv, block, U_new, U_old, s))) return rc;

@@ -535,52 +535,66 @@ __global__ __launch_bounds__(256) void k_ns_jvp(MeshView m, PlanView pl, PhysVie
 // arrays per chunk, coalesced for the 256 lanes of the chunk's workgroup):
 // lin[(chunk * NL + k) * 256 + lane] for the NL values of a block.
 //
-// NS block: 22 values, phi^{k+1} pulled back to [-1,1], v~, its gradient, J,
-// the transport velocity and R_m.  rho, eta, 1/rho, R_c, tau_m and tau_c are
-// recomputed from them by the code the point evaluation runs (ns_material,
-// ns_stab): a division, a square root and two divisions per point instead of
-// 5 more loads.
+// NS block: 7 values per Gauss point, phi^{k+1} pulled back to [-1,1], the
+// transport velocity of R_m and R_m itself, and 4 values per node, the
+// midpoints u~, v~, w~, mu~ (mid[node * 4 + f]).  The JVP stages the nodal
+// midpoints of the chunk's targets next to the direction and rebuilds v~, its
+// gradient and J at the point with the evaluation the element loop runs
+// anyway; that costs four butterflies per lane instead of 15 cached values
+// (960 B per element in FP64).  rho, eta, 1/rho, R_c, tau_m and tau_c are
+// recomputed too (ns_material, ns_stab).  What needs second derivatives (R_m)
+// or the state at both time levels (the transport velocity) stays cached.
 // CH block: 4 values, psi''(phi~) and v~.
-constexpr int kNSLin = 22;
+constexpr int kNSLin = 7;
+constexpr int kNSMid = 4;
 constexpr int kCHLin = 4;
 
 template <class T>
 __device__ __forceinline__ void ns_lin_store(const NSPoint<T>& P, T* __restrict__ q) {
-  int k = 0;
-  q[(k++) * kChunkThreads] = P.ps;
+  q[0] = P.ps;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) q[(k++) * kChunkThreads] = P.vt[i];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) q[(k++) * kChunkThreads] = P.G[i][j];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) q[(k++) * kChunkThreads] = P.J[i];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) q[(k++) * kChunkThreads] = P.adv[i];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) q[(k++) * kChunkThreads] = P.Rm[i];
+  for (int i = 0; i < 3; ++i) {
+    q[(1 + i) * kChunkThreads] = P.adv[i];
+    q[(4 + i) * kChunkThreads] = P.Rm[i];
+  }
 }
 
+// The linearisation point from the cached values q and the lane's corner
+// midpoints cm (u~, v~, w~, mu~).
 template <class T>
-__device__ __forceinline__ void ns_lin_unpack(const PhysView& p, const T (&q)[kNSLin], const Lane<T>& L,
-                                              NSPoint<T>& P) {
-  int k = 0;
-  const T ps = q[k++];
+__device__ __forceinline__ void ns_lin_unpack(const PhysView& p, const T (&q)[kNSLin], const T (&cm)[kNSMid],
+                                              const Lane<T>& L, NSPoint<T>& P) {
 #pragma unroll
-  for (int i = 0; i < 3; ++i) P.vt[i] = q[k++];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) P.G[i][j] = q[k++];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) P.J[i] = q[k++];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) P.adv[i] = q[k++];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) P.Rm[i] = q[k++];
-  ns_material<T>(p, ps, P);
+  for (int i = 0; i < 3; ++i) {
+    P.adv[i] = q[1 + i];
+    P.Rm[i] = q[4 + i];
+    const VG<T> v = eval_vg<T>(cm[i], L);
+    P.vt[i] = v.v;
+    P.G[i][0] = v.dx;
+    P.G[i][1] = v.dy;
+    P.G[i][2] = v.dz;
+  }
+  const VG<T> mut = eval_vg<T>(cm[3], L);
+  const T kap = (T)p.kappa;
+  P.J[0] = kap * mut.dx;
+  P.J[1] = kap * mut.dy;
+  P.J[2] = kap * mut.dz;
+  ns_material<T>(p, q[0], P);
   ns_stab<T>(p, L, P);
+}
+
+// Nodal midpoints of the NS linearisation point: u~, v~, w~, mu~ per node,
+// with the arithmetic of the element loop's staging (both levels converted to
+// T, then averaged).
+template <class T, class TS>
+__global__ __launch_bounds__(256) void k_ns_mid(int64_t n, const TS* __restrict__ U1, const TS* __restrict__ U0,
+                                                T* __restrict__ mid) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n * kNSMid;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = i / kNSMid;
+    const int f = (int)(i - g * kNSMid), src = f < 3 ? 2 + f : 1;
+    mid[i] = (T)0.5 * ((T)U1[g * 6 + src] + (T)U0[g * 6 + src]);
+  }
 }
 
 // Linearisation points of every Gauss point of the mesh (one workgroup per
@@ -633,25 +647,35 @@ __global__ __launch_bounds__(256) void k_ch_lin(MeshView m, PlanView pl, PhysVie
   q[3 * kChunkThreads] = eval_v<T>((T)0.5 * (c[4] + c[9]));
 }
 
-// Prologue of the JVPs from cached linearisation points: stages the ND-field
-// direction of the chunk's targets and its lists, loads the lane's NL cached
-// values and returns the lane's corner direction (after the barrier).
-// Vector memory counters retire in the order the loads were issued, so they
-// are issued in the order they are needed: (1) the chunk's target and
-// incidence lists and the lane's hanging-node record, (2) the cached values,
-// which carry most of the bytes, (3) what depends on (1): the direction
-// records of the targets and the parents of a hanging corner.  The LDS stores
+// Prologue of the JVPs from cached linearisation points: stages, per target
+// of the chunk, the ND-field direction followed by NM cached nodal values
+// (mid[node * NM + f]), and the chunk's lists; loads the lane's NL cached
+// values and returns the lane's corner record, ND + NM values (after the
+// barrier).  Vector memory counters retire in the order the loads were
+// issued, so they are issued in the order they are needed: (1) the chunk's
+// target and incidence lists and the lane's hanging-node record, (2) the
+// cached values, which carry most of the bytes, (3) what depends on (1): the
+// targets' records and the parents of a hanging corner.  The LDS stores
 // of (1) and (3) wait only for their own loads and (2) streams meanwhile.  The
 // fixed per-thread counts cover chunks of up to 128 targets and 512
 // incidences and hanging nodes of up to 4 parents; loops take anything
 // beyond.
-template <class T, class TD, int ND, int NL>
-__device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND, ND>& S, const MeshView& m, const PlanView& pl,
-                                             int ch, int ref, const T* __restrict__ lin,
-                                             const TD* __restrict__ dU, int ldD, int offD, T (&q)[NL],
-                                             T (&c)[ND]) {
-  constexpr int SV = ChunkLDS<T, 0, ND, ND>::SV, KI = 2, KH = 4;
-  constexpr int KD = (128 * ND + kChunkThreads - 1) / kChunkThreads;
+template <class T, class TD, int ND, int NM, int NL>
+__device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND + NM, ND>& S, const MeshView& m,
+                                             const PlanView& pl, int ch, int ref, const T* __restrict__ lin,
+                                             const T* __restrict__ mid, const TD* __restrict__ dU, int ldD,
+                                             int offD, T (&q)[NL], T (&c)[ND + NM]) {
+  constexpr int NV = ND + NM;
+  constexpr int SV = ChunkLDS<T, 0, NV, ND>::SV, KI = 2, KH = 4;
+  constexpr int KD = (128 * NV + kChunkThreads - 1) / kChunkThreads;
+  // value f of target j: the direction (f < ND), then the nodal values
+  auto rec = [&](int64_t g, int f) -> T {
+    if constexpr (NM == 0) {
+      return (T)dU[g * ldD + offD + f];
+    } else {
+      return f < ND ? (T)dU[g * ldD + offD + f] : mid[g * NM + f - ND];
+    }
+  };
   const int t = threadIdx.x;
   const int s0 = pl.tgt_off[ch], cnt = pl.tgt_off[ch + 1] - s0;
   const int i0 = pl.chunk_inc[ch], ni = pl.chunk_inc[ch + 1] - i0;
@@ -663,7 +687,7 @@ __device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND, ND>& S, const Me
   int gd[KD], icv[KI];
   float iwv[KI];
 #pragma unroll
-  for (int k = 0; k < KD; ++k) gd[k] = pl.tgt[s0 + min((t + k * kChunkThreads) / ND, cnt - 1)];
+  for (int k = 0; k < KD; ++k) gd[k] = pl.tgt[s0 + min((t + k * kChunkThreads) / NV, cnt - 1)];
 #pragma unroll
   for (int k = 0; k < KI; ++k) {
     const int i = i0 + min(t + k * kChunkThreads, ni - 1);
@@ -682,9 +706,9 @@ __device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND, ND>& S, const Me
   for (int k = 0; k < NL; ++k) q[k] = ql[k * kChunkThreads];
   __builtin_amdgcn_sched_barrier(0);
   // (3)
-  TD dv[KD];
+  T dv[KD];
 #pragma unroll
-  for (int k = 0; k < KD; ++k) dv[k] = dU[(int64_t)gd[k] * ldD + offD + (t + k * kChunkThreads) % ND];
+  for (int k = 0; k < KD; ++k) dv[k] = rec(gd[k], (t + k * kChunkThreads) % NV);
   int hid[KH];
   T hwt[KH];
   if (ref < 0) {
@@ -707,7 +731,7 @@ __device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND, ND>& S, const Me
 #pragma unroll
   for (int k = 0; k < KD; ++k) {
     const int i = t + k * kChunkThreads;
-    if (i < cnt * ND) S.val[(i / ND) * SV + i % ND] = (T)dv[k];
+    if (i < cnt * NV) S.val[(i / NV) * SV + i % NV] = dv[k];
   }
   // chunks beyond the fixed counts
   for (int i = t + kChunkThreads; i <= cnt; i += kChunkThreads) {
@@ -718,29 +742,29 @@ __device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND, ND>& S, const Me
     S.iw[i] = pl.inc_w[i0 + i];
     S.icor[i] = pl.inc_corner[i0 + i];
   }
-  for (int i = t + KD * kChunkThreads; i < cnt * ND; i += kChunkThreads)
-    S.val[(i / ND) * SV + i % ND] = (T)dU[(int64_t)pl.tgt[s0 + i / ND] * ldD + offD + i % ND];
+  for (int i = t + KD * kChunkThreads; i < cnt * NV; i += kChunkThreads)
+    S.val[(i / NV) * SV + i % NV] = rec(pl.tgt[s0 + i / NV], i % NV);
   __syncthreads();
   // the lane's corner: its node, or its constraint's parents in list order
   if (ref >= 0) {
     const T* v = S.val + S.find(ref) * SV;
 #pragma unroll
-    for (int f = 0; f < ND; ++f) c[f] = v[f];
+    for (int f = 0; f < NV; ++f) c[f] = v[f];
   } else {
 #pragma unroll
-    for (int f = 0; f < ND; ++f) c[f] = (T)0;
+    for (int f = 0; f < NV; ++f) c[f] = (T)0;
 #pragma unroll
     for (int k = 0; k < KH; ++k)
       if (h0 + k < h1) {
         const T* v = S.val + S.find(hid[k]) * SV;
 #pragma unroll
-        for (int f = 0; f < ND; ++f) c[f] += hwt[k] * v[f];
+        for (int f = 0; f < NV; ++f) c[f] += hwt[k] * v[f];
       }
     const auto* w = weights<T>(m);
     for (int j = h0 + KH; j < h1; ++j) {
       const T* v = S.val + S.find(m.hids[j]) * SV;
 #pragma unroll
-      for (int f = 0; f < ND; ++f) c[f] += w[j] * v[f];
+      for (int f = 0; f < NV; ++f) c[f] += w[j] * v[f];
     }
   }
 }
@@ -748,22 +772,23 @@ __device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND, ND>& S, const Me
 // The NS Jacobian-vector product from the cached linearisation points.
 template <class T, class TD>
 __global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, PhysView p, ChunkCaps caps,
-                                                    const T* __restrict__ lin, const TD* __restrict__ dU,
-                                                    int ldD, int offD, T* __restrict__ partial,
-                                                    const int* skip) {
+                                                    const T* __restrict__ lin, const T* __restrict__ mid,
+                                                    const TD* __restrict__ dU, int ldD, int offD,
+                                                    T* __restrict__ partial, const int* skip) {
   if (skip && *skip) return;  // GMRES control: this step is not needed
   extern __shared__ double smem_d[];
-  ChunkLDS<T, 0, 4, 4> S;
+  ChunkLDS<T, 0, 4 + kNSMid, 4> S;
   S.carve((char*)smem_d, caps);
   const int64_t e0 = ((int64_t)blockIdx.x * kChunkThreads + threadIdx.x) >> 3;
   const int64_t e = e0 < m.E ? e0 : m.E - 1;
   Lane<T> L;
   L.init(threadIdx.x & 7, m.level[e]);
   const int ref = m.elem[e * 8 + L.c];
-  T q[kNSLin], c[4];
-  lin_prologue<T, TD, 4, kNSLin>(S, m, pl, blockIdx.x, ref, lin, dU, ldD, offD, q, c);
+  T q[kNSLin], c[4 + kNSMid];  // direction dv, dp, then the midpoints u~, v~, w~, mu~
+  lin_prologue<T, TD, 4, kNSMid, kNSLin>(S, m, pl, blockIdx.x, ref, lin, mid, dU, ldD, offD, q, c);
   NSPoint<T> P;
-  ns_lin_unpack<T>(p, q, L, P);
+  const T cm[kNSMid] = {c[4], c[5], c[6], c[7]};
+  ns_lin_unpack<T>(p, q, cm, L, P);
   VG<T> dvt[3];
   T ddv[3];
 #pragma unroll
@@ -797,7 +822,7 @@ __global__ __launch_bounds__(256) void k_ch_jvp_lin(MeshView m, PlanView pl, Phy
   L.init(threadIdx.x & 7, m.level[e]);
   const int ref = m.elem[e * 8 + L.c];
   T q[kCHLin], c[2];
-  lin_prologue<T, TD, 2, kCHLin>(S, m, pl, blockIdx.x, ref, lin, dU, ldD, offD, q, c);
+  lin_prologue<T, TD, 2, 0, kCHLin>(S, m, pl, blockIdx.x, ref, lin, (const T*)nullptr, dU, ldD, offD, q, c);
   const VG<T> dp = eval_vg<T>(c[0], L);
   const VG<T> dm = eval_vg<T>(c[1], L);
   T r[2];

@@ -37,13 +37,15 @@ int64_t mesh_footprint(const chns_mesh* m) {
          sz(P.tgt.size() * 4, 8) + sz(P.ntouch_slot.size() * 16, 8);
 }
 
-// Device bytes of the cached linearisation points of a mesh, both blocks
-// (ensure_lin), at the precision of the inner solve.  The coupled solve
+// Device bytes of the cached linearisation points of a mesh, both blocks, and
+// the NS nodal midpoints (ensure_lin), at the precision of the inner solve.  The coupled solve
 // builds them only for its multigrid preconditioner.
 int64_t lin_footprint(const chns_mesh* m, const chns_solver_opts& o) {
   if (o.coupled && o.precond != 2) return 0;
   const int64_t chunks = std::max<int64_t>((int64_t)m->plan.tgt_off.size() - 1, 1);
-  return chunks * (dev::kNSLin + dev::kCHLin) * dev::kChunkThreads * (o.precision == 0 ? 8 : 4);
+  const int64_t n = std::max<int64_t>((int64_t)m->h.node_key.size(), 1);
+  return (chunks * (dev::kNSLin + dev::kCHLin) * dev::kChunkThreads + n * dev::kNSMid) *
+         (o.precision == 0 ? 8 : 4);
 }
 
 // Device bytes of Solver::ensure_workspace() for n nodes under opts.
