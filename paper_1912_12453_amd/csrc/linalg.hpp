@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace chns {
 namespace dev {
@@ -59,6 +60,30 @@ __device__ __forceinline__ double block_reduce_sum(double v, double* sh) {
   return r;  // valid on thread 0
 }
 
+// out[j * stride] = the block's sum of v[j], for j < kk: for every j the wave
+// butterfly and the in-order sum over waves of block_reduce_sum (so the bits
+// are those of kk calls of it), behind one barrier instead of 2 kk.
+// sh holds (blockDim.x / 64) * K doubles.
+template <int K>
+__device__ __forceinline__ void block_reduce_sums(const double (&v)[K], int kk, double* sh,
+                                                  double* __restrict__ out, int64_t stride) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    if (j < kk) {
+      double x = v[j];
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if (l == 0) sh[w * K + j] = x;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < kk) {
+    double r = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i * K + threadIdx.x];
+    out[(int64_t)threadIdx.x * stride] = r;
+  }
+}
+
 // max that lets a NaN through (fmax would drop it)
 __device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
 
@@ -74,6 +99,55 @@ __device__ __forceinline__ double block_reduce_max(double v, double* sh) {
   return r;
 }
 
+// f(std::integral_constant<int, kk>) for 1 <= kk <= K: the loops below get
+// compile-time trip counts, so a row's loads of all kk basis vectors are
+// issued before the first wait (a loop over a runtime count with a guarded
+// load per vector waits for each load before issuing the next).
+template <int K, class F>
+__device__ __forceinline__ void with_count(int kk, F&& f) {
+  if constexpr (K > 0) {
+    if (kk == K)
+      f(std::integral_constant<int, K>{});
+    else
+      with_count<K - 1>(kk, f);
+  }
+}
+
+template <class TV, int K>
+__device__ __forceinline__ void multidot_rows(const TV* __restrict__ Vt, int64_t stride,
+                                              const TV* __restrict__ w, int64_t n, double (&acc)[kDotTile]) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double wi = (double)w[i];
+    TV v[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) v[j] = Vt[j * stride + i];
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j] += (double)v[j] * wi;
+  }
+}
+
+// w -= sum_j c_j V_j row by row, then the dots of the updated w with the same
+// K basis entries of the row, kept in registers.
+template <class TV, int K>
+__device__ __forceinline__ void axpy_multidot_rows(TV* __restrict__ w, const TV* __restrict__ V, int64_t stride,
+                                                   const double* cc, int64_t n, double (&acc)[kDotTile]) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    TV v[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) v[j] = V[j * stride + i];
+    double s = (double)w[i];
+#pragma unroll
+    for (int j = 0; j < K; ++j) s -= cc[j] * (double)v[j];
+    const TV st = (TV)s;
+    w[i] = st;
+    const double wi = (double)st;
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j] += (double)v[j] * wi;
+  }
+}
+
 // part[j * gridDim.x + b] = partial sum over block b of V_j . w, j < k.
 // blockIdx.y picks a tile of kDotTile basis vectors (grid.y = ceil(k / kDotTile)).
 template <class TV>
@@ -81,27 +155,15 @@ __global__ __launch_bounds__(256) void k_multidot(const TV* __restrict__ V, int6
                                                   const TV* __restrict__ w, int64_t n,
                                                   double* __restrict__ part, const int* skip) {
   if (skipped(skip)) return;
-  __shared__ double sh[4];
+  __shared__ double shm[4 * kDotTile];
   const int j0 = blockIdx.y * kDotTile;
   const int kk = min(kDotTile, k - j0);
   const TV* __restrict__ Vt = V + (int64_t)j0 * stride;
   double acc[kDotTile];
 #pragma unroll
   for (int j = 0; j < kDotTile; ++j) acc[j] = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const double wi = (double)w[i];
-#pragma unroll
-    for (int j = 0; j < kDotTile; ++j)
-      if (j < kk) acc[j] += (double)Vt[j * stride + i] * wi;
-  }
-#pragma unroll
-  for (int j = 0; j < kDotTile; ++j) {  // unrolled: acc stays in registers
-    if (j < kk) {
-      const double s = block_reduce_sum(acc[j], sh);
-      if (threadIdx.x == 0) part[(int64_t)(j0 + j) * gridDim.x + blockIdx.x] = s;
-    }
-  }
+  with_count<kDotTile>(kk, [&](auto KC) { multidot_rows<TV, decltype(KC)::value>(Vt, stride, w, n, acc); });
+  block_reduce_sums<kDotTile>(acc, kk, shm, part + (int64_t)j0 * gridDim.x + blockIdx.x, gridDim.x);
 }
 
 // w -= sum_{j<k} c_j V_j, then part[j * gridDim.x + b] = partial sum over
@@ -114,33 +176,15 @@ __global__ __launch_bounds__(256) void k_axpy_multidot(TV* __restrict__ w, const
                                                        int64_t stride, int k, const double* __restrict__ c,
                                                        int64_t n, double* __restrict__ part, const int* skip) {
   if (skipped(skip)) return;
-  __shared__ double sh[4];
+  __shared__ double shm[4 * kDotTile];
   __shared__ double cc[kDotTile];
   for (int j = threadIdx.x; j < k; j += blockDim.x) cc[j] = c[j];
   __syncthreads();
   double acc[kDotTile];
 #pragma unroll
   for (int j = 0; j < kDotTile; ++j) acc[j] = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    double s = (double)w[i];
-#pragma unroll 8
-    for (int j = 0; j < k; ++j) s -= cc[j] * (double)V[j * stride + i];
-    const TV st = (TV)s;
-    w[i] = st;
-    const double wi = (double)st;
-    // the second read of the row's basis entries comes from cache
-#pragma unroll
-    for (int j = 0; j < kDotTile; ++j)
-      if (j < k) acc[j] += (double)V[j * stride + i] * wi;
-  }
-#pragma unroll
-  for (int j = 0; j < kDotTile; ++j) {
-    if (j < k) {
-      const double t = block_reduce_sum(acc[j], sh);
-      if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = t;
-    }
-  }
+  with_count<kDotTile>(k, [&](auto KC) { axpy_multidot_rows<TV, decltype(KC)::value>(w, V, stride, cc, n, acc); });
+  block_reduce_sums<kDotTile>(acc, k, shm, part + blockIdx.x, gridDim.x);
 }
 
 // out[j] = sum_b part[j * nb + b] in block order
