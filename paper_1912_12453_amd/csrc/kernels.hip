@@ -902,6 +902,40 @@ __global__ __launch_bounds__(256) void k_ns_jvp_full(MeshView m, PlanView pl, Ph
 }
 
 // -------------------------------------------------------- node gather ----
+// acc[f] = the sum over node i's target slots k = node_off[i] .. node_off[i+1]-1,
+// in that order, of partial[node_slot[k] * NF + f].  The ids of the first four
+// slots, then their rows, are loaded before the first add, so a node waits
+// for three loads in sequence instead of two per slot (past its last slot a
+// node loads that slot again and does not add it).  Slots beyond the fourth
+// follow in a loop.
+template <int NF, class TP>
+__device__ __forceinline__ void gather_node(const PlanView& pl, int64_t i, const TP* __restrict__ partial,
+                                            TP (&acc)[NF]) {
+  constexpr int U = 4;
+  const int k0 = pl.node_off[i], k1 = pl.node_off[i + 1];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) acc[f] = 0;
+  if (k1 <= k0) return;
+  int64_t sl[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) sl[u] = pl.node_slot[min(k0 + u, k1 - 1)];
+  TP v[U][NF];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[u][f] = partial[sl[u] * NF + f];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (k0 + u < k1)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) acc[f] += v[u][f];
+  for (int k = k0 + U; k < k1; ++k) {
+    const int64_t s = pl.node_slot[k];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] += partial[s * NF + f];
+  }
+}
+
 // Every node sums its target slots in slot order and writes its rows of the
 // output (ld values per node starting at off; with ld = 6 the other block's
 // entries are set to 0).  Boundary rows of the NS block are written here too:
@@ -917,13 +951,7 @@ __global__ void k_gather(PlanView pl, int64_t n, const TP* __restrict__ partial,
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     TP acc[NF];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) acc[f] = 0;
-    for (int k = pl.node_off[i]; k < pl.node_off[i + 1]; ++k) {
-      const int64_t s = pl.node_slot[k];
-#pragma unroll
-      for (int f = 0; f < NF; ++f) acc[f] += partial[s * NF + f];
-    }
+    gather_node<NF, TP>(pl, i, partial, acc);
     TO v[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) v[f] = (TO)acc[f];

@@ -187,14 +187,30 @@ __global__ __launch_bounds__(256) void k_axpy_multidot(TV* __restrict__ w, const
   block_reduce_sums<kDotTile>(acc, k, shm, part + blockIdx.x, gridDim.x);
 }
 
+// sum over b = threadIdx.x, threadIdx.x + blockDim.x, ... < nb of p[b], added
+// in that order; the first four loads are issued before the first add (the
+// partial counts here are at most 4 per thread).  Lanes past the end load
+// p[nb - 1] and do not add it.  nb >= 1.
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int nb) {
+  const int t = threadIdx.x, d = blockDim.x;
+  double v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = p[min(t + u * d, nb - 1)];
+  double s = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (t + u * d < nb) s += v[u];
+  for (int b = t + 4 * d; b < nb; b += d) s += p[b];
+  return s;
+}
+
 // out[j] = sum_b part[j * nb + b] in block order
 __global__ void k_finish_sum(const double* __restrict__ part, int nb, int k, double* __restrict__ out,
                              const int* skip) {
   if (skipped(skip)) return;
   __shared__ double sh[4];
   for (int j = blockIdx.x; j < k; j += gridDim.x) {
-    double s = 0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(int64_t)j * nb + b];
+    double s = strided_sum(part + (int64_t)j * nb, nb);
     s = block_reduce_sum(s, sh);
     if (threadIdx.x == 0) out[j] = s;
   }
@@ -303,9 +319,7 @@ struct GmresCtl {
 // fixed-order sum of nb partials, valid on thread 0
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nb) {
   __shared__ double sh[4];
-  double s = 0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
-  return block_reduce_sum(s, sh);
+  return block_reduce_sum(strided_sum(part, nb), sh);
 }
 
 // Starts a run from the partial sums of b . b (x_0 = 0, so r_0 = b).

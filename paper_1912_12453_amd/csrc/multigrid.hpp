@@ -48,11 +48,28 @@ __global__ void k_restrict(const TV* __restrict__ rf, const int32_t* __restrict_
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[f] = 0;
     const int cnt = r_off[j + 1] - r_off[j];
-    for (int k = 0; k < cnt; ++k) {
-      const int64_t i = r_eidx[(int64_t)k * nc + j];
-      const double w = (double)r_ew[(int64_t)k * nc + j];
+    // groups of U entries: ids and weights, then the rows, then the adds in
+    // list order (entries past the end load the last one and are not added)
+    constexpr int U = 8;
+    for (int k = 0; k < cnt; k += U) {
+      int64_t ii[U];
+      double ww[U];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) acc[f] += w * (double)rf[i * NF + f];
+      for (int u = 0; u < U; ++u) {
+        const int64_t q = (int64_t)min(k + u, cnt - 1) * nc + j;
+        ii[u] = r_eidx[q];
+        ww[u] = (double)r_ew[q];
+      }
+      TV vv[U][NF];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) vv[u][f] = rf[ii[u] * NF + f];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (k + u < cnt)
+#pragma unroll
+          for (int f = 0; f < NF; ++f) acc[f] += ww[u] * (double)vv[u][f];
     }
     const uint8_t b = bf_c[j];
     TV v[NF];
@@ -87,11 +104,27 @@ __global__ void k_prolong_add(TV* __restrict__ xf, const uint8_t* __restrict__ b
     double acc[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[f] = 0;
-    for (int k = p_off[i]; k < p_off[i + 1]; ++k) {
-      const int64_t j = p_idx[k];
-      const double w = p_w[k];
+    const int k0 = p_off[i], k1 = p_off[i + 1];
+    constexpr int U = 8;  // as in k_restrict
+    for (int k = k0; k < k1; k += U) {
+      int64_t jj[U];
+      double ww[U];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) acc[f] += w * (double)ec[j * NF + f];
+      for (int u = 0; u < U; ++u) {
+        const int q = min(k + u, k1 - 1);
+        jj[u] = p_idx[q];
+        ww[u] = p_w[q];
+      }
+      TV vv[U][NF];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) vv[u][f] = ec[jj[u] * NF + f];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (k + u < k1)
+#pragma unroll
+          for (int f = 0; f < NF; ++f) acc[f] += ww[u] * (double)vv[u][f];
     }
     const uint8_t b = bf_f[i];
 #pragma unroll
@@ -140,13 +173,7 @@ __global__ void k_gather_vcycle(PlanView pl, int64_t n, const TV* __restrict__ p
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     TV acc[NF];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) acc[f] = 0;
-    for (int k = pl.node_off[i]; k < pl.node_off[i + 1]; ++k) {
-      const int64_t sl = pl.node_slot[k];
-#pragma unroll
-      for (int f = 0; f < NF; ++f) acc[f] += partial[sl * NF + f];
-    }
+    gather_node<NF, TV>(pl, i, partial, acc);
     const uint8_t bb = pl.bflags[i];
     if (NF == 4 && block == 1) {
       if (bb & 1)
