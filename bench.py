@@ -53,9 +53,50 @@ NS_JVP_FLOPS_PER_ELEMENT = {"fp64": 5728, "mixed": 5656}
 NS_JVP_BYTES_PER_NODE = {"fp64": (4 + NS_MID + 4) * 8, "mixed": (4 + NS_MID + 4) * 4}
 NS_JVP_BYTES_PER_ELEMENT = {"fp64": NS_LIN * 8 * 8 + 8 * 4 + 1, "mixed": NS_LIN * 8 * 4 + 8 * 4 + 1}
 
+# The same for every element kernel bench.py times (both roofline fractions
+# per kernel): flops per element (the NS cached JVP and linearisation from the
+# VALU counters of one launch; the others 8 lanes x the static count of one
+# lane's arithmetic in the kernel's gfx950 code) and algorithmic bytes per node
+# (state staged at both time levels, direction, result, nodal midpoints, at
+# their widths) and per element (corner ids and level byte, cached values).
+# Key: bench.py's kernel timing name; value: (flops, bytes/node, bytes/element,
+# peak).  ns_lin_* also launches k_ns_mid (its reads and writes per node).
+ELEMENT_KERNELS = {
+    "ch_residual": (1656, (10 + 2) * 8, 33, "fp64"),
+    "ns_residual": (5216, (12 + 4) * 8, 33, "fp64"),
+    "ch_jvp_f64": (1696, (10 + 2 + 2) * 8, 33, "fp64"),
+    "ch_jvp_f32": (1704, 10 * 8 + (2 + 2) * 4, 33, "mixed"),
+    "ns_jvp_f64": (7064, (12 + 4 + 4) * 8, 33, "fp64"),
+    "ns_jvp_f32": (6992, 12 * 8 + (4 + 4) * 4, 33, "mixed"),
+    "ch_lin_f64": (568, 10 * 8, 33 + 4 * 8 * 8, "fp64"),
+    "ch_lin_f32": (568, 10 * 8, 33 + 4 * 8 * 4, "mixed"),
+    "ch_jvp_lin_f64": (1256, (2 + 2) * 8, 33 + 4 * 8 * 8, "fp64"),
+    "ch_jvp_lin_f32": (1264, (2 + 2) * 4, 33 + 4 * 8 * 4, "mixed"),
+    "ns_lin_f64": (2597, 12 * 8 + (8 + 4) * 8, 33 + NS_LIN * 8 * 8, "fp64"),
+    "ns_lin_f32": (2455, 12 * 8 + 8 * 8 + 4 * 4, 33 + NS_LIN * 8 * 4, "mixed"),
+    "ns_jvp_lin_f64": (NS_JVP_FLOPS_PER_ELEMENT["fp64"], NS_JVP_BYTES_PER_NODE["fp64"],
+                       NS_JVP_BYTES_PER_ELEMENT["fp64"], "fp64"),
+    "ns_jvp_lin_f32": (NS_JVP_FLOPS_PER_ELEMENT["mixed"], NS_JVP_BYTES_PER_NODE["mixed"],
+                       NS_JVP_BYTES_PER_ELEMENT["mixed"], "mixed"),
+}
+
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # FP64 vector; FP32 vector
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_roofline(kern, n, E):
+    """Both roofline fractions of every timed element kernel (one launch)."""
+    out = {}
+    for key, (flops, bpn, bpe, peak) in ELEMENT_KERNELS.items():
+        ms = kern.get(f"{key}_ms")
+        if not ms:
+            continue
+        gbs = (n * bpn + E * bpe) / (ms * 1e-3) / 1e9
+        tf = flops * E / (ms * 1e-3) / 1e12
+        out[key] = {"ms": round(ms, 4), "GBps": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
+                    "TFLOPs": round(tf, 3), "alu_frac": round(tf / PEAK_TFLOPS[peak], 4)}
+    return out
 
 
 def log(*a):
@@ -400,6 +441,7 @@ def main():
         "cpu_baseline": cpu,
         "cn_steps": steps,
         "kernels": {k: round(v, 4) for k, v in kern.items()},
+        "kernel_roofline": kernel_roofline(kern, n, E),
     }
     print(json.dumps(res), flush=True)
 
