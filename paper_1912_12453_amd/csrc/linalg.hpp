@@ -190,8 +190,9 @@ __global__ __launch_bounds__(256) void k_axpy_multidot(TV* __restrict__ w, const
 // sum over b = threadIdx.x, threadIdx.x + blockDim.x, ... < nb of p[b], added
 // in that order; the first four loads are issued before the first add (the
 // partial counts here are at most 4 per thread).  Lanes past the end load
-// p[nb - 1] and do not add it.  nb >= 1.
+// p[nb - 1] and do not add it; nb <= 0 gives 0 and reads nothing.
 __device__ __forceinline__ double strided_sum(const double* __restrict__ p, int nb) {
+  if (nb <= 0) return 0.0;
   const int t = threadIdx.x, d = blockDim.x;
   double v[4];
 #pragma unroll
