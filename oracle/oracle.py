@@ -78,14 +78,14 @@ def lib():
         L.orc_mesh_free.argtypes = [C.c_void_p]
         L.orc_mesh_sizes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
         L.orc_mesh_arrays.argtypes = [C.c_void_p] + [C.c_void_p] * 8
-        L.orc_residual.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, dp, dp, dp, dp]
+        L.orc_residual.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, dp, dp, dp, dp, dp]
         L.orc_jvp.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, dp, dp, dp, dp]
         L.orc_jvp_full.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, dp, dp, dp, dp]
         L.orc_residual_rows.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, dp, dp,
                                         C.POINTER(C.c_int32), C.c_int64, dp, dp]
         L.orc_diag_blocks.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, dp, dp, dp]
         L.orc_diagnostics.argtypes = [C.c_void_p, C.POINTER(Params), dp, dp, dp]
-        L.orc_step.argtypes = [C.c_void_p, C.POINTER(Params), C.POINTER(SolverOpts), dp, dp,
+        L.orc_step.argtypes = [C.c_void_p, C.POINTER(Params), C.POINTER(SolverOpts), dp, dp, dp,
                                C.POINTER(StepStats)]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
@@ -184,14 +184,19 @@ class Mesh:
         """Physical coordinates of the independent nodes."""
         return self.nodes.astype(np.float64) * 2.0 ** (-self.level_max)
 
-    def residual(self, p, block, Unew, Uold, forcing=None):
+    def residual(self, p, block, Unew, Uold, forcing=None, bc=None):
+        """Block residual; forcing (E, 8, 6) at the Gauss points, bc (n, 6)
+        whose boundary velocities are the wall data at t^{k+1}."""
         n = self.n_nodes
         Unew, Uold = _state(Unew, n), _state(Uold, n)
         R = np.zeros((n, 6))
         if forcing is not None:
             forcing = np.ascontiguousarray(forcing, dtype=np.float64)
             assert forcing.shape == (self.n_leaves, 8, 6)
-        rc = lib().orc_residual(self._h, C.byref(p), block, _dp(Unew), _dp(Uold), _dp(forcing), _dp(R))
+        if bc is not None:
+            bc = _state(bc, n)
+        rc = lib().orc_residual(self._h, C.byref(p), block, _dp(Unew), _dp(Uold), _dp(forcing),
+                                _dp(bc), _dp(R))
         if rc != 0:
             raise RuntimeError(_err())
         return R
@@ -246,13 +251,18 @@ class Mesh:
         lib().orc_diagnostics(self._h, C.byref(p), _dp(U), C.byref(m), C.byref(e))
         return m.value, e.value
 
-    def step(self, p, opts, U, forcing=None):
+    def step(self, p, opts, U, forcing=None, bc=None):
+        """One CN step from U; forcing (E, 8, 6) at the Gauss points at
+        t^{k+1/2}, bc (n, 6) with the wall velocities at t^{k+1}."""
         U = _state(U, self.n_nodes).copy()
         st = StepStats()
         if forcing is not None:
             forcing = np.ascontiguousarray(forcing, dtype=np.float64)
             assert forcing.shape == (self.n_leaves, 8, 6)
-        rc = lib().orc_step(self._h, C.byref(p), C.byref(opts), _dp(U), _dp(forcing), C.byref(st))
+        if bc is not None:
+            bc = _state(bc, self.n_nodes)
+        rc = lib().orc_step(self._h, C.byref(p), C.byref(opts), _dp(U), _dp(forcing), _dp(bc),
+                            C.byref(st))
         if rc != 0:
             raise RuntimeError(_err())
         return U, st

@@ -65,11 +65,18 @@ enum { BLOCK_CH = 0, BLOCK_NS = 1 };
 // Optional manufactured-solution forcing at quadrature points:
 // forcing[(e*8 + q)*6 + f], f in (phi-eq, mu-eq, momentum x,y,z, continuity).
 // May be null.
+//
+// Optional Dirichlet data: bc is a node-major 6-field vector whose velocity
+// entries at boundary nodes are the wall velocity at t^{k+1}; the velocity
+// rows of boundary nodes then read v^{k+1} - bc.  When bc is null the wall
+// data is carried by the state (rows v^{k+1} - v^k), which keeps stationary
+// walls (no-slip) fixed.
 
 // Element loop over all elements (or the listed subset), assembled through
 // the hanging-node transpose, followed by the boundary rows.
 std::string residual(const Mesh& m, const Params& p, int block, const double* Unew,
-                     const double* Uold, const double* forcing, double* R);
+                     const double* Uold, const double* forcing, double* R,
+                     const double* bc = nullptr);
 std::string jvp(const Mesh& m, const Params& p, int block, const double* Unew,
                 const double* Uold, const double* dU, double* JdU);
 // The block's rows of the coupled Jacobian: the derivative with respect to all
@@ -99,6 +106,6 @@ struct StepStats {
   double rel_res[2], mass, energy;
 };
 std::string step(const Mesh& m, const Params& p, const SolverOpts& o, double* U,
-                 const double* forcing, StepStats* st);
+                 const double* forcing, const double* bc, StepStats* st);
 
 }  // namespace orc

@@ -67,8 +67,8 @@ void orc_mesh_arrays(void* mp, int32_t* leaves4, int32_t* elem8, int32_t* nodes3
 }
 
 int orc_residual(void* m, const orc::Params* p, int block, const double* Unew, const double* Uold,
-                 const double* forcing, double* R) {
-  std::string e = orc::residual(*(orc::Mesh*)m, *p, block, Unew, Uold, forcing, R);
+                 const double* forcing, const double* bc, double* R) {
+  std::string e = orc::residual(*(orc::Mesh*)m, *p, block, Unew, Uold, forcing, R, bc);
   return e.empty() ? 0 : fail(e);
 }
 
@@ -103,8 +103,8 @@ void orc_diagnostics(void* m, const orc::Params* p, const double* U, double* mas
 }
 
 int orc_step(void* m, const orc::Params* p, const orc::SolverOpts* o, double* U,
-             const double* forcing, orc::StepStats* st) {
-  std::string e = orc::step(*(orc::Mesh*)m, *p, *o, U, forcing, st);
+             const double* forcing, const double* bc, orc::StepStats* st) {
+  std::string e = orc::step(*(orc::Mesh*)m, *p, *o, U, forcing, bc, st);
   return e.empty() ? 0 : fail(e);
 }
 

@@ -366,20 +366,21 @@ static bool ns_element(const Mesh& m, const Params& p, size_t e, const S v1[8][3
 }
 
 // --------------------------------------------------- assembled operators --
-// Boundary rows (the paper's Dirichlet condition v~ = 0 on the boundary and
-// the pressure level, which the all-Dirichlet velocity leaves undetermined):
-// velocity rows of boundary nodes read R = v^{k+1} - v^k (the boundary data is
-// carried by the state and is zero for no-slip walls); the pressure row of the
-// pinned node reads R = p^{k+1} - p^k.  Element contributions to those rows
-// are dropped.
-static void boundary_rows(const Mesh& m, int block, const double* A, const double* B,
-                          double* R) {
+// Boundary rows (the paper's Dirichlet condition on the velocity and the
+// pressure level, which the all-Dirichlet velocity leaves undetermined):
+// velocity rows of boundary nodes read R = v^{k+1} - g with the wall data g
+// (Bv, the velocity entries of Bv; Bv = U^k carries stationary walls); the
+// pressure row of the pinned node reads R = p^{k+1} - p^k (Bp = U^k).
+// Element contributions to those rows are dropped.  For the JVP both B are
+// null and the rows are identity rows.
+static void boundary_rows(const Mesh& m, int block, const double* A, const double* Bv,
+                          const double* Bp, double* R) {
   if (block != BLOCK_NS) return;
   for (size_t n = 0; n < m.nodes.size(); ++n) {
     if (m.bflags[n] & 1)
       for (int d = 0; d < 3; ++d)
-        R[n * 6 + 2 + d] = A[n * 6 + 2 + d] - (B ? B[n * 6 + 2 + d] : 0.0);
-    if (m.bflags[n] & 2) R[n * 6 + 5] = A[n * 6 + 5] - (B ? B[n * 6 + 5] : 0.0);
+        R[n * 6 + 2 + d] = A[n * 6 + 2 + d] - (Bv ? Bv[n * 6 + 2 + d] : 0.0);
+    if (m.bflags[n] & 2) R[n * 6 + 5] = A[n * 6 + 5] - (Bp ? Bp[n * 6 + 5] : 0.0);
   }
 }
 
@@ -433,7 +434,8 @@ static bool element_eval(const Mesh& m, const Params& p, int block, size_t e,
 
 static std::string assemble(const Mesh& m, const Params& p, int block, const double* Unew,
                             const double* Uold, const double* dU, const double* forcing,
-                            double* out, bool want_derivative, bool full = false) {
+                            double* out, bool want_derivative, bool full = false,
+                            const double* bc = nullptr) {
   const size_t n = m.nodes.size(), E = m.leaves.size();
   std::memset(out, 0, sizeof(double) * n * 6);
   const int f0 = block == BLOCK_CH ? 0 : 2, nf = block == BLOCK_CH ? 2 : 4;
@@ -454,15 +456,15 @@ static std::string assemble(const Mesh& m, const Params& p, int block, const dou
     scatter(m, e, r, out, f0, nf);
   }
   if (want_derivative)
-    boundary_rows(m, block, dU, nullptr, out);
+    boundary_rows(m, block, dU, nullptr, nullptr, out);
   else
-    boundary_rows(m, block, Unew, Uold, out);
+    boundary_rows(m, block, Unew, bc ? bc : Uold, Uold, out);
   return "";
 }
 
 std::string residual(const Mesh& m, const Params& p, int block, const double* Unew,
-                     const double* Uold, const double* forcing, double* R) {
-  return assemble(m, p, block, Unew, Uold, nullptr, forcing, R, false);
+                     const double* Uold, const double* forcing, double* R, const double* bc) {
+  return assemble(m, p, block, Unew, Uold, nullptr, forcing, R, false, false, bc);
 }
 
 std::string jvp(const Mesh& m, const Params& p, int block, const double* Unew,
@@ -506,9 +508,9 @@ std::string residual_rows(const Mesh& m, const Params& p, int block, const doubl
     scatter(m, e, dU ? d : o, full.data(), f0, nf);
   }
   if (dU)
-    boundary_rows(m, block, dU, nullptr, full.data());
+    boundary_rows(m, block, dU, nullptr, nullptr, full.data());
   else
-    boundary_rows(m, block, Unew, Uold, full.data());
+    boundary_rows(m, block, Unew, Uold, Uold, full.data());
   for (int64_t k = 0; k < nrows; ++k)
     for (int f = 0; f < 6; ++f) out[k * 6 + f] = full[(size_t)rows[k] * 6 + f];
   return "";

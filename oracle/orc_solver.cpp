@@ -181,7 +181,8 @@ std::string gmres(const BlockSystem& S, const Vec& b, Vec& x, int restart, int m
 
 // Newton's method on one block (Sec. 3.5): U_{s+1} = U_s + dU with J dU = -F.
 std::string newton(const Mesh& m, const Params& p, const SolverOpts& o, int block,
-                   double* Unew, const double* Uold, const double* forcing, int* newton_its,
+                   double* Unew, const double* Uold, const double* forcing, const double* bc,
+                   int* newton_its,
                    int* gmres_its, double* rel_res, bool* converged) {
   const size_t n = m.nodes.size();
   const int f0 = block == BLOCK_CH ? 0 : 2, nf = block == BLOCK_CH ? 2 : 4;
@@ -189,7 +190,7 @@ std::string newton(const Mesh& m, const Params& p, const SolverOpts& o, int bloc
   std::vector<double> R6(n * 6);
   Vec r(n * nf);
   auto eval = [&]() -> std::string {
-    std::string err = residual(m, p, block, Unew, Uold, forcing, R6.data());
+    std::string err = residual(m, p, block, Unew, Uold, forcing, R6.data(), bc);
     if (!err.empty()) return err;
     for (size_t i = 0; i < n; ++i)
       for (int f = 0; f < nf; ++f) r[i * nf + f] = R6[i * 6 + f0 + f];
@@ -232,7 +233,7 @@ std::string newton(const Mesh& m, const Params& p, const SolverOpts& o, int bloc
 }  // namespace
 
 std::string step(const Mesh& m, const Params& p, const SolverOpts& o, double* U,
-                 const double* forcing, StepStats* st) {
+                 const double* forcing, const double* bc, StepStats* st) {
   const size_t n = m.nodes.size();
   std::vector<double> Uold(U, U + n * 6), Unew(U, U + n * 6), prev(n * 6);
   std::memset(st, 0, sizeof(StepStats));
@@ -243,7 +244,8 @@ std::string step(const Mesh& m, const Params& p, const SolverOpts& o, double* U,
       int nit = 0, git = 0;
       double rr = 0;
       bool conv = false;
-      std::string err = newton(m, p, o, b, Unew.data(), Uold.data(), forcing, &nit, &git, &rr, &conv);
+      std::string err = newton(m, p, o, b, Unew.data(), Uold.data(), forcing, bc, &nit, &git, &rr,
+                               &conv);
       if (!err.empty()) return err;
       st->newton_its[b] += nit;
       st->gmres_its[b] += git;

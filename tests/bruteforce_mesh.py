@@ -123,3 +123,36 @@ def build(leaves, D):
             row.append(nid[Q] if Q in nid else -1 - hid[Q])
         elem.append(row)
     return {"leaves": L, "nodes": indep, "hanging": hang, "constraints": cons, "elem": elem}
+
+
+def refine(trees, level_min, level_max, phi0, band):
+    """Top-down refinement of a brick of unit trees (integer unit 2^-level_max),
+    one octant at a time: an octant below level_max splits when it is below
+    level_min, or when any of nine samples of phi0 (its 8 corners and its
+    centre) has |phi0| < band, or the samples take both signs.  Returns the
+    unbalanced leaves (x, y, z, level)."""
+    D = level_max
+    out = []
+    stack = [(i << D, j << D, k << D, 0) for k in range(trees[2]) for j in range(trees[1])
+             for i in range(trees[0])]
+    unit = 2.0 ** -D
+    while stack:
+        L = stack.pop()
+        l = L[3]
+        if l == level_max:
+            out.append(L)
+            continue
+        if l < level_min:
+            split = True
+        else:
+            s = size(D, l)
+            pts = [tuple(q * unit for q in P) for P in corners(L, D)]
+            pts.append(tuple((L[d] + s // 2) * unit for d in range(3)))
+            vals = [float(phi0(P)) for P in pts]
+            split = (any(abs(v) < band for v in vals)
+                     or (any(v > 0 for v in vals) and any(v < 0 for v in vals)))
+        if split:
+            stack.extend(children(L, D))
+        else:
+            out.append(L)
+    return out

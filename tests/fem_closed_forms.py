@@ -84,3 +84,45 @@ def lattice_index(nodes_int, level):
     idx[nodes_int[:, 0], nodes_int[:, 1], nodes_int[:, 2]] = np.arange(nodes_int.shape[0])
     assert (idx >= 0).all()
     return idx
+
+
+# ------------------------------------------------ exact 1-D hat integrals --
+# Hats of a uniform grid of spacing h: node i at x_i = i h.  The integrals
+# below are computed cell by cell with exact polynomial antiderivatives (no
+# quadrature rule), optionally with a polynomial weight w(x) given by its
+# coefficients in increasing powers of x.
+def _hat_piece(i, cell, h, deriv):
+    """Polynomial coefficients, in the local coordinate s = x - x_cell in
+    [0, h], of hat i (or its derivative) on cell [x_cell, x_cell + h]."""
+    if cell == i - 1:      # rising part: s / h
+        return np.array([1.0 / h]) if deriv else np.array([0.0, 1.0 / h])
+    if cell == i:          # falling part: (h - s) / h
+        return np.array([-1.0 / h]) if deriv else np.array([1.0, -1.0 / h])
+    return np.array([0.0])
+
+
+def hat_integral(ia, da, ib, db, h, weight=(1.0,)):
+    """int w(x) hat_ia^(da)(x) hat_ib^(db)(x) dx over the real line (da, db in
+    {0, 1}: value or first derivative)."""
+    P = np.polynomial.polynomial
+    total = 0.0
+    for cell in (ia - 1, ia):
+        if cell not in (ib - 1, ib):
+            continue
+        # the weight in the local coordinate: w(x_cell + s)
+        w = np.polynomial.Polynomial(np.asarray(weight, float))(
+            np.polynomial.Polynomial([cell * h, 1.0])).coef
+        f = P.polymul(P.polymul(_hat_piece(ia, cell, h, da), _hat_piece(ib, cell, h, db)), w)
+        total += P.polyval(h, P.polyint(f))
+    return total
+
+
+def tensor_integral(a, da, b, db, h, weights=None):
+    """int prod_ax w_ax(x_ax) d^da N_a d^db N_b over R^3 for lattice nodes a, b
+    (index triples); da, db are derivative axes (None for the value); weights
+    maps an axis to polynomial coefficients of a weight along that axis."""
+    val = 1.0
+    for ax in range(3):
+        w = (weights or {}).get(ax, (1.0,))
+        val *= hat_integral(a[ax], int(da == ax), b[ax], int(db == ax), h, w)
+    return val

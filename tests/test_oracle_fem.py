@@ -488,3 +488,188 @@ def test_thread_count_does_not_change_results(orc, adaptive, block):
     many = (m.residual(p, block, U1, U0), m.jvp(p, block, U1, U0, d), m.diag_blocks(p, block, U1, U0))
     for a, b in zip(one, many):
         assert np.array_equal(a, b)
+
+
+# ------------------- linearisation about a state with R_m != 0, grad eta != 0 --
+def _jvp_rows_general(p, h, a, b, m, c, J, bvec, rho, eta_w, e, d0):
+    """Interior-row JVP entries (momentum x, y, z and continuity rows of node a)
+    for the direction dv = N_b e_m, about a base state with uniform velocity
+    c (grad v~ = 0), constant mass flux J, constant density rho, a constant
+    strong momentum residual R_m = bvec, R_c = 0, and a viscosity that is
+    linear along axis d0 (weight coefficients eta_w, gradient e); tau_m is
+    constant (C_I = 0 when eta varies).  The derivative of each term of Def. 2
+    (with readings A2, A3, A6, A7) is written out:
+      dR_m,i = delta_im L_b,  L_b = rho N_b/dt + rho/2 c.grad N_b
+                                   + 1/(2Pe) J.grad N_b - 1/(2Re) e.grad N_b
+      d tau_m = D N_b,        D = -tau_m^3 G (c_m + J_m/(2 rho Pe)) / 2
+      dR_c = dN_b/dx_m / 2.
+    Every integral is an exact tensor product of 1-D hat integrals."""
+    eta_const = eta_w[0] if len(eta_w) == 1 else None
+    G = 4 / h ** 2
+    c, J, bvec, e = (np.asarray(v, float) for v in (c, J, bvec, e))
+    visc = 0.0 if eta_const is None else p.C_I * (eta_const / (rho * p.Re)) ** 2 * 3 * G ** 2
+    assert eta_const is not None or p.C_I == 0.0
+    T0 = (4 / p.dt ** 2 + G * c @ c + G * (c @ J) / (rho * p.Pe) + visc) ** -0.5
+    tc = 1.0 / (3 * G * T0)
+    D = -0.5 * T0 ** 3 * G * (c[m] + J[m] / (2 * rho * p.Pe))
+
+    def I(A, B, w=None):
+        return CF.tensor_integral(a, A, b, B, h, None if w is None else {d0: w})
+
+    def IL(A):   # int A L_b
+        return (rho / p.dt * I(A, None)
+                + sum((0.5 * rho * c[k] + 0.5 / p.Pe * J[k] - 0.5 / p.Re * e[k]) * I(A, k)
+                      for k in range(3)))
+
+    rows = np.zeros(4)
+    for i in range(3):
+        t = 0.0
+        if i == m:
+            t += rho / p.dt * I(None, None)                                  # (w, rho dv/dt)
+            t += sum(0.5 * rho * c[j] * I(None, j) for j in range(3))        # Galerkin convection
+            t += sum(0.5 / p.Pe * J[j] * I(None, j) for j in range(3))       # (w, J.grad v)/Pe
+            t -= sum(0.5 * T0 * bvec[j] * I(None, j) for j in range(3))      # -(w_i, tau R_m,j d_j v_i)
+            t += 0.5 / p.Re * sum(I(k, k, eta_w) for k in range(3))          # (grad w, eta grad v)/Re
+            t += T0 * sum(c[j] * IL(j) for j in range(3))                    # SUPG: tau c.grad w dR_m
+            t -= T0 ** 2 / rho * sum(bvec[j] * IL(j) for j in range(3))
+            t += T0 / (rho * p.Pe) * sum(J[j] * IL(j) for j in range(3))
+        t += 0.5 * T0 * bvec[i] * I(m, None)                                 # dv~_j tau R_m,i
+        t += D * bvec[i] * sum(c[j] * I(j, None) for j in range(3))          # c_j d tau R_m,i
+        t -= 2 * T0 * D / rho * bvec[i] * sum(bvec[j] * I(j, None) for j in range(3))
+        t -= T0 ** 2 / rho * bvec[i] * IL(m)
+        t += D / (rho * p.Pe) * bvec[i] * sum(J[j] * I(j, None) for j in range(3))
+        t += rho * tc / (2 * p.We) * I(i, m)                                 # grad-div (tau_c R_c)
+        rows[i] = t
+    rows[3] = (0.5 * I(None, m) + D / rho * sum(bvec[j] * I(j, None) for j in range(3))
+               + T0 / rho * IL(m))
+    return rows
+
+
+@pytest.mark.parametrize("m_axis", [0, 1, 2])
+def test_ns_jvp_closed_form_with_momentum_residual(orc, uni3, m_axis):
+    """phi = 1 (rho = eta = 1), uniform v~ = c, mu~ linear (constant J), and a
+    pressure gradient that does not balance gravity, so R_m is a nonzero
+    constant b.  Pins the fine-scale convection term -(w_i, tau_m R_m,j
+    dv~_i/dx_j) with its index order (reading A3), d tau_m, and the products of
+    R_m with the SUPG and PSPG test functions."""
+    m, idx = uni3
+    h = 1 / 8
+    p = P(orc, dt=0.02, rho_minus=0.25, Cn=0.3, Pe=2.0, We=3.0, Fr=1.5)
+    x = m.node_xyz()
+    c = np.array([0.3, -0.2, 0.45])
+    grad_mu = np.array([0.5, -0.7, 0.2])
+    bvec = np.array([0.7, -0.4, 0.9])
+    alpha = 0.5 * (1 - p.rho_minus)
+    J = -(alpha / p.Cn) * grad_mu
+    g = np.array(p.g[:])
+    U = np.zeros((m.n_nodes, 6))
+    U[:, 0] = 1.0
+    U[:, 1] = x @ grad_mu
+    U[:, 2:5] = c
+    U[:, 5] = p.We * (x @ (bvec + g / p.Fr))     # (1/We) grad p - g/Fr = b
+    i, j, k = interior_centre(idx)
+    bnode = idx[i, j, k]
+    dU = np.zeros_like(U)
+    dU[bnode, 2 + m_axis] = 1.0
+    out = m.jvp(p, NS, U, U, dU)
+    for o in CF.offsets():
+        a = (i - o[0], j - o[1], k - o[2])
+        exp = _jvp_rows_general(p, h, a, (i, j, k), m_axis, c, J, bvec, 1.0, (1.0,), (0, 0, 0), 0)
+        np.testing.assert_allclose(out[idx[a], 2:], exp, rtol=1e-11, atol=1e-13 * np.abs(exp).max())
+
+
+@pytest.mark.parametrize("m_axis", [0, 1, 2])
+def test_ns_jvp_closed_form_with_viscosity_gradient(orc, uni3, m_axis):
+    """Density ratio 1 (rho = 1, J = 0), viscosity ratio 0.3 and phi linear
+    inside (-1, 1), so eta is linear and grad eta = gamma grad phi^{k+1}
+    (reading A22); C_I = 0 keeps tau_m constant.  Pins the -(1/Re) grad eta .
+    grad v~ term of R_m (through the stabilised test functions) and the
+    Galerkin viscous term with a varying eta, next to R_m = b != 0."""
+    m, idx = uni3
+    h = 1 / 8
+    p = P(orc, dt=0.02, rho_minus=1.0, eta_minus=0.3, Re=0.8, C_I=0.0)
+    x = m.node_xyz()
+    c = np.array([0.25, 0.4, -0.3])
+    bvec = np.array([-0.5, 0.6, 0.8])
+    d0, s, phic = 0, 1.2, 0.1                          # phi = phic + s (x - 1/2)
+    gamma, xi = 0.5 * (1 - p.eta_minus), 0.5 * (1 + p.eta_minus)
+    eta_w = (xi + gamma * (phic - 0.5 * s), gamma * s)
+    e = np.zeros(3)
+    e[d0] = gamma * s
+    g = np.array(p.g[:])
+    U = np.zeros((m.n_nodes, 6))
+    U[:, 0] = phic + s * (x[:, d0] - 0.5)
+    U[:, 1] = 0.3
+    U[:, 2:5] = c
+    U[:, 5] = p.We * (x @ (bvec + g / p.Fr))
+    i, j, k = interior_centre(idx)
+    bnode = idx[i, j, k]
+    dU = np.zeros_like(U)
+    dU[bnode, 2 + m_axis] = 1.0
+    out = m.jvp(p, NS, U, U, dU)
+    for o in CF.offsets():
+        a = (i - o[0], j - o[1], k - o[2])
+        exp = _jvp_rows_general(p, h, a, (i, j, k), m_axis, c, (0, 0, 0), bvec, 1.0, eta_w, e, d0)
+        np.testing.assert_allclose(out[idx[a], 2:], exp, rtol=1e-11, atol=1e-13 * np.abs(exp).max())
+
+
+# ------------------------------------------------------------ energy --------
+def _psi_integral_gauss(a, s, h):
+    """int_0^1 psi(a + s y) dy for psi = (phi^2 - 1)^2 / 4 as the per-cell
+    two-point Gauss rule computes it: the exact integral minus the rule's
+    error, which for a quartic is exactly h^5/4320 times the fourth
+    derivative on each cell of width h (the textbook Gauss-Legendre error
+    term), with d^4 psi/dy^4 = 6 s^4."""
+    F = lambda ph: (ph ** 5 / 5 - 2 * ph ** 3 / 3 + ph) / 4
+    exact = (F(a + s) - F(a)) / s
+    n = round(1 / h)
+    return exact - n * h ** 5 * 6 * s ** 4 / 4320
+
+
+@pytest.mark.parametrize("phi,gdir,trees", [(1.0, (0, -1, 0), (1, 1, 1)), (-1.0, (0, -1, 0), (1, 1, 1)),
+                                            (1.3, (0, 0, -1), (1, 1, 2)), (-1.0, (0.6, 0.0, -0.8), (2, 1, 1))])
+def test_energy_uniform_flow(orc, phi, gdir, trees):
+    """E_tot (Sec. 2, eqn energy_functional; readings A10, A11) of a uniform
+    phase with a uniform velocity: the kinetic energy 1/2 rho(phi*) |v|^2 |Omega|,
+    the free energy (1/(Cn We)) psi(phi) |Omega| (psi of the unclamped phi,
+    zero at +-1), and the potential (1/Fr) rho(phi*) int -g.x, outside the
+    1/(Cn We) factor."""
+    m = orc.Mesh(trees, 2, 2)
+    p = P(orc, g=gdir, Cn=0.3, We=3.0, Fr=1.5)
+    v = np.array([0.3, -0.7, 0.45])
+    U = np.zeros((m.n_nodes, 6))
+    U[:, 0] = phi
+    U[:, 2:5] = v
+    U[:, 5] = 0.77
+    _, E = m.diagnostics(p, U)
+    rho = 0.5 * (1 - p.rho_minus) * np.clip(phi, -1, 1) + 0.5 * (1 + p.rho_minus)
+    vol = float(np.prod(trees))
+    centroid = 0.5 * np.array(trees, float)
+    psi = 0.25 * (phi ** 2 - 1) ** 2
+    expect = (0.5 * rho * v @ v * vol + psi * vol / (p.Cn * p.We)
+              + rho / p.Fr * (-(np.array(gdir) @ centroid)) * vol)
+    assert E == pytest.approx(expect, rel=1e-14)
+
+
+def test_energy_linear_phase_field(orc):
+    """phi = a + s y inside (-1, 1), v uniform, gravity along -y: the kinetic
+    and potential integrals are polynomials the rule integrates exactly, the
+    gradient energy is (Cn^2/2) s^2, and the quartic psi(phi) is integrated
+    with the two-point rule's known error."""
+    lev = 3
+    m = orc.Mesh((1, 1, 1), lev, lev)
+    h = 2.0 ** -lev
+    p = P(orc, g=(0.0, -1.0, 0.0), Cn=0.3, We=3.0, Fr=1.5, rho_minus=0.25)
+    a, s = -0.6, 1.3
+    x = m.node_xyz()
+    v = np.array([0.2, 0.5, -0.1])
+    U = np.zeros((m.n_nodes, 6))
+    U[:, 0] = a + s * x[:, 1]
+    U[:, 2:5] = v
+    _, E = m.diagnostics(p, U)
+    alpha, beta = 0.5 * (1 - p.rho_minus), 0.5 * (1 + p.rho_minus)
+    int_rho = alpha * (a + s / 2) + beta                       # int rho
+    int_rho_y = alpha * (a / 2 + s / 3) + beta / 2             # int rho y
+    free = _psi_integral_gauss(a, s, h) + 0.5 * p.Cn ** 2 * s ** 2
+    expect = 0.5 * (v @ v) * int_rho + free / (p.Cn * p.We) + int_rho_y / p.Fr
+    assert E == pytest.approx(expect, rel=1e-13)

@@ -143,3 +143,30 @@ def test_invalid_leaves_rejected(orc):
         orc.Mesh((1, 1, 1), 0, 2, leaves=np.array([[0, 0, 0, 1]], np.int32))
     with pytest.raises(ValueError):
         orc.Mesh((1, 1, 1), 0, 2, leaves=np.array([[1, 0, 0, 2]] * 64, np.int32))
+
+
+def _small_sphere(centre, r, eps):
+    c = np.asarray(centre, float)
+
+    def f(P):
+        P = np.asarray(P, float)
+        return np.tanh((np.linalg.norm(P - c, axis=-1) - r) / eps)
+    return f
+
+
+@pytest.mark.parametrize("centre,r,lmin,lmax,trees", [
+    ((0.25, 0.25, 0.25), 0.05, 1, 4, (1, 1, 1)),      # seen first by a level-1 centre sample
+    ((0.625, 0.375, 0.125), 0.03, 2, 5, (1, 1, 1)),   # by a level-2 centre sample
+    ((1.25, 0.75, 0.25), 0.04, 1, 4, (2, 1, 1)),      # in the second tree of a brick
+    ((0.3, 0.55, 0.7), 0.22, 1, 4, (1, 1, 1)),        # corners and centres both matter
+])
+def test_refinement_matches_bruteforce(orc, centre, r, lmin, lmax, trees):
+    """The refinement rule (Sec. 4 "Refinement", reading A18) against a
+    one-octant-at-a-time restatement followed by the brute-force balance.  The
+    indicator is a sphere much smaller than the octants whose centre it sits
+    at, so the split at those octants comes from the centre sample alone."""
+    phi0 = _small_sphere(centre, r, 0.004)
+    m = orc.Mesh(trees, lmin, lmax, phi0=lambda P: phi0(P), band=0.9)
+    ref = BF.balance(BF.refine(trees, lmin, lmax, phi0, 0.9), lmax)
+    assert [tuple(int(v) for v in L) for L in m.leaves] == ref
+    assert max(L[3] for L in ref) == lmax

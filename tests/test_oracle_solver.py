@@ -8,6 +8,17 @@ import pytest
 from paper_1912_12453_amd import workloads as W
 
 
+@pytest.fixture(autouse=True)
+def one_thread(orc):
+    """These meshes have at most a few thousand elements: the oracle runs
+    them faster on one thread than with a parallel loop's start-up cost per
+    element pass (results do not depend on the thread count)."""
+    cores = orc.num_threads()
+    orc.set_num_threads(1)
+    yield
+    orc.set_num_threads(cores)
+
+
 def drop_setup(orc, level=3):
     w = W.drop16(level=level)
     m = orc.Mesh(w.mesh.trees, w.mesh.level_min, w.mesh.level_max)
