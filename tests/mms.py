@@ -109,3 +109,41 @@ def state(xyz, t):
     U[:, 2:5] = F["v"]
     U[:, 5] = F["p"]
     return U
+
+
+def l2_error(U, nodes_int, level, t, field):
+    """|| u_h - u ||_{L2(unit cube)} of field `field` of the nodal state U on
+    a uniform mesh of the given level, with the 2x2x2 Gauss rule per cell
+    (values at the points from tests/uniform_quadrature.py)."""
+    from tests import fem_closed_forms as CF
+    from tests import uniform_quadrature as UQ
+    h = 2.0 ** -level
+    N = 2 ** level
+    idx = CF.lattice_index(nodes_int, level)
+    val, _ = UQ.qp_fields(U[:, field], idx, h)
+    g = 1.0 / np.sqrt(3.0)
+    off = [0.5 * h * (1 + s * g) for s in (-1.0, 1.0)]
+    cells = np.arange(N) * h
+    e2, q = 0.0, 0
+    for qz in range(2):
+        for qy in range(2):
+            for qx in range(2):
+                X, Y, Z = np.meshgrid(cells + off[qx], cells + off[qy], cells + off[qz], indexing="ij")
+                P = np.stack([X, Y, Z], -1).reshape(-1, 3)
+                ex = state(P, t)[:, field].reshape(N, N, N)
+                e2 += ((val[q] - ex) ** 2).sum() * h ** 3 / 8
+                q += 1
+    return float(np.sqrt(e2))
+
+
+def run(m, prm, dt, T, opts):
+    """CN steps of the oracle from the exact state at t = 0 to T, with the
+    forcing at t^{k+1/2} and the exact wall velocity at t^{k+1}."""
+    import oracle
+    xyz, qp = m.node_xyz(), m.qp_coords()
+    p = oracle.Params.make(dt=dt, **prm)
+    U = state(xyz, 0.0)
+    for k in range(int(round(T / dt))):
+        U, st = m.step(p, opts, U, forcing=forcing_at(qp, (k + 0.5) * dt, prm), bc=state(xyz, (k + 1) * dt))
+        assert st.converged == 1
+    return U
