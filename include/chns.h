@@ -154,9 +154,7 @@ int chns_residual(chns_mesh* mesh, const chns_params* params, int block, const d
 int chns_jvp(chns_mesh* mesh, const chns_params* params, int block, const double* U_new,
              const double* U_old, const void* dU, void* JdU, int prec, void* stream);
 
-/* Node-block diagonal of the block Jacobian (2x2 for CH, 4x4 for NS per node,
- * row-major, device, n_nodes*nf*nf doubles), including the hanging-node
- * couplings; boundary rows are identity rows. */
+
 /* Rows of the coupled Jacobian (both blocks, derivatives with respect to all
  * six fields of U^{k+1}, the cross terms d R_NS / d(phi, mu) and
  * d R_CH / d v included) applied to dU (n_nodes*6 in the arithmetic of
@@ -191,6 +189,12 @@ int chns_linearize(chns_mesh* mesh, const chns_params* params, int block, const 
 int chns_jvp_lin(chns_mesh* mesh, const chns_params* params, int block, const void* dU, void* JdU,
                  int prec, void* stream);
 
+/* Node-block diagonal of the block Jacobian at (U_new, U_old) (2x2 for CH,
+ * 4x4 for NS per node, row-major, device, n_nodes*nf*nf doubles): the
+ * diagonal blocks of P^T J P, hanging-node couplings included, the Jacobi
+ * preconditioner of the Newton-Krylov solves of Sec. 3.5.  NS boundary rows
+ * are identity rows.  Work memory (touch blocks) is allocated with the mesh
+ * on first use. */
 int chns_diag_blocks(chns_mesh* mesh, const chns_params* params, int block,
                      const double* U_new, const double* U_old, double* D, void* stream);
 
@@ -254,6 +258,9 @@ typedef struct {
                             evaluated at the end of the step               */
   double mass, energy;   /* diagnostics of U^{k+1}                          */
   double t_ms;           /* wall time of the step                           */
+  int32_t singular_blocks; /* Newton iterations whose Jacobi or V-cycle
+                            diagonal had a singular node block (replaced by
+                            the identity in the preconditioner); 0 normally */
 } chns_step_stats;
 
 /* One Crank-Nicolson step (Fig. 1): U (device, n_nodes*6) holds U^k on entry

@@ -74,13 +74,13 @@ class chns_step_stats(C.Structure):
     _fields_ = [("block_its", C.c_int32), ("newton_its", C.c_int32 * 2),
                 ("gmres_its", C.c_int32 * 2), ("converged", C.c_int32),
                 ("rel_res", C.c_double * 2), ("mass", C.c_double), ("energy", C.c_double),
-                ("t_ms", C.c_double)]
+                ("t_ms", C.c_double), ("singular_blocks", C.c_int32)]
 
     def as_dict(self):
         return {"block_its": self.block_its, "newton_its": list(self.newton_its),
                 "gmres_its": list(self.gmres_its), "converged": bool(self.converged),
                 "rel_res": list(self.rel_res), "mass": self.mass, "energy": self.energy,
-                "t_ms": self.t_ms}
+                "t_ms": self.t_ms, "singular_blocks": self.singular_blocks}
 
 
 class chns_request_info(C.Structure):

@@ -169,6 +169,7 @@ struct chns_mesh {
   float* d_inc_w = nullptr;
   int64_t *d_touch_off = nullptr, *d_ntouch_off = nullptr, *d_ntouch_slot = nullptr;
   int32_t* d_touch_node = nullptr;
+  int32_t *d_cmap = nullptr, *d_hmap = nullptr;  // corner map of the plan
   double* d_partial = nullptr;  // target slots x 4 (FP64), or x 8 FP32 values
   double* d_tbuf = nullptr;     // element touches x 16, allocated on first diagonal
   int64_t n_chunks = 0;
@@ -226,6 +227,8 @@ dev::PlanView plan_view(const chns_mesh* m) {
   v.ntouch_off = m->d_ntouch_off;
   v.ntouch_slot = m->d_ntouch_slot;
   v.bflags = m->d_bflags;
+  v.cmap = m->d_cmap;
+  v.hmap = m->d_hmap;
   return v;
 }
 
@@ -322,6 +325,7 @@ int upload(chns_mesh* m, hipStream_t s) {
       (rc = dalloc(&m->d_ntouch_off, P.ntouch_off.size(), &B)) ||
       (rc = dalloc(&m->d_ntouch_slot, P.ntouch_slot.size(), &B)) ||
       (rc = dalloc(&m->d_bflags, h.bflags.size(), &B)) ||
+      (rc = dalloc(&m->d_cmap, P.cmap.size(), &B)) || (rc = dalloc(&m->d_hmap, P.hmap.size(), &B)) ||
       (rc = dalloc(&m->d_partial, P.tgt.size() * 4, &B)))
     return rc;
   HIPCHK(hipHostMalloc((void**)&m->h_flag, sizeof(int)));
@@ -336,7 +340,8 @@ int upload(chns_mesh* m, hipStream_t s) {
       (rc = h2d(m->d_node_slot, P.node_slot, s)) || (rc = h2d(m->d_touch_off, P.touch_off, s)) ||
       (rc = h2d(m->d_touch_node, P.touch_node, s)) ||
       (rc = h2d(m->d_ntouch_off, P.ntouch_off, s)) ||
-      (rc = h2d(m->d_ntouch_slot, P.ntouch_slot, s)) || (rc = h2d(m->d_bflags, h.bflags, s)))
+      (rc = h2d(m->d_ntouch_slot, P.ntouch_slot, s)) || (rc = h2d(m->d_bflags, h.bflags, s)) ||
+      (rc = h2d(m->d_cmap, P.cmap, s)) || (rc = h2d(m->d_hmap, P.hmap, s)))
     return rc;
   m->n_chunks = (int64_t)P.tgt_off.size() - 1;
   if (dev::ChunkLDS<double, 6, 4, 4>::bytes(caps(m)) > 65536)
@@ -706,6 +711,7 @@ struct Solver {
       : m(m_), pv(pv_), o(o_), s(s_), w(m_->ws), n((int64_t)m_->h.node_key.size()) {}
 
   bool cancelled() const { return cancel && cancel->load(std::memory_order_relaxed); }
+  int singular = 0;  // Newton iterations of this step with a singular diagonal block
 
   int ensure_workspace() {
     std::lock_guard<std::mutex> lk(g_struct_mu);
@@ -1127,6 +1133,8 @@ struct Solver {
                            n, o.precond == 0 ? 1 : 0, w.flag);
       HIPCHK(hipGetLastError());
       if (o.precond == 2 && (rc = mg_setup(block, U, w.Uk))) return rc;
+      // the singular-block flag of these inversions, read after the next sync
+      HIPCHK(hipMemcpyAsync(w.hflag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
       int its = 0;
       if (o.precision == 0) {
         hipLaunchKernelGGL((dev::k_scale<double, double>), dim3(grid_stride(N)), dim3(256), 0, s, w.b64,
@@ -1147,7 +1155,8 @@ struct Solver {
       *gits += its;
       hipLaunchKernelGGL(dev::k_add_block<double>, dim3(grid_stride(N)), dim3(256), 0, s, U, w.x, n, f0, nf, 1.0);
       ++*nits;
-      if ((rc = residual_norm(block, U, &rn))) return rc;
+      if ((rc = residual_norm(block, U, &rn))) return rc;  // synchronises the stream
+      if (*w.hflag & 2) ++singular;
     }
     *relres = r0 > 0 ? rn / r0 : 0.0;
     return CHNS_OK;
@@ -1181,6 +1190,7 @@ struct Solver {
       HIPCHK(hipGetLastError());
       if (o.precond == 2 && ((rc = mg_setup(CHNS_BLOCK_CH, U, w.Uk)) || (rc = mg_setup(CHNS_BLOCK_NS, U, w.Uk))))
         return rc;
+      HIPCHK(hipMemcpyAsync(w.hflag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
       int its = 0;
       if (o.precision == 0) {
         hipLaunchKernelGGL((dev::k_scale<double, double>), dim3(grid_stride(N)), dim3(256), 0, s, w.b64, w.r,
@@ -1205,7 +1215,8 @@ struct Solver {
       *gits += its;
       hipLaunchKernelGGL(dev::k_add_block<double>, dim3(grid_stride(N)), dim3(256), 0, s, U, w.x, n, 0, 6, 1.0);
       ++*nits;
-      if ((rc = residual_norm(kCoupled, U, &rn))) return rc;
+      if ((rc = residual_norm(kCoupled, U, &rn))) return rc;  // synchronises the stream
+      if (*w.hflag & 2) ++singular;
     }
     *relres = r0 > 0 ? rn / r0 : 0.0;
     return CHNS_OK;
@@ -1227,6 +1238,7 @@ struct Solver {
   int step(double* Uout, chns_step_stats* st) {
     int rc = ensure_workspace();
     if (rc) return rc;
+    singular = 0;
     if (o.precond == 2 && (rc = build_mg(m, o.mg_levels, s))) return rc;
     double* U = w.U1;
     HIPCHK(hipMemcpyAsync(U, Uout, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
@@ -1276,6 +1288,7 @@ struct Solver {
     HIPCHK(hipMemcpyAsync(Uout, U, sizeof(double) * n * 6, hipMemcpyDeviceToDevice, s));
     if ((rc = launch_diagnostics(m, pv, U, &st->mass, &st->energy, s))) return rc;
     st->converged = (all_conv && block_conv) ? 1 : 0;
+    st->singular_blocks = singular;
     return st->converged ? CHNS_OK : CHNS_NOT_CONVERGED;
   }
 };
@@ -1581,7 +1594,7 @@ void free_mesh_locked(chns_mesh* m) {
                   m->d_tgt_off, m->d_tgt, m->d_inc_off, m->d_chunk_inc, m->d_node_off, m->d_node_slot,
                   m->d_inc_corner,
                   m->d_bflags, m->d_inc_w, m->d_touch_off, m->d_touch_node, m->d_ntouch_off, m->d_ntouch_slot,
-                  m->d_partial, m->d_tbuf, m->d_lin[0][0], m->d_lin[0][1], m->d_lin[1][0], m->d_lin[1][1],
+                  m->d_partial, m->d_tbuf, m->d_cmap, m->d_hmap, m->d_lin[0][0], m->d_lin[0][1], m->d_lin[1][0], m->d_lin[1][1],
                   m->d_mid[0], m->d_mid[1]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);

@@ -185,7 +185,10 @@ struct PlanView {
   const int64_t* ntouch_off;  // per node
   const int64_t* ntouch_slot;
   const uint8_t* bflags;      // per node
+  const int32_t* cmap;        // per element corner: target-list position, or -1 - hanging entry
+  const int32_t* hmap;        // per hanging entry: kHMapDev ints (row start, count, 16-bit positions)
 };
+constexpr int kHMapDev = 8;
 
 // Physical parameters in kernel form.
 struct PhysView {

@@ -70,7 +70,14 @@ std::string build_host_mesh(const chns_mesh_spec& spec, HostMesh& out);
 // direct corners in corner order, then the parents of its hanging corners in
 // corner and constraint order, first occurrence only): touch_off[e] ..
 // touch_off[e+1]; node n sums touch_slot[ntouch_off[n] .. ntouch_off[n+1]).
+// Corner map (for kernels that read a corner's record from the staged chunk
+// without searching the target list): cmap[e*8 + k] is the position of
+// corner k's node in its chunk's target list, or -1 - j for a hanging corner
+// whose entry j in hmap holds kHMap ints: the first index t0 of its
+// constraint row, the parent count, then the parents' target-list positions
+// (16 bits each, two per int, constraint-row order, -1 when unused).
 constexpr int kChunk = 32;
+constexpr int kHMap = 8;   // ints per hanging-corner entry (8 parents at most)
 struct ScatterPlan {
   std::vector<int32_t> tgt_off, tgt, inc_off;
   std::vector<int32_t> chunk_inc;  // per chunk: inc_off at its first target
@@ -80,6 +87,7 @@ struct ScatterPlan {
   std::vector<int64_t> touch_off;
   std::vector<int32_t> touch_node;  // per element touch: the node
   std::vector<int64_t> ntouch_off, ntouch_slot;
+  std::vector<int32_t> cmap, hmap;
   int max_targets = 0;  // targets of the largest chunk
   int max_inc = 0;      // incidences of the largest chunk
   int max_touch = 0;

@@ -453,9 +453,11 @@ __device__ __forceinline__ void ns_jvp_point(const PhysView& p, const Lane<T>& L
                                              const T (&ddv)[3], const VG<T>& dpt, T (&r)[4]) {
   T c[4], F[4][3];
   ns_jvp_coef<T>(p, P, dvt, ddv, dpt, c, F);
+  // the contraction is linear and wdet = h^3/8 is a power of two, so scaling
+  // its result instead of its 16 inputs gives the same bits
   const T w = L.wdet;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) r[i] = test_contract<T>(w * c[i], w * F[i][0], w * F[i][1], w * F[i][2], L);
+  for (int i = 0; i < 4; ++i) r[i] = w * test_contract<T>(c[i], F[i][0], F[i][1], F[i][2], L);
 }
 
 template <class T>
@@ -651,31 +653,29 @@ __global__ __launch_bounds__(256) void k_ch_lin(MeshView m, PlanView pl, PhysVie
 // of the chunk, the ND-field direction followed by NM cached nodal values
 // (mid[node * NM + f]), and the chunk's lists; loads the lane's NL cached
 // values and returns the lane's corner record, ND + NM values (after the
-// barrier).  Vector memory counters retire in the order the loads were
-// issued, so they are issued in the order they are needed: (1) the chunk's
-// target and incidence lists and the lane's hanging-node record, (2) the
-// cached values, which carry most of the bytes, (3) what depends on (1): the
-// targets' records and the parents of a hanging corner.  The LDS stores
-// of (1) and (3) wait only for their own loads and (2) streams meanwhile.  The
-// fixed per-thread counts cover chunks of up to 128 targets and 512
-// incidences and hanging nodes of up to 4 parents; loops take anything
-// beyond.
+// barrier).  The corner's record is found through the plan's corner map
+// (cw = cmap[element * 8 + corner]): its position in the staged target list,
+// or for a hanging corner the positions of its constraint parents, so no
+// search of the target list is needed.  Vector memory counters retire in the
+// order the loads were issued, so they are issued in the order they are
+// needed: (1) the chunk's target and incidence lists and the lane's
+// hanging-corner entry, (2) the cached values, which carry most of the bytes,
+// (3) what depends on (1): the targets' records and the constraint weights of
+// a hanging corner.  The LDS stores of (1) and (3) wait only for their own
+// loads and (2) streams meanwhile.  The fixed per-thread counts cover chunks
+// of up to 128 targets and 512 incidences; loops take anything beyond.
 template <class T, class TD, int ND, int NM, int NL>
 __device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND + NM, ND>& S, const MeshView& m,
-                                             const PlanView& pl, int ch, int ref, const T* __restrict__ lin,
+                                             const PlanView& pl, int ch, int cw, const T* __restrict__ lin,
                                              const T* __restrict__ mid, const TD* __restrict__ dU, int ldD,
                                              int offD, T (&q)[NL], T (&c)[ND + NM]) {
   constexpr int NV = ND + NM;
   constexpr int SV = ChunkLDS<T, 0, NV, ND>::SV, KI = 2, KH = 4;
-  constexpr int KD = (128 * NV + kChunkThreads - 1) / kChunkThreads;
-  // value f of target j: the direction (f < ND), then the nodal values
-  auto rec = [&](int64_t g, int f) -> T {
-    if constexpr (NM == 0) {
-      return (T)dU[g * ldD + offD + f];
-    } else {
-      return f < ND ? (T)dU[g * ldD + offD + f] : mid[g * NM + f - ND];
-    }
-  };
+  // the direction and the nodal values are staged by separate passes over
+  // (target, field) pairs, so that the lanes of a wave load from one array
+  constexpr int KD = (128 * ND + kChunkThreads - 1) / kChunkThreads;
+  constexpr int KM = NM > 0 ? (128 * NM + kChunkThreads - 1) / kChunkThreads : 0;
+  static_assert(kChunkThreads % ND == 0 && (NM == 0 || kChunkThreads % NM == 0), "field counts");
   const int t = threadIdx.x;
   const int s0 = pl.tgt_off[ch], cnt = pl.tgt_off[ch + 1] - s0;
   const int i0 = pl.chunk_inc[ch], ni = pl.chunk_inc[ch + 1] - i0;
@@ -684,20 +684,25 @@ __device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND + NM, ND>& S, con
   // (1) lists; indices past the end are clamped and their values dropped
   const int tg = pl.tgt[s0 + min(t, cnt - 1)];
   const int io = pl.inc_off[s0 + min(t, cnt)];
-  int gd[KD], icv[KI];
+  int gd[KD], gm[KM > 0 ? KM : 1], icv[KI];
   float iwv[KI];
 #pragma unroll
-  for (int k = 0; k < KD; ++k) gd[k] = pl.tgt[s0 + min((t + k * kChunkThreads) / NV, cnt - 1)];
+  for (int k = 0; k < KD; ++k) gd[k] = pl.tgt[s0 + min((t + k * kChunkThreads) / ND, cnt - 1)];
+  if constexpr (KM > 0) {
+#pragma unroll
+    for (int k = 0; k < KM; ++k) gm[k] = pl.tgt[s0 + min((t + k * kChunkThreads) / NM, cnt - 1)];
+  }
 #pragma unroll
   for (int k = 0; k < KI; ++k) {
     const int i = i0 + min(t + k * kChunkThreads, ni - 1);
     iwv[k] = pl.inc_w[i];
     icv[k] = pl.inc_corner[i];
   }
-  int h0 = 0, h1 = 0;
-  if (ref < 0) {
-    h0 = m.hoff[-1 - ref];
-    h1 = m.hoff[-ref];
+  int4 he0 = {0, 0, -1, -1}, he1 = {-1, -1, 0, 0};  // hanging entry: row start, count, positions
+  if (cw < 0) {
+    const int4* he = reinterpret_cast<const int4*>(pl.hmap + (int64_t)(-1 - cw) * kHMapDev);
+    he0 = he[0];
+    he1 = he[1];
   }
   __builtin_amdgcn_sched_barrier(0);
   // (2)
@@ -706,19 +711,19 @@ __device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND + NM, ND>& S, con
   for (int k = 0; k < NL; ++k) q[k] = ql[k * kChunkThreads];
   __builtin_amdgcn_sched_barrier(0);
   // (3)
-  T dv[KD];
+  T dv[KD], mv[KM > 0 ? KM : 1];
 #pragma unroll
-  for (int k = 0; k < KD; ++k) dv[k] = rec(gd[k], (t + k * kChunkThreads) % NV);
-  int hid[KH];
+  for (int k = 0; k < KD; ++k) dv[k] = (T)dU[(int64_t)gd[k] * ldD + offD + t % ND];
+  if constexpr (KM > 0) {
+#pragma unroll
+    for (int k = 0; k < KM; ++k) mv[k] = mid[(int64_t)gm[k] * NM + t % NM];
+  }
+  const int h0 = he0.x, h1 = he0.x + he0.y;
   T hwt[KH];
-  if (ref < 0) {
+  if (cw < 0) {
     const auto* w = weights<T>(m);
 #pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const int j = min(h0 + k, h1 - 1);
-      hid[k] = m.hids[j];
-      hwt[k] = w[j];
-    }
+    for (int k = 0; k < KH; ++k) hwt[k] = w[min(h0 + k, h1 - 1)];
   }
   if (t < cnt) S.tgt[t] = tg;
   if (t <= cnt) S.ioff[t] = io - i0;
@@ -731,7 +736,14 @@ __device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND + NM, ND>& S, con
 #pragma unroll
   for (int k = 0; k < KD; ++k) {
     const int i = t + k * kChunkThreads;
-    if (i < cnt * NV) S.val[(i / NV) * SV + i % NV] = dv[k];
+    if (i < cnt * ND) S.val[(i / ND) * SV + i % ND] = dv[k];
+  }
+  if constexpr (KM > 0) {
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      const int i = t + k * kChunkThreads;
+      if (i < cnt * NM) S.val[(i / NM) * SV + ND + i % NM] = mv[k];
+    }
   }
   // chunks beyond the fixed counts
   for (int i = t + kChunkThreads; i <= cnt; i += kChunkThreads) {
@@ -742,30 +754,39 @@ __device__ __forceinline__ void lin_prologue(ChunkLDS<T, 0, ND + NM, ND>& S, con
     S.iw[i] = pl.inc_w[i0 + i];
     S.icor[i] = pl.inc_corner[i0 + i];
   }
-  for (int i = t + KD * kChunkThreads; i < cnt * NV; i += kChunkThreads)
-    S.val[(i / NV) * SV + i % NV] = rec(pl.tgt[s0 + i / NV], i % NV);
+  for (int i = t + KD * kChunkThreads; i < cnt * ND; i += kChunkThreads)
+    S.val[(i / ND) * SV + i % ND] = (T)dU[(int64_t)pl.tgt[s0 + i / ND] * ldD + offD + i % ND];
+  if constexpr (KM > 0) {
+    for (int i = t + KM * kChunkThreads; i < cnt * NM; i += kChunkThreads)
+      S.val[(i / NM) * SV + ND + i % NM] = mid[(int64_t)pl.tgt[s0 + i / NM] * NM + i % NM];
+  }
   __syncthreads();
-  // the lane's corner: its node, or its constraint's parents in list order
-  if (ref >= 0) {
-    const T* v = S.val + S.find(ref) * SV;
+  // the lane's corner: its node, or its constraint's parents in row order
+  if (cw >= 0) {
+    const T* v = S.val + cw * SV;
 #pragma unroll
     for (int f = 0; f < NV; ++f) c[f] = v[f];
   } else {
+    const int pk[8] = {he0.z & 0xFFFF, (int)((unsigned)he0.z >> 16), he0.w & 0xFFFF, (int)((unsigned)he0.w >> 16),
+                       he1.x & 0xFFFF, (int)((unsigned)he1.x >> 16), he1.y & 0xFFFF, (int)((unsigned)he1.y >> 16)};
 #pragma unroll
     for (int f = 0; f < NV; ++f) c[f] = (T)0;
 #pragma unroll
     for (int k = 0; k < KH; ++k)
       if (h0 + k < h1) {
-        const T* v = S.val + S.find(hid[k]) * SV;
+        const T* v = S.val + pk[k] * SV;
 #pragma unroll
         for (int f = 0; f < NV; ++f) c[f] += hwt[k] * v[f];
       }
     const auto* w = weights<T>(m);
-    for (int j = h0 + KH; j < h1; ++j) {
-      const T* v = S.val + S.find(m.hids[j]) * SV;
 #pragma unroll
-      for (int f = 0; f < NV; ++f) c[f] += w[j] * v[f];
-    }
+    for (int k = KH; k < 8; ++k)
+      if (h0 + k < h1) {
+        const T wk = w[h0 + k];
+        const T* v = S.val + pk[k] * SV;
+#pragma unroll
+        for (int f = 0; f < NV; ++f) c[f] += wk * v[f];
+      }
   }
 }
 
@@ -783,9 +804,9 @@ __global__ __launch_bounds__(256) void k_ns_jvp_lin(MeshView m, PlanView pl, Phy
   const int64_t e = e0 < m.E ? e0 : m.E - 1;
   Lane<T> L;
   L.init(threadIdx.x & 7, m.level[e]);
-  const int ref = m.elem[e * 8 + L.c];
+  const int cw = pl.cmap[e * 8 + L.c];
   T q[kNSLin], c[4 + kNSMid];  // direction dv, dp, then the midpoints u~, v~, w~, mu~
-  lin_prologue<T, TD, 4, kNSMid, kNSLin>(S, m, pl, blockIdx.x, ref, lin, mid, dU, ldD, offD, q, c);
+  lin_prologue<T, TD, 4, kNSMid, kNSLin>(S, m, pl, blockIdx.x, cw, lin, mid, dU, ldD, offD, q, c);
   NSPoint<T> P;
   const T cm[kNSMid] = {c[4], c[5], c[6], c[7]};
   ns_lin_unpack<T>(p, q, cm, L, P);
@@ -820,9 +841,9 @@ __global__ __launch_bounds__(256) void k_ch_jvp_lin(MeshView m, PlanView pl, Phy
   const int64_t e = e0 < m.E ? e0 : m.E - 1;
   Lane<T> L;
   L.init(threadIdx.x & 7, m.level[e]);
-  const int ref = m.elem[e * 8 + L.c];
+  const int cw = pl.cmap[e * 8 + L.c];
   T q[kCHLin], c[2];
-  lin_prologue<T, TD, 2, 0, kCHLin>(S, m, pl, blockIdx.x, ref, lin, (const T*)nullptr, dU, ldD, offD, q, c);
+  lin_prologue<T, TD, 2, 0, kCHLin>(S, m, pl, blockIdx.x, cw, lin, (const T*)nullptr, dU, ldD, offD, q, c);
   const VG<T> dp = eval_vg<T>(c[0], L);
   const VG<T> dm = eval_vg<T>(c[1], L);
   T r[2];

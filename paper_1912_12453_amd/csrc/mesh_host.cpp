@@ -434,6 +434,31 @@ std::string build_scatter_plan(const HostMesh& m, ScatterPlan& P) {
     }
     if (!tmp.empty()) P.inc_off.push_back((int32_t)P.inc_corner.size());
     P.tgt_off[c + 1] = P.tgt_off[c] + ntg;
+    // corner map: positions in this chunk's (sorted) target list
+    const int32_t* tb = P.tgt.data() + P.tgt_off[c];
+    auto pos = [&](int32_t node) {
+      return (int32_t)(std::lower_bound(tb, tb + ntg, node) - tb);
+    };
+    for (int64_t e = e0; e < e1; ++e)
+      for (int k = 0; k < 8; ++k) {
+        const int32_t r = m.elem[e * 8 + k];
+        if (r >= 0) {
+          P.cmap.push_back(pos(r));
+          continue;
+        }
+        const int32_t h = -1 - r, t0 = m.hang_off[h], np = m.hang_off[h + 1] - t0;
+        if (np > 8) return "hanging-node fan-in above 8 is not supported";
+        const int64_t j = (int64_t)P.hmap.size() / kHMap;
+        if (j >= INT32_MAX) return "scatter plan too large";
+        P.cmap.push_back((int32_t)(-1 - j));
+        int32_t ent[kHMap] = {t0, np, -1, -1, -1, -1, 0, 0};
+        for (int q = 0; q < np; ++q) {
+          const uint32_t v = (uint32_t)(uint16_t)pos(m.hang_ids[t0 + q]);
+          uint32_t& w = reinterpret_cast<uint32_t&>(ent[2 + q / 2]);
+          w = (q & 1) ? ((w & 0xFFFFu) | (v << 16)) : ((w & 0xFFFF0000u) | v);
+        }
+        P.hmap.insert(P.hmap.end(), ent, ent + kHMap);
+      }
     P.max_targets = std::max(P.max_targets, ntg);
     P.max_inc = std::max(P.max_inc, (int)tmp.size());
     if ((int64_t)P.inc_corner.size() > INT32_MAX) return "scatter plan too large";

@@ -34,7 +34,8 @@ int64_t mesh_footprint(const chns_mesh* m) {
          sz(P.inc_w.size(), 4) +
          sz(P.node_off.size(), 4) + sz(P.node_slot.size(), 4) + sz(P.touch_off.size(), 8) + sz(P.touch_node.size(), 4) +
          sz(P.ntouch_off.size(), 8) + sz(P.ntouch_slot.size(), 8) + sz(h.bflags.size(), 1) +
-         sz(P.tgt.size() * 4, 8) + sz(P.ntouch_slot.size() * 16, 8);
+         sz(P.tgt.size() * 4, 8) + sz(P.ntouch_slot.size() * 16, 8) + sz(P.cmap.size(), 4) +
+         sz(P.hmap.size(), 4);
 }
 
 // Device bytes of the cached linearisation points of a mesh, both blocks, and

@@ -54,6 +54,7 @@ def run_stream(server, requests, time_scale=1.0, log=None, max_wall_s=None):
     dof_steps = 0
     conv = 0
     nsteps = 0
+    missed = []  # steps that ended above the Newton tolerance, per request
     for r in pending:
         if r.rid not in tickets:
             continue
@@ -69,6 +70,10 @@ def run_stream(server, requests, time_scale=1.0, log=None, max_wall_s=None):
         dof_steps += 6 * int(info.n_nodes) * int(info.steps_done)
         conv += sum(1 for s in stats if s.converged)
         nsteps += len(stats)
+        for k, s in enumerate(stats):
+            if not s.converged:
+                missed.append({"rid": r.rid, "step": k, "rel_res": [float(s.rel_res[0]), float(s.rel_res[1])],
+                               "newton_its": list(s.newton_its), "gmres_its": list(s.gmres_its)})
     sst = server.stats().as_dict()
     summary = {"requests": len(pending), "done": sst["done"], "failed": sst["failed"],
                "unfinished": len(pending) - sst["done"] - sst["failed"],
@@ -77,5 +82,7 @@ def run_stream(server, requests, time_scale=1.0, log=None, max_wall_s=None):
                "dof_steps_per_s": round(dof_steps / wall, 1),
                "p50_step_ms": round(float(np.percentile(lat, 50)), 3) if lat else None,
                "p99_step_ms": round(float(np.percentile(lat, 99)), 3) if lat else None,
-               "converged_step_fraction": round(conv / nsteps, 4) if nsteps else None}
+               "converged_step_fraction": round(conv / nsteps, 4) if nsteps else None,
+               "requests_all_steps_converged": sum(1 for p in per if all(p["converged"])),
+               "unconverged_steps": missed}
     return summary, per

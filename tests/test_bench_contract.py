@@ -27,8 +27,8 @@ def test_more_than_one_gpu_exits_with_a_message():
 def test_flops_per_element_match_the_committed_counters():
     b = load_bench()
     t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["kernels"]
-    e64 = t["k_ns_jvp_lin<double,double>"]["bubble_l9"]
-    e32 = t["k_ns_jvp_lin<float,float>"]["bubble_l9"]
+    e64 = t["k_ns_jvp_lin<double,double>"]["rt_l10"]
+    e32 = t["k_ns_jvp_lin<float,float>"]["rt_l10"]
     assert round(e64["f64_flops_per_launch"] / e64["leaves"]) == b.NS_JVP_FLOPS_PER_ELEMENT["fp64"]
     assert round(e32["f32_flops_per_launch"] / e32["leaves"]) == b.NS_JVP_FLOPS_PER_ELEMENT["mixed"]
     lin = t["k_ns_lin<double,double>"]["bubble_l9"]

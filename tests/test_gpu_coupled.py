@@ -25,6 +25,8 @@ def chns():
     return c
 
 
+from tests.tolerances import step_tol  # noqa: E402
+
 def drop(chns, level):
     w = W.drop16(level=level)
     pm = chns.Mesh.from_spec(w.mesh)
@@ -58,12 +60,12 @@ def test_coupled_step_matches_block_iteration(torch, chns, orc, precision, preco
     assert st.rel_res[0] <= 1e-6 and st.rel_res[1] <= 1e-6
     e = field_err(res[1][0], res[0][0])
     print("coupled vs block", ["%.1e" % v for v in e], flush=True)
-    assert max(e[0], e[2], e[3], e[4]) < 1e-5
+    assert max(e[0], e[2], e[3], e[4]) < step_tol(precision)
     Uo, _ = orc.Mesh(w.mesh.trees, w.mesh.level_min, w.mesh.level_max).step(
         orc.Params.make(**vars(w.physics)), orc.SolverOpts.make(), U)
     eo = field_err(res[1][0], Uo)
     print("coupled vs oracle", ["%.1e" % v for v in eo], flush=True)
-    assert max(eo[0], eo[2], eo[3], eo[4]) < 1e-5
+    assert max(eo[0], eo[2], eo[3], eo[4]) < step_tol(precision)
     m0, e0 = pm.diagnostics(p, torch.tensor(U, device="cuda:0"))
     assert abs(st.mass - m0) < 1e-12 and st.energy < e0
 

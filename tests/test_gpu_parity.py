@@ -2,7 +2,8 @@
 
 FP64 residuals, JVPs and node-block diagonals must agree with the oracle to
 1e-12 relative (2-norm over the block's rows, and entry-wise against the
-largest entry); FP32 JVPs are compared at 1e-4 and their error is printed.
+largest entry); FP32 JVPs at 100 FP32 unit roundoffs (6e-6, the ~100 terms
+summed into a row), their error printed.
 Meshes span several workgroups with a ragged tail, the single-leaf and
 all-boundary degenerate cases, multi-tree bricks and every hanging-node case
 of random 2:1 trees."""
@@ -10,11 +11,14 @@ import numpy as np
 import pytest
 
 from paper_1912_12453_amd import workloads as W
+from tests.fp32_bound import FLOOR as FP32_FLOOR
+from tests.fp32_bound import compare_fp32_coupled
 
 pytestmark = pytest.mark.gpu
 
 CH, NS = 0, 1
 TOL = 1e-12
+TOL32 = FP32_FLOOR  # 100 FP32 unit roundoffs: the ~100 terms summed into a row
 
 
 @pytest.fixture(scope="module")
@@ -110,7 +114,7 @@ def test_jvp_parity(torch, chns, orc, kind, block):
     compare(J64, ref, fs, label=f"jvp64 {kind} {block}")
     J32 = pm.jvp(p, block, d1, d0, to_dev(torch, dU, torch.float32), prec=chns.CHNS_F32)
     J32 = J32.cpu().numpy().astype(np.float64)
-    e32 = compare(J32, ref, fs, tol=1e-4, label=f"jvp32 {kind} {block}")
+    e32 = compare(J32, ref, fs, tol=TOL32, label=f"jvp32 {kind} {block}")
     assert e32 > 0
 
 
@@ -118,7 +122,8 @@ def test_jvp_parity(torch, chns, orc, kind, block):
 def test_coupled_jacobian_rows(torch, chns, orc, kind):
     """chns_jvp_full (dual-number differentiation of both residual kernels)
     against the oracle's rows of the coupled Jacobian: FP64 to 1e-12, FP32 to
-    1e-4; its cross part is not negligible."""
+    the FP32 bound away from the pull-back kink of phi; its cross part is not
+    negligible."""
     pm, om = mesh_pair(chns, orc, kind)
     print(f"case jvp_full {kind} E={pm.n_leaves}", flush=True)
     ph = W.moderate_physics()
@@ -134,8 +139,7 @@ def test_coupled_jacobian_rows(torch, chns, orc, kind):
     compare(J, ref, slice(0, 2), label=f"jvp_full64 CH rows {kind}")
     compare(J, ref, slice(2, 6), label=f"jvp_full64 NS rows {kind}")
     J32 = pm.jvp_full(p, d1, d0, to_dev(torch, dU, torch.float32), prec=chns.CHNS_F32)
-    J32 = J32.cpu().numpy().astype(np.float64)
-    compare(J32, ref, slice(0, 6), tol=1e-4, label=f"jvp_full32 {kind}")
+    compare_fp32_coupled(om, U1, J32.cpu().numpy(), ref, TOL32, f"jvp_full32 {kind}")
     blockwise = np.zeros_like(U1)
     for b, f in ((CH, slice(0, 2)), (NS, slice(2, 6))):
         blockwise[:, f] = om.jvp(po, b, U1, U0, dU)[:, f]
@@ -169,8 +173,8 @@ def test_cached_linearisation_jvp(torch, chns, orc, kind):
         pm.linearize(p, blk, d1, d0, prec=chns.CHNS_F32)
         J32 = pm.jvp_lin(p, blk, ddU32, prec=chns.CHNS_F32).cpu().numpy().astype(np.float64)
         compare(J32, pm.jvp(p, blk, d1, d0, ddU32, prec=chns.CHNS_F32).cpu().numpy().astype(np.float64),
-                f, tol=1e-5, label=f"{name} jvp_lin32 vs jvp32 {kind}")
-        compare(J32, ref, f, tol=1e-4, label=f"{name} jvp_lin32 {kind}")
+                f, tol=TOL32, label=f"{name} jvp_lin32 vs jvp32 {kind}")
+        compare(J32, ref, f, tol=TOL32, label=f"{name} jvp_lin32 {kind}")
     # a new linearisation point replaces the cache of its block only
     U1b, U0b = W.random_state(pm.n_nodes, 211)
     pm.linearize(p, NS, to_dev(torch, U1b), to_dev(torch, U0b))

@@ -673,3 +673,19 @@ def test_energy_linear_phase_field(orc):
     free = _psi_integral_gauss(a, s, h) + 0.5 * p.Cn ** 2 * s ** 2
     expect = 0.5 * (v @ v) * int_rho + free / (p.Cn * p.We) + int_rho_y / p.Fr
     assert E == pytest.approx(expect, rel=1e-13)
+
+
+def test_gauss_point_helper_reproduces_trilinear_fields(orc, adaptive):
+    """tests/gauss_points.py (which locates the phi pull-back kink for the FP32
+    comparisons) evaluates a field that is trilinear on the whole domain
+    exactly at the oracle's Gauss points, hanging corners included."""
+    from tests import gauss_points as GP
+    m = adaptive
+    x = m.node_xyz()
+    f = lambda P: 0.3 + P[..., 0] - 2 * P[..., 1] + 0.5 * P[..., 2] + 1.5 * P[..., 0] * P[..., 1] * P[..., 2]
+    got = GP.gauss_values(m, f(x))
+    np.testing.assert_allclose(got, f(m.qp_coords()), rtol=1e-13, atol=1e-14)
+    U = np.zeros((m.n_nodes, 6))
+    U[:, 0] = 1.0
+    el, rows = GP.near_pullback(m, U, 1e-6)
+    assert el.all() and rows.size == m.n_nodes
