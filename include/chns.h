@@ -154,6 +154,19 @@ int chns_residual(chns_mesh* mesh, const chns_params* params, int block, const d
 int chns_jvp(chns_mesh* mesh, const chns_params* params, int block, const double* U_new,
              const double* U_old, const void* dU, void* JdU, int prec, void* stream);
 
+/* chns_jvp for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, kernels and results (bit for bit) as chns_jvp, but the
+ * per-target partial rows live in a static 64 MiB device array of the
+ * library (one per GPU, held until the process ends) instead of the mesh's
+ * own buffer, and nothing is allocated: the mesh must already be on the
+ * current device (chns_mesh_upload or any earlier device call), else
+ * CHNS_EINVAL.  Meshes whose partial rows (4 doubles per chunk target, about
+ * 2.5 targets per leaf) exceed 64 MiB are rejected with CHNS_EINVAL; use
+ * chns_jvp for them.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (different streams or threads) race; serialise them. */
+int chns_jvp_noalloc(chns_mesh* mesh, const chns_params* params, int block, const double* U_new,
+                     const double* U_old, const void* dU, void* JdU, int prec, void* stream);
 
 /* Rows of the coupled Jacobian (both blocks, derivatives with respect to all
  * six fields of U^{k+1}, the cross terms d R_NS / d(phi, mu) and

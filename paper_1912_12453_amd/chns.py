@@ -127,6 +127,7 @@ def lib():
         L.chns_mesh_free.argtypes = [vp]
         L.chns_residual.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp]
         L.chns_jvp.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp, C.c_int, vp]
+        L.chns_jvp_noalloc.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp, C.c_int, vp]
         L.chns_jvp_full.argtypes = [vp, C.POINTER(chns_params), vp, vp, vp, vp, C.c_int, vp]
         L.chns_linearize.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, C.c_int, vp]
         L.chns_jvp_lin.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, C.c_int, vp]
@@ -210,6 +211,14 @@ def chns_jvp(mesh, params, block, U_new, U_old, dU, JdU, prec=CHNS_F64, stream=N
     _dev(U_new, "float64"), _dev(U_old, "float64"), _dev(dU, dt), _dev(JdU, dt)
     return _check(lib().chns_jvp(mesh, C.byref(params), block, U_new.data_ptr(), U_old.data_ptr(),
                                  dU.data_ptr(), JdU.data_ptr(), prec, _stream(stream)))
+
+
+def chns_jvp_noalloc(mesh, params, block, U_new, U_old, dU, JdU, prec=CHNS_F64, stream=None):
+    dt = "float64" if prec == CHNS_F64 else "float32"
+    _dev(U_new, "float64"), _dev(U_old, "float64"), _dev(dU, dt), _dev(JdU, dt)
+    return _check(lib().chns_jvp_noalloc(mesh, C.byref(params), block, U_new.data_ptr(),
+                                         U_old.data_ptr(), dU.data_ptr(), JdU.data_ptr(), prec,
+                                         _stream(stream)))
 
 
 def chns_jvp_full(mesh, params, U_new, U_old, dU, JdU, prec=CHNS_F64, stream=None):

@@ -404,16 +404,18 @@ int launch_residual(chns_mesh* m, const dev::PhysView& pv, int block, const doub
 
 // T: arithmetic, TS: state storage, TD: direction and output storage (partials
 // are kept in T)
+// partials of the chunk targets: the mesh's own buffer unless `part` is given
+// (chns_jvp_noalloc passes the library's static scratch).
 template <class T, class TS, class TD>
 int launch_jvp(chns_mesh* m, const dev::PhysView& pv, int block, const TS* U1, const TS* U0,
                const TD* dU, int ldD, int offD, TD* out, int ldO, int offO, hipStream_t s,
-               const int* skip = nullptr) {
+               const int* skip = nullptr, void* part_buf = nullptr) {
   const int64_t n = (int64_t)m->h.node_key.size();
   const auto mv = view(m);
   const auto pl = plan_view(m);
   const dim3 g((unsigned)m->n_chunks), b(dev::kChunkThreads);
   const dev::ChunkCaps cc = caps(m);
-  T* part = (T*)m->d_partial;
+  T* part = (T*)(part_buf ? part_buf : (void*)m->d_partial);
   if (block == CHNS_BLOCK_CH) {
     hipLaunchKernelGGL((dev::k_ch_jvp<T, TS, TD>), g, b, (dev::ChunkLDS<T, 5, 2, 2>::bytes(cc)), s, mv, pl,
                        pv, cc, U1, U0, dU, ldD, offD, part, skip);
@@ -1570,7 +1572,33 @@ int chns_mesh_free(chns_mesh* m) {
 
 }  // extern "C"
 
+// Scratch of chns_jvp_noalloc: the per-target partial rows of one JVP.  Each
+// GPU holds its own copy of this array for the life of the process.  In host
+// code `scratch` is only a stand-in for the symbol: the device address is
+// looked up once per device (hipGetSymbolAddress) and kept in
+// g_scratch_ptr, which is what the kernels receive.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev`, which must be current.
+int noalloc_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(CHNS_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(CHNS_EHIP, "hipGetSymbolAddress returned a null address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CHNS_OK;
+}
 
 void free_mg_locked(chns_mesh* m) {
   for (size_t l = 0; l < m->mg.size(); ++l) {
@@ -1636,6 +1664,35 @@ int chns_jvp(chns_mesh* m, const chns_params* params, int block, const double* U
     return launch_jvp<float, double, float>(m, pv, block, U_new, U_old, (const float*)dU, 6, off,
                                             (float*)JdU, 6, off, s);
   return fail(CHNS_EINVAL, "prec must be CHNS_F64 or CHNS_F32");
+}
+
+int chns_jvp_noalloc(chns_mesh* m, const chns_params* params, int block, const double* U_new,
+                     const double* U_old, const void* dU, void* JdU, int prec, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (!m) return fail(CHNS_EINVAL, "mesh is NULL");
+  if (!m->uploaded)
+    return fail(CHNS_EINVAL, "chns_jvp_noalloc needs a mesh already on the device (chns_mesh_upload)");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != m->device) return fail(CHNS_EINVAL, "mesh was uploaded to another device");
+  dev::PhysView pv;
+  int rc;
+  if ((rc = phys_view(params, pv))) return rc;
+  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "unknown block");
+  if (!U_new || !U_old || !dU || !JdU) return fail(CHNS_EINVAL, "pointers must not be NULL");
+  if (prec != CHNS_F64 && prec != CHNS_F32) return fail(CHNS_EINVAL, "prec must be CHNS_F64 or CHNS_F32");
+  const size_t need = m->plan.tgt.size() * 4 * sizeof(double);
+  if (need > kNoAllocScratchBytes)
+    return fail(CHNS_EINVAL, "mesh needs " + std::to_string(need) + " bytes of partial rows; chns_jvp_noalloc "
+                "holds at most " + std::to_string(kNoAllocScratchBytes) + " (use chns_jvp)");
+  void* part = nullptr;
+  if ((rc = noalloc_scratch(dev, &part))) return rc;
+  const int off = block == CHNS_BLOCK_CH ? 0 : 2;
+  if (prec == CHNS_F64)
+    return launch_jvp<double, double, double>(m, pv, block, U_new, U_old, (const double*)dU, 6, off,
+                                              (double*)JdU, 6, off, s, nullptr, part);
+  return launch_jvp<float, double, float>(m, pv, block, U_new, U_old, (const float*)dU, 6, off,
+                                          (float*)JdU, 6, off, s, nullptr, part);
 }
 
 int chns_jvp_full(chns_mesh* m, const chns_params* params, const double* U_new, const double* U_old,
