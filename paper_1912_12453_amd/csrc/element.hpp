@@ -31,10 +31,16 @@ constexpr int kXor2 = 0x4E;
 constexpr int kXor7 = 0x141;
 
 // Every lane of the wave is active whenever these run (all row and bank masks
-// set), so the moved value never falls back to an "old" operand.
+// set), and every source lane of these controls lies in the lane's own row,
+// so the moved value never falls back to the "old" operand or to bound_ctrl's
+// zero.  The FP32 form is written as update_dpp with bound_ctrl set because
+// then the compiler folds the move into the VOP2 that consumes it
+// (v_sub_f32_dpp, v_add_f32_dpp): one VALU instruction instead of two.  The
+// 64-bit moves stay separate (no DPP form of the FP64 arithmetic with these
+// controls).
 template <int CTRL>
 __device__ __forceinline__ float xchg(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double xchg(double v) {
