@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["orc_mesh.cpp", "orc_fem.cpp", "orc_solver.cpp", "orc_capi.cpp"]
+SOURCES = ["orc_mesh.cpp", "orc_fem.cpp", "orc_solver.cpp", "orc_q2.cpp", "orc_capi.cpp"]
 LIB = os.path.join(HERE, "liborc.so")
 
 

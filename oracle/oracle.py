@@ -87,6 +87,12 @@ def lib():
         L.orc_diagnostics.argtypes = [C.c_void_p, C.POINTER(Params), dp, dp, dp]
         L.orc_step.argtypes = [C.c_void_p, C.POINTER(Params), C.POINTER(SolverOpts), dp, dp, dp,
                                C.POINTER(StepStats)]
+        L.orc_q2_build.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
+        L.orc_q2_free.argtypes = [C.c_void_p]
+        L.orc_q2_sizes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.orc_q2_arrays.argtypes = [C.c_void_p] + [C.c_void_p] * 6
+        L.orc_q2_residual.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(Params), dp, dp, dp]
+        L.orc_q2_jvp.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(Params), dp, dp, dp, dp]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_set_num_threads.restype = None
@@ -276,3 +282,71 @@ class Mesh:
         x0 = self.leaves[:, :3].astype(np.float64) * unit
         h = 2.0 ** (-self.leaves[:, 3].astype(np.float64))
         return x0[:, None, :] + 0.5 * h[:, None, None] * (1.0 + s[None, :, :] * g)
+
+    def q2(self):
+        """The cG(2) numbering of this mesh (27-node leaves, CH block)."""
+        return MeshQ2(self)
+
+
+class MeshQ2:
+    """Triquadratic numbering on the leaves of an oracle Mesh: node a = i +
+    3j + 9k of a leaf at its anchor plus (i, j, k) half sides; coordinates in
+    doubled units 2^-(level_max+1).  Hanging lattice points take the
+    coarsest neighbouring leaf's triquadratic interpolant (Sec. 4, carried
+    over to cG(2))."""
+
+    def __init__(self, mesh):
+        L = lib()
+        self.mesh = mesh
+        h = C.c_void_p()
+        if L.orc_q2_build(mesh._h, C.byref(h)) != 0:
+            raise ValueError("oracle Q2 numbering failed: " + _err())
+        self._h = h
+        s = (C.c_int64 * 3)()
+        L.orc_q2_sizes(h, s)
+        n, nh, nc = (int(v) for v in s)
+        E = mesh.n_leaves
+        self.elem = np.zeros((E, 27), np.int32)
+        self.nodes = np.zeros((n, 3), np.int32)
+        self.hang_xyz = np.zeros((nh, 3), np.int32)
+        self.hang_off = np.zeros(nh + 1, np.int64)
+        self.hang_ids = np.zeros(nc, np.int32)
+        self.hang_w = np.zeros(nc, np.float64)
+        L.orc_q2_arrays(h, self.elem.ctypes.data, self.nodes.ctypes.data, self.hang_xyz.ctypes.data,
+                        self.hang_off.ctypes.data, self.hang_ids.ctypes.data, self.hang_w.ctypes.data)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_q2_free(h)
+            self._h = None
+
+    @property
+    def n_nodes(self):
+        return self.nodes.shape[0]
+
+    def node_xyz(self):
+        """Physical coordinates of the independent nodes."""
+        return self.nodes.astype(np.float64) * 2.0 ** (-(self.mesh.level_max + 1))
+
+    def hang_coords(self):
+        return self.hang_xyz.astype(np.float64) * 2.0 ** (-(self.mesh.level_max + 1))
+
+    def residual(self, p, Unew, Uold):
+        """CH rows (fields 0, 1) over the Q2 nodes."""
+        n = self.n_nodes
+        Unew, Uold = _state(Unew, n), _state(Uold, n)
+        R = np.zeros((n, 6))
+        if lib().orc_q2_residual(self.mesh._h, self._h, C.byref(p), _dp(Unew), _dp(Uold), _dp(R)) != 0:
+            raise RuntimeError(_err())
+        return R
+
+    def jvp(self, p, Unew, Uold, dU):
+        """CH block Jacobian (derivative in phi^{k+1}, mu^{k+1}) applied to dU."""
+        n = self.n_nodes
+        Unew, Uold, dU = _state(Unew, n), _state(Uold, n), _state(dU, n)
+        out = np.zeros((n, 6))
+        if lib().orc_q2_jvp(self.mesh._h, self._h, C.byref(p), _dp(Unew), _dp(Uold), _dp(dU),
+                            _dp(out)) != 0:
+            raise RuntimeError(_err())
+        return out

@@ -108,4 +108,26 @@ struct StepStats {
 std::string step(const Mesh& m, const Params& p, const SolverOpts& o, double* U,
                  const double* forcing, const double* bc, StepStats* st);
 
+// ------------------------------------------------------ cG(2), CH block ----
+// Triquadratic (27-node) numbering on the leaves of a Mesh.  Coordinates are
+// in doubled units 2^-(D+1), so every lattice point of every leaf is an
+// integer point.  Node a = i + 3j + 9k of a leaf sits at its anchor plus
+// (i, j, k) half sides.
+struct MeshQ2 {
+  int D = 0;
+  std::vector<std::array<int32_t, 27>> elem;     // id >= 0 node, < 0 hanging -1-h
+  std::vector<std::array<uint32_t, 3>> nodes;    // independent nodes, Morton order
+  std::vector<std::array<uint32_t, 3>> hang_xyz; // hanging nodes, Morton order
+  std::vector<int64_t> hang_off;
+  std::vector<int32_t> hang_ids;
+  std::vector<double> hang_w;
+};
+std::string build_q2(const Mesh& m, MeshQ2& out);
+// CH rows (fields 0, 1 of a node-major 6-field vector over the Q2 nodes; the
+// velocity fields enter as the frozen v~ of the block iteration).
+std::string residual_q2(const Mesh& m, const MeshQ2& q, const Params& p, const double* Unew,
+                        const double* Uold, double* R);
+std::string jvp_q2(const Mesh& m, const MeshQ2& q, const Params& p, const double* Unew,
+                   const double* Uold, const double* dU, double* JdU);
+
 }  // namespace orc

@@ -108,6 +108,56 @@ int orc_step(void* m, const orc::Params* p, const orc::SolverOpts* o, double* U,
   return e.empty() ? 0 : fail(e);
 }
 
+// cG(2) numbering of a mesh and the CH block on it
+int orc_q2_build(void* m, void** out) {
+  orc::MeshQ2* q = new orc::MeshQ2();
+  std::string e = orc::build_q2(*(orc::Mesh*)m, *q);
+  if (!e.empty()) {
+    delete q;
+    return fail(e);
+  }
+  *out = q;
+  return 0;
+}
+
+void orc_q2_free(void* q) { delete (orc::MeshQ2*)q; }
+
+// sizes: n_nodes, n_hanging, n_constraint_entries
+void orc_q2_sizes(void* qp, int64_t* s) {
+  const orc::MeshQ2& q = *(orc::MeshQ2*)qp;
+  s[0] = (int64_t)q.nodes.size();
+  s[1] = (int64_t)q.hang_xyz.size();
+  s[2] = (int64_t)q.hang_ids.size();
+}
+
+void orc_q2_arrays(void* qp, int32_t* elem27, int32_t* nodes3, int32_t* hang3, int64_t* hang_off,
+                   int32_t* hang_ids, double* hang_w) {
+  const orc::MeshQ2& q = *(orc::MeshQ2*)qp;
+  for (size_t e = 0; e < q.elem.size(); ++e)
+    for (int a = 0; a < 27; ++a) elem27[27 * e + a] = q.elem[e][a];
+  for (size_t i = 0; i < q.nodes.size(); ++i)
+    for (int d = 0; d < 3; ++d) nodes3[3 * i + d] = (int32_t)q.nodes[i][d];
+  for (size_t i = 0; i < q.hang_xyz.size(); ++i)
+    for (int d = 0; d < 3; ++d) hang3[3 * i + d] = (int32_t)q.hang_xyz[i][d];
+  for (size_t i = 0; i < q.hang_off.size(); ++i) hang_off[i] = q.hang_off[i];
+  for (size_t i = 0; i < q.hang_ids.size(); ++i) {
+    hang_ids[i] = q.hang_ids[i];
+    hang_w[i] = q.hang_w[i];
+  }
+}
+
+int orc_q2_residual(void* m, void* q, const orc::Params* p, const double* Unew, const double* Uold,
+                    double* R) {
+  std::string e = orc::residual_q2(*(orc::Mesh*)m, *(orc::MeshQ2*)q, *p, Unew, Uold, R);
+  return e.empty() ? 0 : fail(e);
+}
+
+int orc_q2_jvp(void* m, void* q, const orc::Params* p, const double* Unew, const double* Uold,
+               const double* dU, double* JdU) {
+  std::string e = orc::jvp_q2(*(orc::Mesh*)m, *(orc::MeshQ2*)q, *p, Unew, Uold, dU, JdU);
+  return e.empty() ? 0 : fail(e);
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   extern int omp_get_max_threads(void);
