@@ -238,6 +238,46 @@ def oracle_anchor(oracle, w, om, states, rows):
     return res
 
 
+def q2_run(chns, W, torch, name, reps):
+    """The cG(2) CH block (27-node leaves) on a workload's mesh: host build of
+    the numbering, then the element pass and node gather of the residual and
+    of the JVP, each timed over `reps` launches with HIP events on the launch
+    stream.  Random state and direction (seeded)."""
+    w = W.by_name(name)
+    mesh = chns.Mesh.from_spec(w.mesh)
+    mesh.upload()
+    t0 = time.time()
+    q = mesh.q2()
+    t_build = time.time() - t0
+    U1, U0 = W.random_state(q.n_nodes, 1)
+    dU = W.direction(q.n_nodes, 2)
+    d1, d0, dd = (torch.tensor(a, device="cuda:0") for a in (U1, U0, dU))
+    out = torch.empty_like(dd)
+    p = chns.make_params(w.physics)
+    res = {"workload": name, "leaves": mesh.n_leaves, "nodes": q.n_nodes, "hanging": q.n_hanging,
+           "constraint_entries": q.n_constraint, "host_build_s": round(t_build, 2),
+           "device_bytes": q.device_bytes, "precision": "fp64"}
+    stream = torch.cuda.current_stream()
+    for mode in ("residual", "jvp"):
+        f = (lambda: q.residual(p, d1, d0, out)) if mode == "residual" else (lambda: q.jvp(p, d1, d0, dd, out))
+        f()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        for _ in range(reps):
+            f()
+        e.record(stream)
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / reps
+        res[mode] = {"ms": round(ms, 4), "GDoF_per_s": round(2 * q.n_nodes / ms / 1e6, 4),
+                     "ns_per_leaf": round(ms * 1e6 / mesh.n_leaves, 2)}
+    q.close()
+    mesh.close()
+    del d1, d0, dd, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving_run(args, chns, W):
     """The serving stream: Poisson arrivals of independent droplet / bubble
     problems (workloads.serving_stream), mixed precision with the
@@ -374,6 +414,8 @@ def main():
     ap.add_argument("--serve-newton-max-it", type=int, default=8)
     ap.add_argument("--serve-max-wall-s", type=float, default=300.0)
     ap.add_argument("--serve-coupled", type=int, default=1)
+    ap.add_argument("--q2-workload", default="bubble_l9", help="mesh of the cG(2) CH block line")
+    ap.add_argument("--no-q2", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
@@ -591,6 +633,12 @@ def main():
         serving_summary = summ
         log(f"[bench] serving {summ} ({time.time() - t_bench:.0f}s)")
 
+    # ---- cG(2) CH block
+    q2 = None
+    if not args.no_q2:
+        q2 = q2_run(chns, W, torch, args.q2_workload, args.kernel_reps)
+        log(f"[bench] q2 {q2} ({time.time() - t_bench:.0f}s)")
+
     # ---- CPU baseline: the oracle's 6-DoF JVP on the same workload at level 8
     cpu = None
     if not args.no_cpu_baseline:
@@ -640,6 +688,7 @@ def main():
         "cn_steps": steps,
         "oracle_anchor": anchor,
         "serving": serving_summary,
+        "q2_ch": q2,
         "kernels": {k: round(v, 4) for k, v in kern.items()},
         "kernel_roofline": kernel_roofline(kern, n, E),
         "bench_wall_s": round(time.time() - t_bench, 1),

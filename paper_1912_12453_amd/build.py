@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchns.so")
-SOURCES = ["capi.hip", "mesh_host.cpp", "multigrid_host.cpp", "remesh_host.cpp"]
+SOURCES = ["capi.hip", "mesh_host.cpp", "multigrid_host.cpp", "remesh_host.cpp", "q2_host.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions in device code

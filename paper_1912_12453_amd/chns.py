@@ -128,6 +128,14 @@ def lib():
         L.chns_residual.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp]
         L.chns_jvp.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp, C.c_int, vp]
         L.chns_jvp_noalloc.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp, C.c_int, vp]
+        L.chns_q2_build.argtypes = [vp, C.POINTER(vp), vp]
+        L.chns_q2_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64)]
+        L.chns_q2_nodes.argtypes = [vp, vp]
+        L.chns_q2_residual.argtypes = [vp, C.POINTER(chns_params), vp, vp, vp, vp]
+        L.chns_q2_jvp.argtypes = [vp, C.POINTER(chns_params), vp, vp, vp, vp, vp]
+        L.chns_q2_free.argtypes = [vp]
+        L.chns_q2_host_arrays.argtypes = [vp, C.POINTER(C.c_int64)] + [vp] * 6
         L.chns_jvp_full.argtypes = [vp, C.POINTER(chns_params), vp, vp, vp, vp, C.c_int, vp]
         L.chns_linearize.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, C.c_int, vp]
         L.chns_jvp_lin.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, C.c_int, vp]
@@ -318,6 +326,34 @@ def chns_server_stats_get(server):
 
 def chns_server_destroy(server):
     _check(lib().chns_server_destroy(server))
+
+
+def chns_q2_build(mesh, stream=None):
+    h = C.c_void_p()
+    _check(lib().chns_q2_build(mesh, C.byref(h), _stream(stream)))
+    return h
+
+
+def chns_q2_info(q):
+    v = [C.c_int64() for _ in range(4)]
+    _check(lib().chns_q2_info(q, *[C.byref(x) for x in v]))
+    return tuple(int(x.value) for x in v)
+
+
+def chns_q2_residual(q, params, U_new, U_old, R, stream=None):
+    _dev(U_new, "float64"), _dev(U_old, "float64"), _dev(R, "float64")
+    return _check(lib().chns_q2_residual(q, C.byref(params), U_new.data_ptr(), U_old.data_ptr(),
+                                         R.data_ptr(), _stream(stream)))
+
+
+def chns_q2_jvp(q, params, U_new, U_old, dU, JdU, stream=None):
+    _dev(U_new, "float64"), _dev(U_old, "float64"), _dev(dU, "float64"), _dev(JdU, "float64")
+    return _check(lib().chns_q2_jvp(q, C.byref(params), U_new.data_ptr(), U_old.data_ptr(),
+                                    dU.data_ptr(), JdU.data_ptr(), _stream(stream)))
+
+
+def chns_q2_free(q):
+    _check(lib().chns_q2_free(q))
 
 
 def _stream(stream):
@@ -519,6 +555,24 @@ class Mesh:
         chns_mesh_upload(self.h, stream)
         self.stats = chns_mesh_info(self.h)
 
+    def q2_arrays(self):
+        """Host-only cG(2) numbering (chns_q2_host_arrays): dict of numpy arrays."""
+        sz = (C.c_int64 * 3)()
+        _check(lib().chns_q2_host_arrays(self.h, sz, None, None, None, None, None, None))
+        n, nh, nc = (int(v) for v in sz)
+        a = {"elem": np.zeros((self.n_leaves, 27), np.int32), "nodes": np.zeros((n, 3)),
+             "hang_xyz": np.zeros((nh, 3)), "hang_off": np.zeros(nh + 1, np.int32),
+             "hang_ids": np.zeros(nc, np.int32), "hang_w": np.zeros(nc)}
+        _check(lib().chns_q2_host_arrays(self.h, sz, a["elem"].ctypes.data, a["nodes"].ctypes.data,
+                                         a["hang_xyz"].ctypes.data, a["hang_off"].ctypes.data,
+                                         a["hang_ids"].ctypes.data, a["hang_w"].ctypes.data))
+        return a
+
+    def q2(self, stream=None):
+        """The cG(2) CH block on this mesh's leaves (a Q2; the mesh must
+        outlive it)."""
+        return Q2(self, stream)
+
     def residual(self, params, block, U_new, U_old, out=None):
         import torch
         if out is None:
@@ -563,3 +617,42 @@ class Mesh:
     def step(self, params, opts, U):
         rc, st = chns_step(self.h, params, opts, U)
         return rc, st
+
+
+class Q2:
+    """Triquadratic (27-node) CH block on the leaves of a Mesh (chns_q2_*)."""
+
+    def __init__(self, mesh, stream=None):
+        self.mesh = mesh  # the numbering reads the mesh's device arrays
+        self.h = chns_q2_build(mesh.h, stream)
+        self.n_nodes, self.n_hanging, self.n_constraint, self.device_bytes = chns_q2_info(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            chns_q2_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nodes(self):
+        xyz = np.zeros((self.n_nodes, 3))
+        _check(lib().chns_q2_nodes(self.h, xyz.ctypes.data))
+        return xyz
+
+    def residual(self, params, U_new, U_old, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(U_new)
+        chns_q2_residual(self.h, params, U_new, U_old, out)
+        return out
+
+    def jvp(self, params, U_new, U_old, dU, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(dU)
+        chns_q2_jvp(self.h, params, U_new, U_old, dU, out)
+        return out

@@ -1869,3 +1869,4 @@ int chns_launch_element_loop(chns_mesh* m, const chns_params* params, int block,
 }  // extern "C"
 
 #include "serve.inl"
+#include "q2.inl"

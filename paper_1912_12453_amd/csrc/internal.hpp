@@ -58,6 +58,23 @@ struct HostMesh {
 // Returns "" or an error message.
 std::string build_host_mesh(const chns_mesh_spec& spec, HostMesh& out);
 
+// cG(2) numbering of a host mesh for the triquadratic CH block (q2_host.cpp):
+// Morton keys of the doubled lattice coordinates of the independent and
+// hanging points, the constraint rows (CSR), the 27 node refs per leaf (id,
+// or -1 - h) and the gather plan: node n sums the element results g_slot[k]
+// (leaf * 27 + local node) times g_w[k], g_off[n] <= k < g_off[n+1], in
+// increasing slot order.
+struct HostQ2 {
+  std::vector<uint64_t> node_key, hang_key;
+  std::vector<int32_t> hang_off, hang_ids;
+  std::vector<double> hang_w;
+  std::vector<int32_t> elem;
+  std::vector<int64_t> g_off;
+  std::vector<int32_t> g_slot;
+  std::vector<double> g_w;
+};
+std::string build_host_q2(const HostMesh& h, HostQ2& out);
+
 // Scatter plan of the element loop (all integer, built once per mesh).
 // Elements are cut into Morton chunks of kChunk consecutive leaves, one
 // workgroup each.  The targets of chunk c are the independent nodes its

@@ -1,0 +1,106 @@
+"""GPU parity of the cG(2) CH block (chns_q2_residual, chns_q2_jvp) with the
+oracle's triquadratic element loop, through the C ABI, on adaptive meshes
+with quadratic hanging constraints (2:1 faces and edges), an odd leaf count
+(the last workgroup's second leaf idle), the RT brick, and random states
+(phi partly outside [-1, 1]).  FP64 on both sides: 1e-12 relative."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_12453_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "a GPU is required"
+    return t
+
+
+@pytest.fixture(scope="module")
+def chns():
+    from paper_1912_12453_amd import chns as c
+    c.lib()
+    return c
+
+
+CASES = {
+    "random925": ("random", (1, 1, 1), 2, 4, 7),
+    "random4159": ("random", (1, 1, 1), 2, 5, 5),
+    "brick": ("random", (2, 1, 1), 1, 4, 3),
+    "drop": ("drop", (1, 1, 1), 2, 6, 0),
+    "rt": ("rt", (1, 1, 4), 2, 5, 0),
+}
+
+
+def build(chns, kind, trees, lmin, lmax, seed):
+    if kind == "random":
+        leaves = W.random_leaves(trees, lmax, seed, p_split=0.35, level_min=lmin)
+        return chns.Mesh(trees, 0, lmax, leaves=leaves), oracle.Mesh(trees, 0, lmax, leaves=leaves)
+    if kind == "drop":
+        phi0 = W.drops_phi([(np.array([0.4, 0.45, 0.5]), 0.2)], 0.05, -1.0)
+    else:
+        phi0 = W.rt(level_max=lmax).mesh.phi0
+    return chns.Mesh(trees, lmin, lmax, phi0, 0.9), oracle.Mesh(trees, lmin, lmax, phi0, 0.9)
+
+
+def physics(name):
+    if name == "rt":
+        return W.rt(level_max=5).physics
+    if name == "drop":
+        return W.Physics(Cn=0.05, Pe=1.0 / (3 * 0.05 ** 2), Re=35.0, We=10.0, Fr=1.0, rho_minus=500.0,
+                         eta_minus=50.0, dt=5e-4)
+    return W.moderate_physics()
+
+
+def compare(gpu, ref, label):
+    g, r = gpu[:, 0:2], ref[:, 0:2]
+    e = np.linalg.norm(g - r) / np.linalg.norm(r)
+    emax = np.abs(g - r).max() / np.abs(r).max()
+    print(f"{label}: rel2 {e:.2e} relmax {emax:.2e}", flush=True)
+    assert e <= TOL and emax <= 10 * TOL, (e, emax)
+    assert np.all(gpu[:, 2:] == 0.0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_q2_residual_and_jvp(torch, chns, name):
+    pm, om = build(chns, *CASES[name])
+    q = pm.q2()
+    oq = om.q2()
+    print(f"case q2 {name}: E={pm.n_leaves} n={q.n_nodes} hanging={q.n_hanging}", flush=True)
+    assert q.n_nodes == oq.n_nodes and q.n_hanging == oq.hang_xyz.shape[0]
+    np.testing.assert_array_equal(q.nodes(), oq.node_xyz())
+    ph = physics(name)
+    p, po = chns.make_params(ph), oracle.Params.make(**vars(ph))
+    for seed in (1, 2):
+        U1, U0 = W.random_state(q.n_nodes, 40 + seed)
+        dU = W.direction(q.n_nodes, 60 + seed)
+        d1 = torch.tensor(U1, device="cuda:0")
+        d0 = torch.tensor(U0, device="cuda:0")
+        dd = torch.tensor(dU, device="cuda:0")
+        R = q.residual(p, d1, d0).cpu().numpy()
+        compare(R, oq.residual(po, U1, U0), f"residual {name} seed {seed}")
+        J = q.jvp(p, d1, d0, dd).cpu().numpy()
+        compare(J, oq.jvp(po, U1, U0, dU), f"jvp {name} seed {seed}")
+    q.close()
+    pm.close()
+
+
+def test_q2_repeat_is_bitwise(torch, chns):
+    """Fixed-order gather: the same call twice gives the same bits."""
+    pm, _ = build(chns, *CASES["drop"])
+    q = pm.q2()
+    p = chns.make_params(physics("drop"))
+    U1, U0 = W.random_state(q.n_nodes, 5)
+    d1 = torch.tensor(U1, device="cuda:0")
+    d0 = torch.tensor(U0, device="cuda:0")
+    a = q.residual(p, d1, d0)
+    b = q.residual(p, d1, d0)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    q.close()
+    pm.close()
