@@ -90,9 +90,9 @@ def lib():
         L.orc_q2_build.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
         L.orc_q2_free.argtypes = [C.c_void_p]
         L.orc_q2_sizes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
-        L.orc_q2_arrays.argtypes = [C.c_void_p] + [C.c_void_p] * 6
-        L.orc_q2_residual.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(Params), dp, dp, dp]
-        L.orc_q2_jvp.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(Params), dp, dp, dp, dp]
+        L.orc_q2_arrays.argtypes = [C.c_void_p] + [C.c_void_p] * 7
+        L.orc_q2_residual.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_int, dp, dp, dp]
+        L.orc_q2_jvp.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_int, dp, dp, dp, dp]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_set_num_threads.restype = None
@@ -284,7 +284,7 @@ class Mesh:
         return x0[:, None, :] + 0.5 * h[:, None, None] * (1.0 + s[None, :, :] * g)
 
     def q2(self):
-        """The cG(2) numbering of this mesh (27-node leaves, CH block)."""
+        """The cG(2) numbering of this mesh (27-node leaves)."""
         return MeshQ2(self)
 
 
@@ -293,7 +293,7 @@ class MeshQ2:
     3j + 9k of a leaf at its anchor plus (i, j, k) half sides; coordinates in
     doubled units 2^-(level_max+1).  Hanging lattice points take the
     coarsest neighbouring leaf's triquadratic interpolant (Sec. 4, carried
-    over to cG(2))."""
+    over to cG(2)).  Both blocks' rows (CH and VMS NS) on this space."""
 
     def __init__(self, mesh):
         L = lib()
@@ -312,8 +312,10 @@ class MeshQ2:
         self.hang_off = np.zeros(nh + 1, np.int64)
         self.hang_ids = np.zeros(nc, np.int32)
         self.hang_w = np.zeros(nc, np.float64)
+        self.bflags = np.zeros(n, np.uint8)
         L.orc_q2_arrays(h, self.elem.ctypes.data, self.nodes.ctypes.data, self.hang_xyz.ctypes.data,
-                        self.hang_off.ctypes.data, self.hang_ids.ctypes.data, self.hang_w.ctypes.data)
+                        self.hang_off.ctypes.data, self.hang_ids.ctypes.data, self.hang_w.ctypes.data,
+                        self.bflags.ctypes.data)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -332,21 +334,22 @@ class MeshQ2:
     def hang_coords(self):
         return self.hang_xyz.astype(np.float64) * 2.0 ** (-(self.mesh.level_max + 1))
 
-    def residual(self, p, Unew, Uold):
-        """CH rows (fields 0, 1) over the Q2 nodes."""
+    def residual(self, p, Unew, Uold, block=BLOCK_CH):
+        """Block rows over the Q2 nodes: CH fields 0, 1 or NS fields 2..5."""
         n = self.n_nodes
         Unew, Uold = _state(Unew, n), _state(Uold, n)
         R = np.zeros((n, 6))
-        if lib().orc_q2_residual(self.mesh._h, self._h, C.byref(p), _dp(Unew), _dp(Uold), _dp(R)) != 0:
+        if lib().orc_q2_residual(self.mesh._h, self._h, C.byref(p), block, _dp(Unew), _dp(Uold),
+                                 _dp(R)) != 0:
             raise RuntimeError(_err())
         return R
 
-    def jvp(self, p, Unew, Uold, dU):
-        """CH block Jacobian (derivative in phi^{k+1}, mu^{k+1}) applied to dU."""
+    def jvp(self, p, Unew, Uold, dU, block=BLOCK_CH):
+        """The block's Jacobian (derivative in its own unknowns) applied to dU."""
         n = self.n_nodes
         Unew, Uold, dU = _state(Unew, n), _state(Uold, n), _state(dU, n)
         out = np.zeros((n, 6))
-        if lib().orc_q2_jvp(self.mesh._h, self._h, C.byref(p), _dp(Unew), _dp(Uold), _dp(dU),
+        if lib().orc_q2_jvp(self.mesh._h, self._h, C.byref(p), block, _dp(Unew), _dp(Uold), _dp(dU),
                             _dp(out)) != 0:
             raise RuntimeError(_err())
         return out

@@ -121,13 +121,15 @@ struct MeshQ2 {
   std::vector<int64_t> hang_off;
   std::vector<int32_t> hang_ids;
   std::vector<double> hang_w;
+  std::vector<uint8_t> bflags;                   // bit0 on boundary, bit1 pressure pin
 };
 std::string build_q2(const Mesh& m, MeshQ2& out);
-// CH rows (fields 0, 1 of a node-major 6-field vector over the Q2 nodes; the
-// velocity fields enter as the frozen v~ of the block iteration).
-std::string residual_q2(const Mesh& m, const MeshQ2& q, const Params& p, const double* Unew,
+// Block rows over the Q2 nodes (node-major 6-field vectors): CH fields 0, 1
+// (the velocities enter as the frozen v~ of the block iteration), or NS
+// fields 2..5 with the boundary rows of the cG(1) oracle.
+std::string residual_q2(const Mesh& m, const MeshQ2& q, const Params& p, int block, const double* Unew,
                         const double* Uold, double* R);
-std::string jvp_q2(const Mesh& m, const MeshQ2& q, const Params& p, const double* Unew,
+std::string jvp_q2(const Mesh& m, const MeshQ2& q, const Params& p, int block, const double* Unew,
                    const double* Uold, const double* dU, double* JdU);
 
 }  // namespace orc

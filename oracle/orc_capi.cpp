@@ -131,8 +131,9 @@ void orc_q2_sizes(void* qp, int64_t* s) {
 }
 
 void orc_q2_arrays(void* qp, int32_t* elem27, int32_t* nodes3, int32_t* hang3, int64_t* hang_off,
-                   int32_t* hang_ids, double* hang_w) {
+                   int32_t* hang_ids, double* hang_w, uint8_t* bflags) {
   const orc::MeshQ2& q = *(orc::MeshQ2*)qp;
+  for (size_t i = 0; i < q.bflags.size(); ++i) bflags[i] = q.bflags[i];
   for (size_t e = 0; e < q.elem.size(); ++e)
     for (int a = 0; a < 27; ++a) elem27[27 * e + a] = q.elem[e][a];
   for (size_t i = 0; i < q.nodes.size(); ++i)
@@ -146,15 +147,15 @@ void orc_q2_arrays(void* qp, int32_t* elem27, int32_t* nodes3, int32_t* hang3, i
   }
 }
 
-int orc_q2_residual(void* m, void* q, const orc::Params* p, const double* Unew, const double* Uold,
-                    double* R) {
-  std::string e = orc::residual_q2(*(orc::Mesh*)m, *(orc::MeshQ2*)q, *p, Unew, Uold, R);
+int orc_q2_residual(void* m, void* q, const orc::Params* p, int block, const double* Unew,
+                    const double* Uold, double* R) {
+  std::string e = orc::residual_q2(*(orc::Mesh*)m, *(orc::MeshQ2*)q, *p, block, Unew, Uold, R);
   return e.empty() ? 0 : fail(e);
 }
 
-int orc_q2_jvp(void* m, void* q, const orc::Params* p, const double* Unew, const double* Uold,
+int orc_q2_jvp(void* m, void* q, const orc::Params* p, int block, const double* Unew, const double* Uold,
                const double* dU, double* JdU) {
-  std::string e = orc::jvp_q2(*(orc::Mesh*)m, *(orc::MeshQ2*)q, *p, Unew, Uold, dU, JdU);
+  std::string e = orc::jvp_q2(*(orc::Mesh*)m, *(orc::MeshQ2*)q, *p, block, Unew, Uold, dU, JdU);
   return e.empty() ? 0 : fail(e);
 }
 
