@@ -239,10 +239,10 @@ def oracle_anchor(oracle, w, om, states, rows):
 
 
 def q2_run(chns, W, torch, name, reps):
-    """The cG(2) CH block (27-node leaves) on a workload's mesh: host build of
-    the numbering, then the element pass and node gather of the residual and
-    of the JVP, each timed over `reps` launches with HIP events on the launch
-    stream.  Random state and direction (seeded)."""
+    """The cG(2) blocks (27-node leaves) on a workload's mesh: host build of
+    the numbering, then the element pass and node gather of each block's
+    residual and JVP, each timed over `reps` launches with HIP events on the
+    launch stream.  Random state and direction (seeded)."""
     w = W.by_name(name)
     mesh = chns.Mesh.from_spec(w.mesh)
     mesh.upload()
@@ -258,19 +258,23 @@ def q2_run(chns, W, torch, name, reps):
            "constraint_entries": q.n_constraint, "host_build_s": round(t_build, 2),
            "device_bytes": q.device_bytes, "precision": "fp64"}
     stream = torch.cuda.current_stream()
-    for mode in ("residual", "jvp"):
-        f = (lambda: q.residual(p, d1, d0, out)) if mode == "residual" else (lambda: q.jvp(p, d1, d0, dd, out))
-        f()
-        torch.cuda.synchronize()
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s.record(stream)
-        for _ in range(reps):
+    for block, bname, nf in ((0, "ch", 2), (1, "ns", 4)):
+        for mode in ("residual", "jvp"):
+            if mode == "residual":
+                f = lambda: q.residual(p, d1, d0, block=block, out=out)
+            else:
+                f = lambda: q.jvp(p, d1, d0, dd, block=block, out=out)
             f()
-        e.record(stream)
-        torch.cuda.synchronize()
-        ms = s.elapsed_time(e) / reps
-        res[mode] = {"ms": round(ms, 4), "GDoF_per_s": round(2 * q.n_nodes / ms / 1e6, 4),
-                     "ns_per_leaf": round(ms * 1e6 / mesh.n_leaves, 2)}
+            torch.cuda.synchronize()
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record(stream)
+            for _ in range(reps):
+                f()
+            e.record(stream)
+            torch.cuda.synchronize()
+            ms = s.elapsed_time(e) / reps
+            res[f"{bname}_{mode}"] = {"ms": round(ms, 4), "GDoF_per_s": round(nf * q.n_nodes / ms / 1e6, 4),
+                                      "ns_per_leaf": round(ms * 1e6 / mesh.n_leaves, 2)}
     q.close()
     mesh.close()
     del d1, d0, dd, out

@@ -419,18 +419,19 @@ int chns_server_stats_get(chns_server* srv, chns_server_stats* out);
 /* Stops the builder, frees every request's device and host memory. */
 int chns_server_destroy(chns_server* srv);
 
-/* ------------------------------------------- cG(2) Cahn-Hilliard block ---
- * Triquadratic (27-node) elements on the leaves of a mesh, for the CH block
- * only: the paper discretises with cG(1) (Sec. 3.4) and names higher-order
- * cG spaces as the next step (Sec. 7).  Nodes are the 3x3x3 lattice of every
- * leaf; a lattice point that is not on the lattice of some other leaf whose
- * closure contains it hangs, and takes the triquadratic interpolant of the
- * coarsest such leaf (Sec. 4 "Handling hanging nodes", carried over), with
- * hanging parents substituted.  Independent nodes are numbered in Morton
- * order of their coordinates in units of 2^-(level_max+1).  Integrals use the
- * 3x3x3 Gauss rule; the rows are those of chns_residual's CH block (Def. 2,
- * eqns mu_eqn_var_semi_disc and phi_eqn_var_semi_disc, Crank-Nicolson
- * midpoints, psi'(phi~) = phi~^3 - phi~) on the cG(2) space.  FP64 only. */
+/* ---------------------------------------------------------- cG(2) blocks ---
+ * Triquadratic (27-node) elements on the leaves of a mesh: the paper
+ * discretises with cG(1) (Sec. 3.4) and names higher-order cG spaces as the
+ * next step (Sec. 7).  Nodes are the 3x3x3 lattice of every leaf; a lattice
+ * point that is not on the lattice of some other leaf whose closure contains
+ * it hangs, and takes the triquadratic interpolant of the coarsest such leaf
+ * (Sec. 4 "Handling hanging nodes", carried over), with hanging parents
+ * substituted.  Independent nodes are numbered in Morton order of their
+ * coordinates in units of 2^-(level_max+1); wall and pressure-pin flags
+ * follow the cG(1) mesh's rules.  Integrals use the 3x3x3 Gauss rule; the
+ * rows are those of chns_residual for the same block on the cG(2) space,
+ * except that the NS strong residual R_m keeps the Laplacian parts of the
+ * capillary and viscous divergences (zero on trilinear leaves).  FP64 only. */
 typedef struct chns_q2 chns_q2;
 /* Builds the numbering and its gather plan on the host and copies them to
  * the current device (which must be the mesh's; the mesh is uploaded first if
@@ -442,26 +443,31 @@ int chns_q2_info(const chns_q2* q, int64_t* n_nodes, int64_t* n_hanging, int64_t
                  int64_t* device_bytes);
 /* Physical coordinates of the independent nodes (host, n_nodes*3). */
 int chns_q2_nodes(const chns_q2* q, double* xyz);
-/* CH residual rows over the Q2 nodes.  U_new, U_old, R: device, node-major
- * n_nodes*6 FP64 (phi, mu, u, v, w, p; the velocities enter as the frozen v~
- * of the block iteration); R's fields 0, 1 are written, fields 2..5 set to 0.
- * Asynchronous on `stream`. */
-int chns_q2_residual(chns_q2* q, const chns_params* params, const double* U_new, const double* U_old,
-                     double* R, void* stream);
-/* The CH block's Jacobian (derivative in phi^{k+1}, mu^{k+1}) applied to dU
- * (device, n_nodes*6; fields 0, 1 are read); JdU like R above. */
-int chns_q2_jvp(chns_q2* q, const chns_params* params, const double* U_new, const double* U_old,
-                const double* dU, double* JdU, void* stream);
+/* Residual rows of a block over the Q2 nodes.  U_new, U_old, R: device,
+ * node-major n_nodes*6 FP64 (phi, mu, u, v, w, p).  CH: R's fields 0, 1 (the
+ * velocities enter as the frozen v~ of the block iteration); NS: fields 2..5,
+ * velocity rows of wall nodes v^{k+1} - v^k and the pinned pressure row
+ * p^{k+1} - p^k.  The other block's fields are set to 0.  A point whose
+ * tau_m bracket is not positive gives non-finite rows.  Asynchronous on
+ * `stream`. */
+int chns_q2_residual(chns_q2* q, const chns_params* params, int block, const double* U_new,
+                     const double* U_old, double* R, void* stream);
+/* The block's Jacobian (derivative in its own unknowns) applied to dU
+ * (device, n_nodes*6; the block's fields are read); JdU like R above, with
+ * identity rows on the NS wall and pin rows. */
+int chns_q2_jvp(chns_q2* q, const chns_params* params, int block, const double* U_new,
+                const double* U_old, const double* dU, double* JdU, void* stream);
 int chns_q2_free(chns_q2* q);
 /* Host-only view of the same numbering (no device needed): sizes[0..2] =
  * independent nodes, hanging nodes, constraint entries; then, for non-NULL
  * outputs (caller-allocated from the sizes; a first call with NULL arrays
  * gives them): the 27 refs per leaf (id, or -1 - hanging index), node and
- * hanging-node coordinates (n*3), and the constraint rows as CSR (hang_off
- * of n_hanging+1 entries into hang_ids / hang_w, ascending ids).  Builds the
- * numbering on every call. */
+ * hanging-node coordinates (n*3), the constraint rows as CSR (hang_off of
+ * n_hanging+1 entries into hang_ids / hang_w, ascending ids) and the nodes'
+ * wall / pressure-pin flags.  Builds the numbering on every call. */
 int chns_q2_host_arrays(const chns_mesh* mesh, int64_t* sizes, int32_t* elem27, double* node_xyz,
-                        double* hang_xyz, int32_t* hang_off, int32_t* hang_ids, double* hang_w);
+                        double* hang_xyz, int32_t* hang_off, int32_t* hang_ids, double* hang_w,
+                        uint8_t* bflags);
 
 const char* chns_last_error(void);
 

@@ -132,10 +132,10 @@ def lib():
         L.chns_q2_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64)]
         L.chns_q2_nodes.argtypes = [vp, vp]
-        L.chns_q2_residual.argtypes = [vp, C.POINTER(chns_params), vp, vp, vp, vp]
-        L.chns_q2_jvp.argtypes = [vp, C.POINTER(chns_params), vp, vp, vp, vp, vp]
+        L.chns_q2_residual.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp]
+        L.chns_q2_jvp.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, vp, vp, vp]
         L.chns_q2_free.argtypes = [vp]
-        L.chns_q2_host_arrays.argtypes = [vp, C.POINTER(C.c_int64)] + [vp] * 6
+        L.chns_q2_host_arrays.argtypes = [vp, C.POINTER(C.c_int64)] + [vp] * 7
         L.chns_jvp_full.argtypes = [vp, C.POINTER(chns_params), vp, vp, vp, vp, C.c_int, vp]
         L.chns_linearize.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, C.c_int, vp]
         L.chns_jvp_lin.argtypes = [vp, C.POINTER(chns_params), C.c_int, vp, vp, C.c_int, vp]
@@ -340,15 +340,15 @@ def chns_q2_info(q):
     return tuple(int(x.value) for x in v)
 
 
-def chns_q2_residual(q, params, U_new, U_old, R, stream=None):
+def chns_q2_residual(q, params, block, U_new, U_old, R, stream=None):
     _dev(U_new, "float64"), _dev(U_old, "float64"), _dev(R, "float64")
-    return _check(lib().chns_q2_residual(q, C.byref(params), U_new.data_ptr(), U_old.data_ptr(),
+    return _check(lib().chns_q2_residual(q, C.byref(params), block, U_new.data_ptr(), U_old.data_ptr(),
                                          R.data_ptr(), _stream(stream)))
 
 
-def chns_q2_jvp(q, params, U_new, U_old, dU, JdU, stream=None):
+def chns_q2_jvp(q, params, block, U_new, U_old, dU, JdU, stream=None):
     _dev(U_new, "float64"), _dev(U_old, "float64"), _dev(dU, "float64"), _dev(JdU, "float64")
-    return _check(lib().chns_q2_jvp(q, C.byref(params), U_new.data_ptr(), U_old.data_ptr(),
+    return _check(lib().chns_q2_jvp(q, C.byref(params), block, U_new.data_ptr(), U_old.data_ptr(),
                                     dU.data_ptr(), JdU.data_ptr(), _stream(stream)))
 
 
@@ -558,18 +558,19 @@ class Mesh:
     def q2_arrays(self):
         """Host-only cG(2) numbering (chns_q2_host_arrays): dict of numpy arrays."""
         sz = (C.c_int64 * 3)()
-        _check(lib().chns_q2_host_arrays(self.h, sz, None, None, None, None, None, None))
+        _check(lib().chns_q2_host_arrays(self.h, sz, None, None, None, None, None, None, None))
         n, nh, nc = (int(v) for v in sz)
         a = {"elem": np.zeros((self.n_leaves, 27), np.int32), "nodes": np.zeros((n, 3)),
              "hang_xyz": np.zeros((nh, 3)), "hang_off": np.zeros(nh + 1, np.int32),
-             "hang_ids": np.zeros(nc, np.int32), "hang_w": np.zeros(nc)}
+             "hang_ids": np.zeros(nc, np.int32), "hang_w": np.zeros(nc), "bflags": np.zeros(n, np.uint8)}
         _check(lib().chns_q2_host_arrays(self.h, sz, a["elem"].ctypes.data, a["nodes"].ctypes.data,
                                          a["hang_xyz"].ctypes.data, a["hang_off"].ctypes.data,
-                                         a["hang_ids"].ctypes.data, a["hang_w"].ctypes.data))
+                                         a["hang_ids"].ctypes.data, a["hang_w"].ctypes.data,
+                                         a["bflags"].ctypes.data))
         return a
 
     def q2(self, stream=None):
-        """The cG(2) CH block on this mesh's leaves (a Q2; the mesh must
+        """The cG(2) blocks on this mesh's leaves (a Q2; the mesh must
         outlive it)."""
         return Q2(self, stream)
 
@@ -620,7 +621,7 @@ class Mesh:
 
 
 class Q2:
-    """Triquadratic (27-node) CH block on the leaves of a Mesh (chns_q2_*)."""
+    """Triquadratic (27-node) CH and NS blocks on the leaves of a Mesh (chns_q2_*)."""
 
     def __init__(self, mesh, stream=None):
         self.mesh = mesh  # the numbering reads the mesh's device arrays
@@ -643,16 +644,16 @@ class Q2:
         _check(lib().chns_q2_nodes(self.h, xyz.ctypes.data))
         return xyz
 
-    def residual(self, params, U_new, U_old, out=None):
+    def residual(self, params, U_new, U_old, block=CHNS_BLOCK_CH, out=None):
         import torch
         if out is None:
             out = torch.empty_like(U_new)
-        chns_q2_residual(self.h, params, U_new, U_old, out)
+        chns_q2_residual(self.h, params, block, U_new, U_old, out)
         return out
 
-    def jvp(self, params, U_new, U_old, dU, out=None):
+    def jvp(self, params, U_new, U_old, dU, block=CHNS_BLOCK_CH, out=None):
         import torch
         if out is None:
             out = torch.empty_like(dU)
-        chns_q2_jvp(self.h, params, U_new, U_old, dU, out)
+        chns_q2_jvp(self.h, params, block, U_new, U_old, dU, out)
         return out

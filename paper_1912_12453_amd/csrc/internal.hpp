@@ -72,6 +72,7 @@ struct HostQ2 {
   std::vector<int64_t> g_off;
   std::vector<int32_t> g_slot;
   std::vector<double> g_w;
+  std::vector<uint8_t> bflags;  // per node: bit 0 on the brick's boundary, bit 1 the pressure pin
 };
 std::string build_host_q2(const HostMesh& h, HostQ2& out);
 

@@ -394,10 +394,14 @@ __device__ __forceinline__ void ns_residual_point(const PhysView& p, const Lane<
 // p^{k+1}) at the point: dvt = dv/2 (value and gradient), ddv = dv (value),
 // dpt = dp/2.  Returns the coefficients (c, F) of the momentum rows i = 0..2
 // and the continuity row 3, before the Gauss weight.
-template <class T>
+// LAP: the direction's v~ has a Laplacian (dlap, already halved) whose
+// viscous part -(eta/Re) lap dv~_i enters dR_m (triquadratic leaves; on
+// trilinear leaves it vanishes and the term is compiled out).
+template <class T, bool LAP = false>
 __device__ __forceinline__ void ns_jvp_coef(const PhysView& p, const NSPoint<T>& P,
                                             const VG<T> (&dvt)[3], const T (&ddv)[3],
-                                            const VG<T>& dpt, T (&c)[4], T (&F)[4][3]) {
+                                            const VG<T>& dpt, T (&c)[4], T (&F)[4][3],
+                                            const T* dlap = nullptr) {
   const T iPe = (T)p.inv_Pe, iWe = (T)p.inv_We, tm = P.tau_m, ir = P.inv_rho;
   const T er = P.eta * (T)p.inv_Re, idt = (T)p.inv_dt;
   T dG[3][3];
@@ -414,6 +418,7 @@ __device__ __forceinline__ void ns_jvp_coef(const PhysView& p, const NSPoint<T>&
     T t = P.rho * ddv[i] * idt + iWe * dgp[i];
 #pragma unroll
     for (int j = 0; j < 3; ++j) t += P.adv[j] * dG[i][j] + P.rho * dvt[j].v * P.G[i][j];
+    if constexpr (LAP) t -= P.eta * (T)p.inv_Re * dlap[i];
     dRm[i] = t;
   }
   const T dRc = dG[0][0] + dG[1][1] + dG[2][2];

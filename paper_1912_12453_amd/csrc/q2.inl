@@ -1,9 +1,11 @@
-// cG(2) Cahn-Hilliard block on the octree: triquadratic leaves (27 nodes),
-// the 3x3x3 Gauss rule, the residual rows of Def. 2's chemical-potential and
-// CH equations (eqns mu_eqn_var_semi_disc, phi_eqn_var_semi_disc) with the
-// Crank-Nicolson midpoints of the cG(1) element loop, and their Jacobian in
-// the direction of (phi^{k+1}, mu^{k+1}).  The paper discretises with cG(1)
-// (Sec. 3.4) and names higher-order cG spaces as the next step (Sec. 7).
+// cG(2) blocks on the octree: triquadratic leaves (27 nodes), the 3x3x3
+// Gauss rule, and the residual rows and block Jacobians of the cG(1) element
+// loop on that space: the CH block (Def. 2's chemical-potential and CH
+// equations, eqns mu_eqn_var_semi_disc, phi_eqn_var_semi_disc) and the VMS
+// Navier-Stokes block, whose strong residual R_m keeps the Laplacian parts of
+// the capillary and viscous divergences (they vanish on trilinear leaves).
+// The paper discretises with cG(1) (Sec. 3.4) and names higher-order cG
+// spaces as the next step (Sec. 7).
 //
 // Device layout: one 64-lane wave per two leaves, 32 lanes per leaf (27 in
 // use).  Lane a gathers local node a's fields (through its constraint row
@@ -42,6 +44,9 @@ struct Q2View {
   const double* hw;
   int64_t E;
 };
+
+// second derivative d2/du2 of the basis on [0, 1] with nodes 0, 1/2, 1
+__device__ __forceinline__ double q2_basis_dd(int i) { return i == 1 ? -8.0 : 4.0; }
 
 __device__ __forceinline__ double q2_node(const Q2View& q, int32_t ref, const double* __restrict__ U, int f) {
   if (ref >= 0) return U[(int64_t)ref * 6 + f];
@@ -158,23 +163,217 @@ __global__ __launch_bounds__(64) void k_q2_ch(Q2View q, PhysView p, const double
   }
 }
 
-// out[n][0..1] = sum over the node's plan entries of weight x element result;
-// out[n][2..5] = 0 (the CH block's rows only)
+// NS block on one leaf.  MODE 0: residual rows; MODE 1: the block Jacobian
+// (derivative in v^{k+1}, p^{k+1}) applied to dU.  The point quantities are
+// those of the cG(1) kernels (NSPoint, ns_material, ns_stab, ns_jvp_coef)
+// with R_m completed by -(eta/Re) lap v~ and (Cn/We) grad phi~ lap phi~.
+template <int MODE>
+__global__ __launch_bounds__(64) void k_q2_ns(Q2View q, PhysView p, const double* __restrict__ U1,
+                                              const double* __restrict__ U0, const double* __restrict__ dU,
+                                              double* __restrict__ part) {
+  constexpr int NS_ = MODE == 0 ? 10 : 14;  // nodal arrays per leaf
+  __shared__ double sn[2][NS_][27];
+  __shared__ double sq[2][16][27];
+  const int half = threadIdx.x >> 5, lane = threadIdx.x & 31;
+  const int64_t e0 = (int64_t)blockIdx.x * 2 + half;
+  const bool live = e0 < q.E;
+  const int64_t e = live ? e0 : q.E - 1;
+  const int lev = q.level[e];
+  const double h = ldexp(1.0, -lev), ih = ldexp(1.0, lev), ih2 = ih * ih;
+  if (lane < 27) {
+    const int32_t ref = q.elem[e * 27 + lane];
+    const double f1 = q2_node(q, ref, U1, 0), f0 = q2_node(q, ref, U0, 0);
+    sn[half][0][lane] = f1;                                                          // phi^{k+1}
+    sn[half][1][lane] = 0.5 * (f1 + f0);                                             // phi~
+    sn[half][2][lane] = 0.5 * (q2_node(q, ref, U1, 1) + q2_node(q, ref, U0, 1));     // mu~
+    for (int d = 0; d < 3; ++d) {
+      const double a = q2_node(q, ref, U1, 2 + d), b = q2_node(q, ref, U0, 2 + d);
+      sn[half][3 + d][lane] = 0.5 * (a + b);  // v~
+      sn[half][6 + d][lane] = a - b;          // v^{k+1} - v^k
+    }
+    sn[half][9][lane] = 0.5 * (q2_node(q, ref, U1, 5) + q2_node(q, ref, U0, 5));  // p~
+    if (MODE == 1)
+      for (int d = 0; d < 4; ++d) sn[half][10 + d][lane] = q2_node(q, ref, dU, 2 + d);  // dv, dp
+  }
+  __syncthreads();
+  if (lane < 27) {
+    const int g0 = lane % 3, g1 = (lane / 3) % 3, g2 = lane / 9;
+    double bx[3], dx[3], by[3], dy[3], bz[3], dz[3];
+    q2_basis_1d(q2_gauss_u(g0), bx, dx);
+    q2_basis_1d(q2_gauss_u(g1), by, dy);
+    q2_basis_1d(q2_gauss_u(g2), bz, dz);
+    double ph1 = 0.0, gph1[3] = {0.0, 0.0, 0.0}, gpt[3] = {0.0, 0.0, 0.0}, Hpt[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double gmu[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0}, gv[3][3] = {{0.0}}, lv[3] = {0.0, 0.0, 0.0};
+    double dvv[3] = {0.0, 0.0, 0.0}, pp = 0.0, gp[3] = {0.0, 0.0, 0.0};
+    double ev[3] = {0.0, 0.0, 0.0}, egv[3][3] = {{0.0}}, elv[3] = {0.0, 0.0, 0.0}, ep = 0.0, egp[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 27; ++a) {
+      const int i = a % 3, j = (a / 3) % 3, k = a / 9;
+      const double N = bx[i] * by[j] * bz[k];
+      const double G[3] = {dx[i] * by[j] * bz[k] * ih, bx[i] * dy[j] * bz[k] * ih, bx[i] * by[j] * dz[k] * ih};
+      // Hessian xx, yy, zz, xy, xz, yz
+      const double H[6] = {q2_basis_dd(i) * by[j] * bz[k] * ih2, bx[i] * q2_basis_dd(j) * bz[k] * ih2,
+                           bx[i] * by[j] * q2_basis_dd(k) * ih2, dx[i] * dy[j] * bz[k] * ih2,
+                           dx[i] * by[j] * dz[k] * ih2, bx[i] * dy[j] * dz[k] * ih2};
+      const double lap = H[0] + H[1] + H[2];
+      const double u1 = sn[half][0][a], ut = sn[half][1][a], um = sn[half][2][a], up = sn[half][9][a];
+      ph1 += N * u1;
+      pp += N * up;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        gph1[d] += G[d] * u1;
+        gpt[d] += G[d] * ut;
+        gmu[d] += G[d] * um;
+        gp[d] += G[d] * up;
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) Hpt[c] += H[c] * ut;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double uv = sn[half][3 + d][a];
+        v[d] += N * uv;
+        lv[d] += lap * uv;
+        dvv[d] += N * sn[half][6 + d][a];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gv[d][c] += G[c] * uv;
+      }
+      if (MODE == 1) {
+        const double ud = sn[half][13][a];
+        ep += N * ud;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          egp[d] += G[d] * ud;
+          const double uv = sn[half][10 + d][a];
+          ev[d] += N * uv;
+          elv[d] += lap * uv;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) egv[d][c] += G[c] * uv;
+        }
+      }
+    }
+    // the linearisation point (as ns_point, with the second-derivative terms completed)
+    NSPoint<double> P;
+    ns_material<double>(p, clamp1(ph1), P);
+    const bool inside = ph1 <= 1.0 && ph1 >= -1.0;
+    const double gg = inside ? p.gamma : 0.0;
+    const double iPe = p.inv_Pe, iRe = p.inv_Re, iWe = p.inv_We, cw = p.CnWe;
+    for (int d = 0; d < 3; ++d) {
+      P.vt[d] = v[d];
+      P.J[d] = p.kappa * gmu[d];
+      P.gpht[d] = gpt[d];
+      for (int c = 0; c < 3; ++c) P.G[d][c] = gv[d][c];
+    }
+    for (int d = 0; d < 3; ++d) P.adv[d] = P.rho * P.vt[d] + iPe * P.J[d] - iRe * gg * gph1[d];
+    P.pt = pp;
+    const double Hm[3][3] = {{Hpt[0], Hpt[3], Hpt[4]}, {Hpt[3], Hpt[1], Hpt[5]}, {Hpt[4], Hpt[5], Hpt[2]}};
+    const double lpt = Hpt[0] + Hpt[1] + Hpt[2];
+    for (int i = 0; i < 3; ++i) {
+      P.tg[i] = P.rho * (dvv[i] * p.inv_dt - p.g[i] * p.inv_Fr);
+      const double cap = cw * (gpt[0] * Hm[i][0] + gpt[1] * Hm[i][1] + gpt[2] * Hm[i][2] + gpt[i] * lpt);
+      P.Rm[i] = P.tg[i] + P.adv[0] * P.G[i][0] + P.adv[1] * P.G[i][1] + P.adv[2] * P.G[i][2] + cap +
+                iWe * gp[i] - P.eta * iRe * lv[i];
+    }
+    Lane<double> L;
+    L.Gh = 4.0 * ih2;
+    ns_stab<double>(p, L, P);
+    double c[4], F[4][3];
+    if (MODE == 0) {
+      // the cG(1) residual integrand (ns_residual_point) before the contraction
+      const double tm = P.tau_m, er = P.eta * iRe;
+      double W[3];
+      for (int j = 0; j < 3; ++j) W[j] = P.vt[j] + (P.J[j] * iPe - tm * P.Rm[j]) * P.inv_rho;
+      const double dgl = iWe * (P.rho * P.tau_c * P.Rc - P.pt);
+      for (int i = 0; i < 3; ++i) {
+        double ci = P.tg[i];
+        for (int j = 0; j < 3; ++j) ci += (P.rho * P.vt[j] + iPe * P.J[j] - tm * P.Rm[j]) * P.G[i][j];
+        c[i] = ci;
+        for (int j = 0; j < 3; ++j) F[i][j] = P.Rm[i] * tm * W[j] - cw * P.gpht[i] * P.gpht[j] + er * P.G[i][j];
+        F[i][i] += dgl;
+      }
+      c[3] = P.Rc;
+      for (int j = 0; j < 3; ++j) F[3][j] = tm * P.inv_rho * P.Rm[j];
+    } else {
+      VG<double> dvt[3], dpt;
+      double ddv[3], dlap[3];
+      for (int d = 0; d < 3; ++d) {
+        dvt[d].v = 0.5 * ev[d];
+        dvt[d].dx = 0.5 * egv[d][0];
+        dvt[d].dy = 0.5 * egv[d][1];
+        dvt[d].dz = 0.5 * egv[d][2];
+        ddv[d] = ev[d];
+        dlap[d] = 0.5 * elv[d];
+      }
+      dpt.v = 0.5 * ep;
+      dpt.dx = 0.5 * egp[0];
+      dpt.dy = 0.5 * egp[1];
+      dpt.dz = 0.5 * egp[2];
+      ns_jvp_coef<double, true>(p, P, dvt, ddv, dpt, c, F, dlap);
+    }
+    const double w = q2_gauss_w(g0) * q2_gauss_w(g1) * q2_gauss_w(g2) * h * h * h;
+    for (int f = 0; f < 4; ++f) {
+      sq[half][4 * f][lane] = w * c[f];
+      for (int d = 0; d < 3; ++d) sq[half][4 * f + 1 + d][lane] = w * F[f][d];
+    }
+  }
+  __syncthreads();
+  if (lane < 27 && live) {
+    const int ia = lane % 3, ja = (lane / 3) % 3, ka = lane / 9;
+    double cx[3], cy[3], cz[3], ex[3], ey[3], ez[3];
+    for (int g = 0; g < 3; ++g) {
+      double b[3], d[3];
+      q2_basis_1d(q2_gauss_u(g), b, d);
+      cx[g] = b[ia];
+      ex[g] = d[ia] * ih;
+      cy[g] = b[ja];
+      ey[g] = d[ja] * ih;
+      cz[g] = b[ka];
+      ez[g] = d[ka] * ih;
+    }
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int g = 0; g < 27; ++g) {
+      const int g0 = g % 3, g1 = (g / 3) % 3, g2 = g / 9;
+      const double N = cx[g0] * cy[g1] * cz[g2], Nx = ex[g0] * cy[g1] * cz[g2], Ny = cx[g0] * ey[g1] * cz[g2],
+                   Nz = cx[g0] * cy[g1] * ez[g2];
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+        r[f] += N * sq[half][4 * f][g] + Nx * sq[half][4 * f + 1][g] + Ny * sq[half][4 * f + 2][g] +
+                Nz * sq[half][4 * f + 3][g];
+    }
+    for (int f = 0; f < 4; ++f) part[(e * 27 + lane) * 4 + f] = r[f];
+  }
+}
+
+// Node rows of a block from the element results (NF per slot): out[n][OFF +
+// f] = sum of weight x result over the node's plan entries, the other block's
+// fields set to 0.  NS: velocity rows of wall nodes read v^{k+1} - v^k (A =
+// U1, B = U0) or, for the JVP, dv (A = dU, B = null); the pinned node's
+// pressure row likewise.
+template <int NF, int OFF>
 __global__ __launch_bounds__(256) void k_q2_gather(int64_t n, const int64_t* __restrict__ goff,
                                                    const int32_t* __restrict__ gslot,
                                                    const double* __restrict__ gw,
-                                                   const double* __restrict__ part, double* __restrict__ out) {
+                                                   const double* __restrict__ part, const uint8_t* __restrict__ bflags,
+                                                   const double* __restrict__ A, const double* __restrict__ B,
+                                                   double* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double s0 = 0.0, s1 = 0.0;
+    double s[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) s[f] = 0.0;
     for (int64_t k = goff[i]; k < goff[i + 1]; ++k) {
       const int64_t t = gslot[k];
-      s0 += gw[k] * part[t * 2];
-      s1 += gw[k] * part[t * 2 + 1];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) s[f] += gw[k] * part[t * NF + f];
     }
     double* o = out + i * 6;
-    o[0] = s0;
-    o[1] = s1;
-    o[2] = o[3] = o[4] = o[5] = 0.0;
+    for (int f = 0; f < 6; ++f) o[f] = 0.0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) o[OFF + f] = s[f];
+    if (NF == 4) {
+      const uint8_t b = bflags[i];
+      for (int f = 2; f < 6; ++f) {
+        const bool wall = f < 5 ? (b & 1) : (b & 2);
+        if (wall) o[f] = A[i * 6 + f] - (B ? B[i * 6 + f] : 0.0);
+      }
+    }
   }
 }
 
@@ -188,6 +387,7 @@ struct chns_q2 {
   int32_t *d_elem = nullptr, *d_hoff = nullptr, *d_hids = nullptr, *d_gslot = nullptr;
   double *d_hw = nullptr, *d_gw = nullptr, *d_part = nullptr;
   int64_t* d_goff = nullptr;
+  uint8_t* d_bflags = nullptr;
   int64_t bytes = 0;
 };
 
@@ -202,10 +402,11 @@ void free_q2_locked(chns_q2* q) {
   (void)hipFree(q->d_gw);
   (void)hipFree(q->d_part);
   (void)hipFree(q->d_goff);
+  (void)hipFree(q->d_bflags);
 }
 
-int q2_launch(chns_q2* q, const chns_params* params, const double* U1, const double* U0, const double* dU,
-              double* out, void* stream, int mode) {
+int q2_launch(chns_q2* q, const chns_params* params, int block, const double* U1, const double* U0,
+              const double* dU, double* out, void* stream, int mode) {
   if (!q) return fail(CHNS_EINVAL, "Q2 numbering is NULL");
   hipStream_t s = (hipStream_t)stream;
   int dev = 0;
@@ -214,16 +415,30 @@ int q2_launch(chns_q2* q, const chns_params* params, const double* U1, const dou
   dev::PhysView pv;
   int rc = phys_view(params, pv);
   if (rc) return rc;
+  if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "unknown block");
   if (!U1 || !U0 || !out || (mode == 1 && !dU)) return fail(CHNS_EINVAL, "pointers must not be NULL");
   const int64_t E = (int64_t)q->m->h.leaf_key.size(), n = (int64_t)q->h.node_key.size();
   dev::Q2View v{q->d_elem, q->m->d_level, q->d_hoff, q->d_hids, q->d_hw, E};
-  const dim3 g((unsigned)((E + 1) / 2)), b(64);
-  if (mode == 0)
-    hipLaunchKernelGGL(dev::k_q2_ch<0>, g, b, 0, s, v, pv, U1, U0, (const double*)nullptr, q->d_part);
-  else
-    hipLaunchKernelGGL(dev::k_q2_ch<1>, g, b, 0, s, v, pv, U1, U0, dU, q->d_part);
-  hipLaunchKernelGGL(dev::k_q2_gather, dim3(grid_stride(n)), dim3(256), 0, s, n, q->d_goff, q->d_gslot, q->d_gw,
-                     q->d_part, out);
+  const dim3 g((unsigned)((E + 1) / 2)), b(64), gg(grid_stride(n)), bg(256);
+  const double* nd = nullptr;
+  if (block == CHNS_BLOCK_CH) {
+    if (mode == 0)
+      hipLaunchKernelGGL(dev::k_q2_ch<0>, g, b, 0, s, v, pv, U1, U0, nd, q->d_part);
+    else
+      hipLaunchKernelGGL(dev::k_q2_ch<1>, g, b, 0, s, v, pv, U1, U0, dU, q->d_part);
+    hipLaunchKernelGGL((dev::k_q2_gather<2, 0>), gg, bg, 0, s, n, q->d_goff, q->d_gslot, q->d_gw, q->d_part,
+                       q->d_bflags, nd, nd, out);
+  } else {
+    if (mode == 0) {
+      hipLaunchKernelGGL(dev::k_q2_ns<0>, g, b, 0, s, v, pv, U1, U0, nd, q->d_part);
+      hipLaunchKernelGGL((dev::k_q2_gather<4, 2>), gg, bg, 0, s, n, q->d_goff, q->d_gslot, q->d_gw, q->d_part,
+                         q->d_bflags, U1, U0, out);
+    } else {
+      hipLaunchKernelGGL(dev::k_q2_ns<1>, g, b, 0, s, v, pv, U1, U0, dU, q->d_part);
+      hipLaunchKernelGGL((dev::k_q2_gather<4, 2>), gg, bg, 0, s, n, q->d_goff, q->d_gslot, q->d_gw, q->d_part,
+                         q->d_bflags, dU, nd, out);
+    }
+  }
   HIPCHK(hipGetLastError());
   return CHNS_OK;
 }
@@ -263,7 +478,8 @@ int chns_q2_build(chns_mesh* m, chns_q2** out, void* stream) {
     if ((rc = dalloc(&q->d_elem, H.elem.size(), B)) || (rc = dalloc(&q->d_hoff, H.hang_off.size(), B)) ||
         (rc = dalloc(&q->d_hids, H.hang_ids.size(), B)) || (rc = dalloc(&q->d_hw, H.hang_w.size(), B)) ||
         (rc = dalloc(&q->d_goff, H.g_off.size(), B)) || (rc = dalloc(&q->d_gslot, H.g_slot.size(), B)) ||
-        (rc = dalloc(&q->d_gw, H.g_w.size(), B)) || (rc = dalloc(&q->d_part, E * 27 * 2, B))) {
+        (rc = dalloc(&q->d_gw, H.g_w.size(), B)) || (rc = dalloc(&q->d_part, E * 27 * 4, B)) ||
+        (rc = dalloc(&q->d_bflags, H.bflags.size(), B))) {
       free_q2_locked(q);
       delete q;
       return rc;
@@ -271,7 +487,8 @@ int chns_q2_build(chns_mesh* m, chns_q2** out, void* stream) {
   }
   if ((rc = h2d(q->d_elem, H.elem, s)) || (rc = h2d(q->d_hoff, H.hang_off, s)) ||
       (rc = h2d(q->d_hids, H.hang_ids, s)) || (rc = h2d(q->d_hw, H.hang_w, s)) ||
-      (rc = h2d(q->d_goff, H.g_off, s)) || (rc = h2d(q->d_gslot, H.g_slot, s)) || (rc = h2d(q->d_gw, H.g_w, s))) {
+      (rc = h2d(q->d_goff, H.g_off, s)) || (rc = h2d(q->d_gslot, H.g_slot, s)) || (rc = h2d(q->d_gw, H.g_w, s)) ||
+      (rc = h2d(q->d_bflags, H.bflags, s))) {
     std::lock_guard<std::mutex> lk(g_struct_mu);
     free_q2_locked(q);
     delete q;
@@ -310,18 +527,18 @@ int chns_q2_nodes(const chns_q2* q, double* xyz) {
   return CHNS_OK;
 }
 
-int chns_q2_residual(chns_q2* q, const chns_params* params, const double* U_new, const double* U_old, double* R,
-                     void* stream) {
-  return q2_launch(q, params, U_new, U_old, nullptr, R, stream, 0);
+int chns_q2_residual(chns_q2* q, const chns_params* params, int block, const double* U_new, const double* U_old,
+                     double* R, void* stream) {
+  return q2_launch(q, params, block, U_new, U_old, nullptr, R, stream, 0);
 }
 
-int chns_q2_jvp(chns_q2* q, const chns_params* params, const double* U_new, const double* U_old, const double* dU,
-                double* JdU, void* stream) {
-  return q2_launch(q, params, U_new, U_old, dU, JdU, stream, 1);
+int chns_q2_jvp(chns_q2* q, const chns_params* params, int block, const double* U_new, const double* U_old,
+                const double* dU, double* JdU, void* stream) {
+  return q2_launch(q, params, block, U_new, U_old, dU, JdU, stream, 1);
 }
 
 int chns_q2_host_arrays(const chns_mesh* m, int64_t* sizes, int32_t* elem27, double* node_xyz, double* hang_xyz,
-                        int32_t* hang_off, int32_t* hang_ids, double* hang_w) {
+                        int32_t* hang_off, int32_t* hang_ids, double* hang_w, uint8_t* bflags) {
   if (!m || !sizes) return fail(CHNS_EINVAL, "mesh and sizes must not be NULL");
   HostQ2 H;
   std::string err;
@@ -350,6 +567,7 @@ int chns_q2_host_arrays(const chns_mesh* m, int64_t* sizes, int32_t* elem27, dou
   if (hang_off) std::copy(H.hang_off.begin(), H.hang_off.end(), hang_off);
   if (hang_ids) std::copy(H.hang_ids.begin(), H.hang_ids.end(), hang_ids);
   if (hang_w) std::copy(H.hang_w.begin(), H.hang_w.end(), hang_w);
+  if (bflags) std::copy(H.bflags.begin(), H.bflags.end(), bflags);
   return CHNS_OK;
 }
 

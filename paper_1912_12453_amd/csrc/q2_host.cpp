@@ -184,6 +184,16 @@ std::string build_host_q2(const HostMesh& h, HostQ2& out) {
     }
     out.hang_off.push_back((int32_t)out.hang_ids.size());
   }
+  // wall and pressure-pin flags (the cG(1) mesh's rules: a node on the
+  // brick's boundary; the Morton-first node)
+  out.bflags.assign(out.node_key.size(), 0);
+  for (size_t i = 0; i < out.node_key.size(); ++i) {
+    uint32_t c[3];
+    unkey(out.node_key[i], c[0], c[1], c[2]);
+    for (int d = 0; d < 3; ++d)
+      if (c[d] == 0 || (int64_t)c[d] == 2 * ext[d]) out.bflags[i] = 1;
+  }
+  if (!out.bflags.empty()) out.bflags[0] |= 2;
   // connectivity
   out.elem.resize((size_t)E * 27);
   for (int64_t e = 0; e < E; ++e) {

@@ -1,7 +1,7 @@
 """Host logic of the library's cG(2) numbering (no GPU needed): the 27 node
 refs per leaf, the node and hanging-node coordinates and the quadratic
-constraint rows equal the oracle's, bit for bit, on adaptive meshes with 2:1
-faces and edges."""
+constraint rows and the wall / pressure-pin flags equal the oracle's, bit for
+bit, on adaptive meshes with 2:1 faces and edges."""
 import numpy as np
 import pytest
 
@@ -36,5 +36,6 @@ def test_q2_numbering_matches_oracle(kind, trees, lmin, lmax, seed):
     np.testing.assert_array_equal(a["hang_off"], q.hang_off)
     np.testing.assert_array_equal(a["hang_ids"], q.hang_ids)
     np.testing.assert_array_equal(a["hang_w"], q.hang_w)
+    np.testing.assert_array_equal(a["bflags"], q.bflags)
     if kind != "rt":
         assert a["hang_xyz"].shape[0] > 0
