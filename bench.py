@@ -333,6 +333,85 @@ def serving_main(args):
     print(json.dumps(res), flush=True)
 
 
+def batching_main(args):
+    """bench.py --batching K LEVEL: the serving operator (the coupled FP32
+    JVP, chns_jvp_full) over K serving-size drop problems, applied (a) in one
+    launch over a brick of K trees holding one problem each, (b) as K
+    launches on one stream and (c) as K launches on K streams (the serving
+    loop's design).  Seeded drops as in the serving stream (1-4 per problem,
+    r ~ U(0.08, 0.2)), one physics for all."""
+    import numpy as np
+    import torch
+
+    from paper_1912_12453_amd import chns
+    from paper_1912_12453_amd import workloads as W
+    K, lmax = args.batching
+    reps = args.kernel_reps
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(4)
+    Cn = 0.01
+    probs = []
+    for _ in range(K):
+        nd, drops = int(rng.integers(1, 5)), []
+        while len(drops) < nd:
+            r = rng.uniform(0.08, 0.2)
+            c = rng.uniform(r + 0.05, 1 - r - 0.05, 3)
+            if all(np.linalg.norm(c - c2) > r + r2 + 4 * np.sqrt(2) * Cn for c2, r2 in drops):
+                drops.append((c, r))
+        probs.append(drops)
+    ph = W.Physics(Cn=Cn, Pe=1 / (3 * Cn * Cn), Re=35.0, We=10.0, Fr=1.0, rho_minus=100.0, eta_minus=10.0,
+                   dt=5e-4)
+    p = chns.make_params(ph)
+    meshes = []
+    for drops in probs:
+        m = chns.Mesh.from_spec(W.MeshSpec((1, 1, 1), 4, lmax, W.drops_phi(drops, Cn, -1.0), 0.9))
+        m.upload()
+        meshes.append(m)
+    alld = [(np.array(c) + np.array([i, 0, 0]), r) for i, drops in enumerate(probs) for c, r in drops]
+    big = chns.Mesh.from_spec(W.MeshSpec((K, 1, 1), 4, lmax, W.drops_phi(alld, Cn, -1.0), 0.9))
+    big.upload()
+
+    def tensors(m):
+        U1, U0 = W.random_state(m.n_nodes, 3, mu_sigma=0.01)
+        d = W.direction(m.n_nodes, 4)
+        return (torch.tensor(U1, device="cuda:0"), torch.tensor(U0, device="cuda:0"),
+                torch.tensor(d, dtype=torch.float32, device="cuda:0"),
+                torch.empty((m.n_nodes, 6), dtype=torch.float32, device="cuda:0"))
+    ts = [tensors(m) for m in meshes]
+    tb = tensors(big)
+    streams = [torch.cuda.Stream() for _ in meshes]
+
+    def run_big():
+        chns.chns_jvp_full(big.h, p, tb[0], tb[1], tb[2], tb[3], chns.CHNS_F32)
+
+    def run_serial():
+        for m, t in zip(meshes, ts):
+            chns.chns_jvp_full(m.h, p, t[0], t[1], t[2], t[3], chns.CHNS_F32)
+
+    def run_streams():
+        cur = torch.cuda.current_stream()
+        ev = torch.cuda.Event()
+        ev.record(cur)
+        for st, m, t in zip(streams, meshes, ts):
+            st.wait_event(ev)
+            chns.chns_jvp_full(m.h, p, t[0], t[1], t[2], t[3], chns.CHNS_F32, stream=st.cuda_stream)
+        for st in streams:
+            cur.wait_stream(st)
+    out = {"problems": K, "level_max": lmax, "leaves": [m.n_leaves for m in meshes], "brick_leaves": big.n_leaves,
+           "operator": "coupled FP32 JVP (chns_jvp_full)", "reps": reps}
+    for key, f in (("one_launch_over_brick_ms", run_big), ("k_launches_one_stream_ms", run_serial),
+                   ("k_launches_k_streams_ms", run_streams)):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        out[key] = round((time.perf_counter() - t0) / reps * 1e3, 4)
+        log(f"[batching] {key}: {out[key]} ms")
+    print(json.dumps(out), flush=True)
+
+
 def probe_main(args):
     """bench.py --probe KIND...: launches single element kernels of a workload
     (the per-chunk element loop alone), and a device copy of known size, for
@@ -408,6 +487,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving", action="store_true")
     ap.add_argument("--probe", nargs="+", metavar="KIND")
+    ap.add_argument("--batching", nargs=2, type=int, metavar=("K", "LEVEL"),
+                    help="serving operator over K problems: one launch vs K launches")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=10)
     ap.add_argument("--serve-level-min", type=int, default=6)
@@ -427,6 +508,8 @@ def main():
         sys.exit(2)
     if args.probe:
         return probe_main(args)
+    if args.batching:
+        return batching_main(args)
     if args.serving:
         return serving_main(args)
 
