@@ -444,7 +444,9 @@ int chns_q2_info(const chns_q2* q, int64_t* n_nodes, int64_t* n_hanging, int64_t
 /* Physical coordinates of the independent nodes (host, n_nodes*3). */
 int chns_q2_nodes(const chns_q2* q, double* xyz);
 /* Residual rows of a block over the Q2 nodes.  U_new, U_old, R: device,
- * node-major n_nodes*6 FP64 (phi, mu, u, v, w, p).  CH: R's fields 0, 1 (the
+ * node-major n_nodes*6 FP64 (phi, mu, u, v, w, p); the state vectors must be
+ * 16-byte aligned (node records are read as 16-byte loads), else
+ * CHNS_EINVAL.  CH: R's fields 0, 1 (the
  * velocities enter as the frozen v~ of the block iteration); NS: fields 2..5,
  * velocity rows of wall nodes v^{k+1} - v^k and the pinned pressure row
  * p^{k+1} - p^k.  The other block's fields are set to 0.  A point whose

@@ -9,12 +9,13 @@
 //
 // Device layout: one 64-lane wave per two leaves, 32 lanes per leaf (27 in
 // use).  Lane a gathers local node a's fields (through its constraint row
-// when it hangs) into LDS; lane g evaluates the fields at Gauss point g from
-// the 27 nodal values with the tensor-product basis and writes the point's
-// coefficients (c, F) to LDS; lane a then contracts them against its test
-// function.  Element results go to an E x 27 x 2 array; the gather kernel
-// sums them per node through the host-built fixed-order plan (leaf, local
-// node, constraint weight), so the result does not depend on scheduling.
+// when it hangs) into LDS; the fields are evaluated at the 27 Gauss points
+// (CH: sum factorisation, three 3-term passes; NS: 27-term sums with the
+// tensor-product basis, Hessians included), each point's coefficients (c, F)
+// go to LDS, and lane a contracts them against its test function.  Element
+// results go to an E x 27 x NF array; the gather kernel sums them per node
+// through the host-built fixed-order plan (leaf, local node, constraint
+// weight), so the result does not depend on scheduling.
 // Included by capi.hip.
 
 namespace chns {
@@ -45,71 +46,132 @@ struct Q2View {
   int64_t E;
 };
 
+// The six fields of a node (or, for a hanging node, its constraint row's
+// combination) as three 16-byte loads per node record: the row's ids and
+// weights are read once for all fields.  Node records are 48 bytes, so a
+// 16-byte aligned vector keeps every record 16-byte aligned.
+__device__ __forceinline__ void q2_load6(const double* __restrict__ U, int64_t id, double (&o)[6]) {
+  const double2* r = reinterpret_cast<const double2*>(U + id * 6);
+  const double2 x = r[0], y = r[1], z = r[2];
+  o[0] = x.x;
+  o[1] = x.y;
+  o[2] = y.x;
+  o[3] = y.y;
+  o[4] = z.x;
+  o[5] = z.y;
+}
+__device__ __forceinline__ void q2_node6(const Q2View& q, int32_t ref, const double* __restrict__ U,
+                                         double (&o)[6]) {
+  if (ref >= 0) {
+    q2_load6(U, ref, o);
+    return;
+  }
+  const int32_t hh = -1 - ref;
+  for (int f = 0; f < 6; ++f) o[f] = 0.0;
+  for (int32_t t = q.hoff[hh]; t < q.hoff[hh + 1]; ++t) {
+    double v[6];
+    q2_load6(U, q.hids[t], v);
+    const double w = q.hw[t];
+    for (int f = 0; f < 6; ++f) o[f] += w * v[f];
+  }
+}
+
 // second derivative d2/du2 of the basis on [0, 1] with nodes 0, 1/2, 1
 __device__ __forceinline__ double q2_basis_dd(int i) { return i == 1 ? -8.0 : 4.0; }
 
-__device__ __forceinline__ double q2_node(const Q2View& q, int32_t ref, const double* __restrict__ U, int f) {
-  if (ref >= 0) return U[(int64_t)ref * 6 + f];
-  const int32_t hh = -1 - ref;
-  double s = 0.0;
-  for (int32_t t = q.hoff[hh]; t < q.hoff[hh + 1]; ++t) s += q.hw[t] * U[(int64_t)q.hids[t] * 6 + f];
-  return s;
-}
 
 // MODE 0: residual rows; MODE 1: Jacobian rows applied to dU (phi, mu parts).
+// Sum factorisation on the tensor-product lattice: the 27-point evaluation
+// is three passes of 3-term sums, one axis at a time (x, then y, then z),
+// and the contraction the same passes transposed (z, y, x).  Lane l of a
+// leaf stands for the index triple (l % 3, l / 3 % 3, l / 9) of the pass;
+// each pass reads the previous one's LDS array and writes the next, so one
+// leaf needs two LDS buffers of 12 x 27 values.
 template <int MODE>
 __global__ __launch_bounds__(64) void k_q2_ch(Q2View q, PhysView p, const double* __restrict__ U1,
                                               const double* __restrict__ U0, const double* __restrict__ dU,
                                               double* __restrict__ part) {
-  __shared__ double sn[2][6][27];  // per leaf: three scalar fields and v~ at the nodes
-  __shared__ double sq[2][8][27];  // per leaf: c and F of the two rows at the points
+  __shared__ double sa[2][12][27];
+  __shared__ double sb[2][12][27];
   const int half = threadIdx.x >> 5, lane = threadIdx.x & 31;
   const int64_t e0 = (int64_t)blockIdx.x * 2 + half;
   const bool live = e0 < q.E;
   const int64_t e = live ? e0 : q.E - 1;
   const int lev = q.level[e];
   const double h = ldexp(1.0, -lev), ih = ldexp(1.0, lev);
-  if (lane < 27) {
-    const int32_t ref = q.elem[e * 27 + lane];
-    const double p1 = q2_node(q, ref, U1, 0), p0 = q2_node(q, ref, U0, 0);
-    sn[half][0][lane] = 0.5 * (p1 + p0);  // phi~
-    if (MODE == 0) {
-      sn[half][1][lane] = 0.5 * (q2_node(q, ref, U1, 1) + q2_node(q, ref, U0, 1));  // mu~
-      sn[half][2][lane] = p1 - p0;                                                  // phi^{k+1} - phi^k
-    } else {
-      sn[half][1][lane] = q2_node(q, ref, dU, 1);  // d mu^{k+1}
-      sn[half][2][lane] = q2_node(q, ref, dU, 0);  // d phi^{k+1}
+  // B[g][i], Dh[g][i]: basis i and its physical derivative at Gauss coordinate g
+  double B[3][3], Dh[3][3];
+  for (int g = 0; g < 3; ++g) {
+    double b[3], d[3];
+    q2_basis_1d(q2_gauss_u(g), b, d);
+    for (int i = 0; i < 3; ++i) {
+      B[g][i] = b[i];
+      Dh[g][i] = d[i] * ih;
     }
-    for (int d = 0; d < 3; ++d)
-      sn[half][3 + d][lane] = 0.5 * (q2_node(q, ref, U1, 2 + d) + q2_node(q, ref, U0, 2 + d));
+  }
+  const bool act = lane < 27;
+  const int p0 = lane % 3, p1 = (lane / 3) % 3, p2 = lane / 9;
+  double (*A)[27] = sa[half];
+  double (*C)[27] = sb[half];
+  // nodal fields: 0 phi~, 1 mu~ (residual) or d mu^{k+1} (JVP), 2 phi^{k+1} - phi^k
+  // (residual) or d phi^{k+1} (JVP), 3..5 v~
+  if (act) {
+    const int32_t ref = q.elem[e * 27 + lane];
+    double a1[6], a0[6];
+    q2_node6(q, ref, U1, a1);
+    q2_node6(q, ref, U0, a0);
+    A[0][lane] = 0.5 * (a1[0] + a0[0]);
+    if (MODE == 0) {
+      A[1][lane] = 0.5 * (a1[1] + a0[1]);
+      A[2][lane] = a1[0] - a0[0];
+    } else {
+      double dd[6];
+      q2_node6(q, ref, dU, dd);
+      A[1][lane] = dd[1];
+      A[2][lane] = dd[0];
+    }
+    for (int d = 0; d < 3; ++d) A[3 + d][lane] = 0.5 * (a1[2 + d] + a0[2 + d]);
   }
   __syncthreads();
-  if (lane < 27) {
-    const int g0 = lane % 3, g1 = (lane / 3) % 3, g2 = lane / 9;
-    double bx[3], dx[3], by[3], dy[3], bz[3], dz[3];
-    q2_basis_1d(q2_gauss_u(g0), bx, dx);
-    q2_basis_1d(q2_gauss_u(g1), by, dy);
-    q2_basis_1d(q2_gauss_u(g2), bz, dz);
-    double val[3] = {0.0, 0.0, 0.0}, grd[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int a = 0; a < 27; ++a) {
-      const int i = a % 3, j = (a / 3) % 3, k = a / 9;
-      const double yz = by[j] * bz[k];
-      const double N = bx[i] * yz, Nx = dx[i] * yz * ih, Ny = bx[i] * dy[j] * bz[k] * ih,
-                   Nz = bx[i] * by[j] * dz[k] * ih;
-#pragma unroll
-      for (int f = 0; f < 3; ++f) {
-        const double u = sn[half][f][a];
-        val[f] += N * u;
-        grd[f][0] += Nx * u;
-        grd[f][1] += Ny * u;
-        grd[f][2] += Nz * u;
-      }
-#pragma unroll
-      for (int d = 0; d < 3; ++d) v[d] += N * sn[half][3 + d][a];
+  // x pass, lane (g0, j, k): values of all six fields, x-derivatives of the first three
+  if (act) {
+    for (int f = 0; f < 6; ++f) {
+      const double* u = A[f] + 3 * p1 + 9 * p2;
+      C[f][lane] = B[p0][0] * u[0] + B[p0][1] * u[1] + B[p0][2] * u[2];
+      if (f < 3) C[6 + f][lane] = Dh[p0][0] * u[0] + Dh[p0][1] * u[1] + Dh[p0][2] * u[2];
     }
-    const double w = q2_gauss_w(g0) * q2_gauss_w(g1) * q2_gauss_w(g2) * h * h * h;
+  }
+  __syncthreads();
+  // y pass, lane (g0, g1, k): values; y-derivatives of values; x-derivatives carried
+  if (act) {
+    for (int f = 0; f < 6; ++f) {
+      const double* u = C[f] + p0 + 9 * p2;
+      A[f][lane] = B[p1][0] * u[0] + B[p1][1] * u[3] + B[p1][2] * u[6];
+      if (f < 3) {
+        A[6 + f][lane] = Dh[p1][0] * u[0] + Dh[p1][1] * u[3] + Dh[p1][2] * u[6];
+        const double* t = C[6 + f] + p0 + 9 * p2;
+        A[9 + f][lane] = B[p1][0] * t[0] + B[p1][1] * t[3] + B[p1][2] * t[6];
+      }
+    }
+  }
+  __syncthreads();
+  // z pass at Gauss point (g0, g1, g2), then the point's coefficients
+  if (act) {
+    double val[6], grd[3][3];
+    for (int f = 0; f < 6; ++f) {
+      const double* u = A[f] + p0 + 3 * p1;
+      val[f] = B[p2][0] * u[0] + B[p2][1] * u[9] + B[p2][2] * u[18];
+      if (f < 3) {
+        const double* ty = A[6 + f] + p0 + 3 * p1;
+        const double* tx = A[9 + f] + p0 + 3 * p1;
+        grd[f][0] = B[p2][0] * tx[0] + B[p2][1] * tx[9] + B[p2][2] * tx[18];
+        grd[f][1] = B[p2][0] * ty[0] + B[p2][1] * ty[9] + B[p2][2] * ty[18];
+        grd[f][2] = Dh[p2][0] * u[0] + Dh[p2][1] * u[9] + Dh[p2][2] * u[18];
+      }
+    }
+    const double w = q2_gauss_w(p0) * q2_gauss_w(p1) * q2_gauss_w(p2) * h * h * h;
     const double kd = p.inv_PeCn, cn2 = p.Cn2, pt = val[0];
+    const double v[3] = {val[3], val[4], val[5]};
     double c0, c1, F0[3], F1[3];
     if (MODE == 0) {
       // (q, (phi^{k+1}-phi^k)/dt) - (grad q, v~ phi~) + 1/(Pe Cn) (grad q, grad mu~)
@@ -129,37 +191,59 @@ __global__ __launch_bounds__(64) void k_q2_ch(Q2View q, PhysView p, const double
         F1[d] = cn2 * 0.5 * grd[2][d];
       }
     }
-    sq[half][0][lane] = w * c0;
-    sq[half][4][lane] = w * c1;
+    C[0][lane] = w * c0;
+    C[4][lane] = w * c1;
     for (int d = 0; d < 3; ++d) {
-      sq[half][1 + d][lane] = w * F0[d];
-      sq[half][5 + d][lane] = w * F1[d];
+      C[1 + d][lane] = w * F0[d];
+      C[5 + d][lane] = w * F1[d];
     }
   }
   __syncthreads();
-  if (lane < 27 && live) {
-    const int ia = lane % 3, ja = (lane / 3) % 3, ka = lane / 9;
-    double cx[3], cy[3], cz[3], ex[3], ey[3], ez[3];
-    for (int g = 0; g < 3; ++g) {
-      double b[3], d[3];
-      q2_basis_1d(q2_gauss_u(g), b, d);
-      cx[g] = b[ia];
-      ex[g] = d[ia] * ih;
-      cy[g] = b[ja];
-      ey[g] = d[ja] * ih;
-      cz[g] = b[ka];
-      ez[g] = d[ka] * ih;
+  // transposed z pass, lane (g0, g1, k): per row r, the terms with factor
+  // N_x N_y (c and F_z), N_x' N_y (F_x) and N_x N_y' (F_y)
+  if (act) {
+    for (int r = 0; r < 2; ++r) {
+      const double* c = C[4 * r] + p0 + 3 * p1;
+      const double* fx = C[4 * r + 1] + p0 + 3 * p1;
+      const double* fy = C[4 * r + 2] + p0 + 3 * p1;
+      const double* fz = C[4 * r + 3] + p0 + 3 * p1;
+      double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int g2 = 0; g2 < 3; ++g2) {
+        s1 += B[g2][p2] * c[9 * g2] + Dh[g2][p2] * fz[9 * g2];
+        s2 += B[g2][p2] * fx[9 * g2];
+        s3 += B[g2][p2] * fy[9 * g2];
+      }
+      A[3 * r][lane] = s1;
+      A[3 * r + 1][lane] = s2;
+      A[3 * r + 2][lane] = s3;
     }
-    double r0 = 0.0, r1 = 0.0;
-    for (int g = 0; g < 27; ++g) {
-      const int g0 = g % 3, g1 = (g / 3) % 3, g2 = g / 9;
-      const double N = cx[g0] * cy[g1] * cz[g2], Nx = ex[g0] * cy[g1] * cz[g2], Ny = cx[g0] * ey[g1] * cz[g2],
-                   Nz = cx[g0] * cy[g1] * ez[g2];
-      r0 += N * sq[half][0][g] + Nx * sq[half][1][g] + Ny * sq[half][2][g] + Nz * sq[half][3][g];
-      r1 += N * sq[half][4][g] + Nx * sq[half][5][g] + Ny * sq[half][6][g] + Nz * sq[half][7][g];
+  }
+  __syncthreads();
+  // transposed y pass, lane (g0, j, k)
+  if (act) {
+    for (int r = 0; r < 2; ++r) {
+      const double* t1 = A[3 * r] + p0 + 9 * p2;
+      const double* t2 = A[3 * r + 1] + p0 + 9 * p2;
+      const double* t3 = A[3 * r + 2] + p0 + 9 * p2;
+      double s1 = 0.0, s2 = 0.0;
+      for (int g1 = 0; g1 < 3; ++g1) {
+        s1 += B[g1][p1] * t1[3 * g1] + Dh[g1][p1] * t3[3 * g1];
+        s2 += B[g1][p1] * t2[3 * g1];
+      }
+      C[2 * r][lane] = s1;
+      C[2 * r + 1][lane] = s2;
     }
-    part[(e * 27 + lane) * 2] = r0;
-    part[(e * 27 + lane) * 2 + 1] = r1;
+  }
+  __syncthreads();
+  // transposed x pass, lane = node (i, j, k)
+  if (act && live) {
+    for (int r = 0; r < 2; ++r) {
+      const double* t1 = C[2 * r] + 3 * p1 + 9 * p2;
+      const double* t2 = C[2 * r + 1] + 3 * p1 + 9 * p2;
+      double s = 0.0;
+      for (int g0 = 0; g0 < 3; ++g0) s += B[g0][p0] * t1[g0] + Dh[g0][p0] * t2[g0];
+      part[(e * 27 + lane) * 2 + r] = s;
+    }
   }
 }
 
@@ -182,18 +266,22 @@ __global__ __launch_bounds__(64) void k_q2_ns(Q2View q, PhysView p, const double
   const double h = ldexp(1.0, -lev), ih = ldexp(1.0, lev), ih2 = ih * ih;
   if (lane < 27) {
     const int32_t ref = q.elem[e * 27 + lane];
-    const double f1 = q2_node(q, ref, U1, 0), f0 = q2_node(q, ref, U0, 0);
-    sn[half][0][lane] = f1;                                                          // phi^{k+1}
-    sn[half][1][lane] = 0.5 * (f1 + f0);                                             // phi~
-    sn[half][2][lane] = 0.5 * (q2_node(q, ref, U1, 1) + q2_node(q, ref, U0, 1));     // mu~
+    double a1[6], a0[6];
+    q2_node6(q, ref, U1, a1);
+    q2_node6(q, ref, U0, a0);
+    sn[half][0][lane] = a1[0];                       // phi^{k+1}
+    sn[half][1][lane] = 0.5 * (a1[0] + a0[0]);       // phi~
+    sn[half][2][lane] = 0.5 * (a1[1] + a0[1]);       // mu~
     for (int d = 0; d < 3; ++d) {
-      const double a = q2_node(q, ref, U1, 2 + d), b = q2_node(q, ref, U0, 2 + d);
-      sn[half][3 + d][lane] = 0.5 * (a + b);  // v~
-      sn[half][6 + d][lane] = a - b;          // v^{k+1} - v^k
+      sn[half][3 + d][lane] = 0.5 * (a1[2 + d] + a0[2 + d]);  // v~
+      sn[half][6 + d][lane] = a1[2 + d] - a0[2 + d];          // v^{k+1} - v^k
     }
-    sn[half][9][lane] = 0.5 * (q2_node(q, ref, U1, 5) + q2_node(q, ref, U0, 5));  // p~
-    if (MODE == 1)
-      for (int d = 0; d < 4; ++d) sn[half][10 + d][lane] = q2_node(q, ref, dU, 2 + d);  // dv, dp
+    sn[half][9][lane] = 0.5 * (a1[5] + a0[5]);  // p~
+    if (MODE == 1) {
+      double dd[6];
+      q2_node6(q, ref, dU, dd);
+      for (int d = 0; d < 4; ++d) sn[half][10 + d][lane] = dd[2 + d];  // dv, dp
+    }
   }
   __syncthreads();
   if (lane < 27) {
@@ -417,6 +505,9 @@ int q2_launch(chns_q2* q, const chns_params* params, int block, const double* U1
   if (rc) return rc;
   if (block != CHNS_BLOCK_CH && block != CHNS_BLOCK_NS) return fail(CHNS_EINVAL, "unknown block");
   if (!U1 || !U0 || !out || (mode == 1 && !dU)) return fail(CHNS_EINVAL, "pointers must not be NULL");
+  auto misaligned = [](const void* ptr) { return ((uintptr_t)ptr & 15) != 0; };
+  if (misaligned(U1) || misaligned(U0) || (mode == 1 && misaligned(dU)))
+    return fail(CHNS_EINVAL, "state vectors must be 16-byte aligned");
   const int64_t E = (int64_t)q->m->h.leaf_key.size(), n = (int64_t)q->h.node_key.size();
   dev::Q2View v{q->d_elem, q->m->d_level, q->d_hoff, q->d_hids, q->d_hw, E};
   const dim3 g((unsigned)((E + 1) / 2)), b(64), gg(grid_stride(n)), bg(256);
