@@ -312,7 +312,7 @@ int upload(chns_mesh* m, hipStream_t s) {
       (rc = dalloc(&m->d_anchor, E * 3, &B)) || (rc = dalloc(&m->d_hoff, NH + 1, &B)) ||
       (rc = dalloc(&m->d_hids, NC, &B)) || (rc = dalloc(&m->d_hw, NC, &B)) ||
       (rc = dalloc(&m->d_hw32, NC, &B)) || (rc = dalloc(&m->d_flag, 1, &B)) ||
-      (rc = dalloc(&m->d_part, E * 2, &B)) || (rc = dalloc(&m->d_sum, 2, &B)) ||
+      (rc = dalloc(&m->d_part, (int64_t)dev::diag_blocks(E) * 2, &B)) || (rc = dalloc(&m->d_sum, 2, &B)) ||
       (rc = dalloc(&m->d_tgt_off, P.tgt_off.size(), &B)) || (rc = dalloc(&m->d_tgt, P.tgt.size(), &B)) ||
       (rc = dalloc(&m->d_inc_off, P.inc_off.size(), &B)) ||
       (rc = dalloc(&m->d_chunk_inc, P.chunk_inc.size(), &B)) ||
@@ -572,9 +572,10 @@ int launch_diagnostics(chns_mesh* m, const dev::PhysView& pv, const double* U, d
                        double* energy, hipStream_t s) {
   const int64_t E = (int64_t)m->h.leaf_key.size();
   const auto mv = view(m);
-  hipLaunchKernelGGL(dev::k_diagnostics, dim3(grid_for(E * 8)), dim3(256), 0, s, mv, pv, m->d_anchor,
+  const int nb = dev::diag_blocks(E);
+  hipLaunchKernelGGL(dev::k_diagnostics, dim3(nb), dim3(256), 0, s, mv, pv, m->d_anchor,
                      std::ldexp(1.0, -m->h.D), U, m->d_part);
-  hipLaunchKernelGGL(dev::k_finish_sum, dim3(2), dim3(256), 0, s, m->d_part, (int)E, 2, m->d_sum,
+  hipLaunchKernelGGL(dev::k_finish_sum, dim3(2), dim3(256), 0, s, m->d_part, nb, 2, m->d_sum,
                      (const int*)nullptr);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(m->h_sum, m->d_sum, 2 * sizeof(double), hipMemcpyDeviceToHost, s));

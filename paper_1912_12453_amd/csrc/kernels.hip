@@ -1270,37 +1270,61 @@ __global__ __launch_bounds__(256) void k_diag(MeshView m, PlanView pl, PhysView 
 }
 
 // ------------------------------------------------------- diagnostics ----
-// Per-element sums of phi and of the energy density at the Gauss points;
-// the element totals are reduced by k_reduce_sum in a fixed order.
+// Sums of phi and of the energy density over the Gauss points.  A workgroup
+// takes 32 elements at a time (8 lanes each) and walks the mesh with stride
+// 32 * gridDim.x; each lane group adds its element totals in element order,
+// then lane 0 adds the 32 groups in order: part[b] (mass) and
+// part[gridDim.x + b] (energy) for workgroup b, summed by k_finish_sum.
+constexpr int kDiagBlocks = 2048;  // most workgroups of k_diagnostics
+__host__ __device__ inline int diag_blocks(int64_t E) {
+  return (int)(E < (int64_t)kDiagBlocks * 32 ? (E + 31) / 32 : kDiagBlocks);
+}
+
 __global__ __launch_bounds__(256) void k_diagnostics(MeshView m, PhysView p,
                                                      const int32_t* __restrict__ anchor,
                                                      double unit, const double* __restrict__ U,
                                                      double* __restrict__ part) {
-  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
-  const bool valid = e0 < m.E;
-  const int64_t e = valid ? e0 : m.E - 1;
-  Lane<double> L;
-  L.init(threadIdx.x & 7, m.level[e]);
-  const int ref = m.elem[e * 8 + L.c];
-  double a[5];
-  gather<double, double, 5>(m, ref, U, 6, 0, a);
-  const VG<double> ph = eval_vg<double>(a[0], L);
-  const double vx = eval_v<double>(a[2]), vy = eval_v<double>(a[3]), vz = eval_v<double>(a[4]);
-  // Gauss point position: anchor + h (1 + s g)/2 per axis
-  const double x = anchor[e * 3 + 0] * unit + 0.5 * L.h * (1.0 + (L.sxh > 0 ? kGauss : -kGauss));
-  const double y = anchor[e * 3 + 1] * unit + 0.5 * L.h * (1.0 + (L.syh > 0 ? kGauss : -kGauss));
-  const double z = anchor[e * 3 + 2] * unit + 0.5 * L.h * (1.0 + (L.szh > 0 ? kGauss : -kGauss));
-  const double rho = p.alpha * clamp1(ph.v) + p.beta;
-  const double psi = 0.25 * (ph.v * ph.v - 1.0) * (ph.v * ph.v - 1.0);
-  const double g2 = ph.dx * ph.dx + ph.dy * ph.dy + ph.dz * ph.dz;
-  const double en = 0.5 * rho * (vx * vx + vy * vy + vz * vz) +
-                    p.inv_Fr * rho * -(p.g[0] * x + p.g[1] * y + p.g[2] * z);
-  const double fe = (psi + 0.5 * p.Cn2 * g2) * p.inv_We / p.Cn;
-  const double mass = group_sum<double>(L.wdet * ph.v);
-  const double energy = group_sum<double>(L.wdet * (en + fe));
-  if (valid && (threadIdx.x & 7) == 0) {
-    part[e0] = mass;
-    part[m.E + e0] = energy;
+  __shared__ double sh[2][32];
+  double am = 0, ae = 0;
+  // the loop bound is the same for the whole workgroup: every lane takes part
+  // in the exchanges of group_sum
+  for (int64_t base = (int64_t)blockIdx.x * 32; base < m.E; base += (int64_t)gridDim.x * 32) {
+    const int64_t e0 = base + (threadIdx.x >> 3);
+    const bool valid = e0 < m.E;
+    const int64_t e = valid ? e0 : m.E - 1;
+    Lane<double> L;
+    L.init(threadIdx.x & 7, m.level[e]);
+    const int ref = m.elem[e * 8 + L.c];
+    double a[5];
+    gather<double, double, 5>(m, ref, U, 6, 0, a);
+    const VG<double> ph = eval_vg<double>(a[0], L);
+    const double vx = eval_v<double>(a[2]), vy = eval_v<double>(a[3]), vz = eval_v<double>(a[4]);
+    // Gauss point position: anchor + h (1 + s g)/2 per axis
+    const double x = anchor[e * 3 + 0] * unit + 0.5 * L.h * (1.0 + (L.sxh > 0 ? kGauss : -kGauss));
+    const double y = anchor[e * 3 + 1] * unit + 0.5 * L.h * (1.0 + (L.syh > 0 ? kGauss : -kGauss));
+    const double z = anchor[e * 3 + 2] * unit + 0.5 * L.h * (1.0 + (L.szh > 0 ? kGauss : -kGauss));
+    const double rho = p.alpha * clamp1(ph.v) + p.beta;
+    const double psi = 0.25 * (ph.v * ph.v - 1.0) * (ph.v * ph.v - 1.0);
+    const double g2 = ph.dx * ph.dx + ph.dy * ph.dy + ph.dz * ph.dz;
+    const double en = 0.5 * rho * (vx * vx + vy * vy + vz * vz) +
+                      p.inv_Fr * rho * -(p.g[0] * x + p.g[1] * y + p.g[2] * z);
+    const double fe = (psi + 0.5 * p.Cn2 * g2) * p.inv_We / p.Cn;
+    const double mass = group_sum<double>(L.wdet * ph.v);
+    const double energy = group_sum<double>(L.wdet * (en + fe));
+    if (valid) {
+      am += mass;
+      ae += energy;
+    }
+  }
+  if ((threadIdx.x & 7) == 0) {
+    sh[0][threadIdx.x >> 3] = am;
+    sh[1][threadIdx.x >> 3] = ae;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0;
+    for (int g = 0; g < 32; ++g) t += sh[threadIdx.x][g];
+    part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
   }
 }
 

@@ -29,7 +29,7 @@ int64_t mesh_footprint(const chns_mesh* m) {
   auto sz = [](size_t count, size_t elem) { return (int64_t)(std::max<size_t>(count, 1) * elem); };
   const size_t E = h.leaf_key.size(), NH = h.hang_key.size(), NC = h.hang_ids.size();
   return sz(E * 8, 4) + sz(E, 1) + sz(E * 3, 4) + sz(NH + 1, 4) + sz(NC, 4) + sz(NC, 8) + sz(NC, 4) +
-         sz(1, 4) + sz(E * 2, 8) + sz(2, 8) + sz(P.tgt_off.size(), 4) + sz(P.tgt.size(), 4) +
+         sz(1, 4) + sz((size_t)dev::diag_blocks((int64_t)E) * 2, 8) + sz(2, 8) + sz(P.tgt_off.size(), 4) + sz(P.tgt.size(), 4) +
          sz(P.inc_off.size(), 4) + sz(P.chunk_inc.size(), 4) + sz(P.inc_corner.size(), 1) +
          sz(P.inc_w.size(), 4) +
          sz(P.node_off.size(), 4) + sz(P.node_slot.size(), 4) + sz(P.touch_off.size(), 8) + sz(P.touch_node.size(), 4) +
