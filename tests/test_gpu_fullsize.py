@@ -81,3 +81,17 @@ def test_fullsize_jvp_rows(setup, orc, block):
           f"oracle change under FP32 perturbations {ch:.1e})", flush=True)
     assert e < 1e-12
     assert e32 < tol32
+
+
+def test_fullsize_diagnostics(setup, orc):
+    """The integral of phi (Prop. 1) and E_tot (Sec. 2) over the whole mesh:
+    at this size the device reduction walks the mesh in several passes per
+    workgroup, so its summation order differs from the oracle's."""
+    S = setup
+    t, c = S["torch"], S["chns"]
+    d1 = t.tensor(S["U1"], device="cuda:0")
+    m, e = S["pm"].diagnostics(c.make_params(S["w"].physics), d1)
+    mo, eo = S["om"].diagnostics(orc.Params.make(**vars(S["w"].physics)), S["U1"])
+    print(f"fullsize diagnostics: mass {m:.15e} vs {mo:.15e}, energy {e:.15e} vs {eo:.15e}", flush=True)
+    assert abs(m - mo) <= 1e-12 * abs(mo)
+    assert abs(e - eo) <= 1e-12 * abs(eo)
