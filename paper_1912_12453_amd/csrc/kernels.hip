@@ -284,6 +284,40 @@ struct NSPoint {
   bool ok;           // tau_m bracket positive
 };
 
+// 1/x and 1/sqrt(x) for the point quantities (x > 0 and far from the
+// exponent limits here).  FP64: the hardware estimate (v_rcp_f64, v_rsq_f64)
+// refined by two Newton steps, r <- r + r (1 - x r) and y <- y + y (1/2 -
+// (x/2) y^2), each of which squares the relative error; the result is within
+// about an ulp of the rounded quotient, where a correctly rounded division or
+// square root takes two to three times the instructions.  FP32: the
+// hardware's 1-ulp instructions.  Other types (the dual numbers of the
+// coupled rows) keep the plain expressions.
+template <class T>
+__device__ __forceinline__ T recip_nr(const T& x) {
+  return (T)1 / x;
+}
+template <class T>
+__device__ __forceinline__ T rsqrt_nr(const T& x) {
+  return (T)1 / sqrt(x);
+}
+__device__ __forceinline__ double recip_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float recip_nr(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  double t = fma(-hx * y, y, 0.5);
+  y = fma(y, t, y);
+  t = fma(-hx * y, y, 0.5);
+  return fma(y, t, y);
+}
+__device__ __forceinline__ float rsqrt_nr(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // rho, eta (linear in the pulled-back phi) and 1/rho.  The point evaluation
 // and the cached linearisation share this code, so both get the same values.
 template <class T>
@@ -291,7 +325,7 @@ __device__ __forceinline__ void ns_material(const PhysView& p, T ps, NSPoint<T>&
   P.ps = ps;
   P.rho = (T)p.alpha * ps + (T)p.beta;
   P.eta = (T)p.gamma * ps + (T)p.xi;
-  P.inv_rho = (T)1 / P.rho;
+  P.inv_rho = recip_nr(P.rho);
 }
 
 // R_c, the metric Gh = 4/h^2 and the stabilisation parameters tau_m, tau_c
@@ -307,9 +341,9 @@ __device__ __forceinline__ void ns_stab(const PhysView& p, const Lane<T>& L, NSP
   const T br = (T)4 * idt * idt + P.Gh * vv + P.Gh * vJ * P.inv_rho * iPe +
                (T)p.C_I * nu * nu * (T)3 * P.Gh * P.Gh;
   P.ok = br > (T)0;
-  P.sbr = sqrt(br);
-  P.tau_m = (T)1 / P.sbr;
-  P.tau_c = (T)1 / ((T)3 * P.Gh * P.tau_m);
+  P.tau_m = rsqrt_nr(br);
+  P.sbr = br * P.tau_m;  // 1/tau_m
+  P.tau_c = P.sbr * recip_nr((T)3 * P.Gh);
 }
 
 // Linearisation point from the lane's corner values of U^{k+1} (a) and U^k (b),
