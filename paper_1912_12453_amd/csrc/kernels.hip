@@ -290,8 +290,8 @@ struct NSPoint {
 // (x/2) y^2), each of which squares the relative error; the result is within
 // about an ulp of the rounded quotient, where a correctly rounded division or
 // square root takes two to three times the instructions.  FP32: the
-// hardware's 1-ulp instructions.  Other types (the dual numbers of the
-// coupled rows) keep the plain expressions.
+// hardware's 1-ulp instructions; dual numbers (the coupled rows) take the
+// derivative of the same value.
 template <class T>
 __device__ __forceinline__ T recip_nr(const T& x) {
   return (T)1 / x;
@@ -317,6 +317,17 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return fma(y, t, y);
 }
 __device__ __forceinline__ float rsqrt_nr(float x) { return __builtin_amdgcn_rsqf(x); }
+// dual numbers: (1/x)' = -x'/x^2, (x^-1/2)' = -x' x^-3/2 / 2
+template <class T>
+__device__ __forceinline__ Dual<T> recip_nr(const Dual<T>& x) {
+  const T r = recip_nr(x.v);
+  return Dual<T>(r, -x.d * r * r);
+}
+template <class T>
+__device__ __forceinline__ Dual<T> rsqrt_nr(const Dual<T>& x) {
+  const T y = rsqrt_nr(x.v);
+  return Dual<T>(y, (T)-0.5 * x.d * y * y * y);
+}
 
 // rho, eta (linear in the pulled-back phi) and 1/rho.  The point evaluation
 // and the cached linearisation share this code, so both get the same values.
