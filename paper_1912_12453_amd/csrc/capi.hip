@@ -733,7 +733,7 @@ struct Solver {
           (rc = dalloc(&w.DiC32, n * 4, &B)) || (rc = dalloc(&w.pk64, n * 4, &B)) ||
           (rc = dalloc(&w.pz64, n * 4, &B)) || (rc = dalloc(&w.pk32, n * 4, &B)) ||
           (rc = dalloc(&w.pz32, n * 4, &B)) ||
-          (rc = dalloc(&w.part, (size_t)w.nb_part * (dev::kMaxBasis + 1), &B)) ||
+          (rc = dalloc(&w.part, (size_t)w.nb_part * (2 * dev::kMaxBasis + 2), &B)) ||
           (rc = dalloc(&w.dots, dev::kMaxBasis + 1, &B)) || (rc = dalloc(&w.flag, 1, &B)) ||
           (rc = dalloc(&w.ctl, 1, &B))) {
         free_workspace(w);
@@ -948,22 +948,14 @@ struct Solver {
     for (int k = k0; k < k1; ++k) {
       TV* Vk = V + (int64_t)k * N;
       TV* Zk = Z + (int64_t)k * N;
-      const dim3 gp(w.nb_part, (k + dev::kDotTile) / dev::kDotTile);  // ceil((k + 1) / tile)
+      const dim3 gp(w.nb_part, std::max(1, (k + dev::kDcTile - 1) / dev::kDcTile));
       if ((rc = precondition<TV>(block, Vk, Zk, idle, U1, U0))) return rc;
       if ((rc = apply<TV>(block, Zk, wv, U1, U0, idle))) return rc;
-      hipLaunchKernelGGL(dev::k_multidot<TV>, gp, b, 0, s, V, N, k + 1, wv, N, w.part, idle);
-      hipLaunchKernelGGL(dev::k_finish_sum, dim3(k + 1), b, 0, s, w.part, w.nb_part, k + 1, C->h1, idle);
-      if (k + 1 <= dev::kDotTile) {  // one sweep: w -= V h1 and the second pass's V^T w
-        hipLaunchKernelGGL(dev::k_axpy_multidot<TV>, dim3(w.nb_part), b, 0, s, wv, V, N, k + 1, C->h1, N, w.part,
-                           idle);
-      } else {
-        hipLaunchKernelGGL(dev::k_multi_axpy<TV>, gs, b, 0, s, wv, V, N, k + 1, C->h1, N, idle);
-        hipLaunchKernelGGL(dev::k_multidot<TV>, gp, b, 0, s, V, N, k + 1, wv, N, w.part, idle);
-      }
-      hipLaunchKernelGGL(dev::k_finish_sum, dim3(k + 1), b, 0, s, w.part, w.nb_part, k + 1, C->h2, idle);
-      hipLaunchKernelGGL(dev::k_axpy_norm<TV>, dim3(w.nb_part), b, 0, s, wv, V, N, k + 1, C->h2, N, w.part,
-                         idle);
-      hipLaunchKernelGGL(dev::k_arnoldi_close, dim3(1), b, 0, s, C, k, w.part, w.nb_part);
+      hipLaunchKernelGGL(dev::k_dc_dots<TV>, gp, b, 0, s, V, N, k, (const int*)nullptr, wv, N, w.part, idle);
+      hipLaunchKernelGGL(dev::k_finish_sum, dim3(2 * k + 2), b, 0, s, w.part, w.nb_part, 2 * k + 2, C->dsum, idle);
+      hipLaunchKernelGGL(dev::k_dc_coef, dim3(1), b, 0, s, C, k);
+      hipLaunchKernelGGL(dev::k_dc_update<TV>, dim3(w.nb_part), b, 0, s, V, N, k, wv, N, C, w.part, idle);
+      hipLaunchKernelGGL(dev::k_dc_norm, dim3(1), b, 0, s, C, k, w.part, w.nb_part);
       hipLaunchKernelGGL(dev::k_scale_dev<TV>, gs, b, 0, s, V + (int64_t)(k + 1) * N, wv, &C->inv_scale, N,
                          idle);
     }
@@ -979,6 +971,14 @@ struct Solver {
     const int* fin = &C->finished;
     const dim3 gs(grid_stride(N)), b(256);
     int rc;
+    // the second pass of the cycle's last provisional vector (k = C->kfin <= mres)
+    const int mres = std::max(1, std::min(o.gmres_restart, dev::kMaxBasis - 1));
+    const dim3 gp(w.nb_part, std::max(1, (mres + dev::kDcTile - 1) / dev::kDcTile));
+    hipLaunchKernelGGL(dev::k_dc_dots<TV>, gp, b, 0, s, V, N, 0, &C->kfin, (const TV*)nullptr, N, w.part,
+                       &C->noprov);
+    hipLaunchKernelGGL(dev::k_finish_sum_n, dim3(2 * mres + 2), b, 0, s, w.part, w.nb_part, &C->nfin, C->dsum,
+                       &C->noprov);
+    hipLaunchKernelGGL(dev::k_dc_final, dim3(1), b, 0, s, C);
     hipLaunchKernelGGL(dev::k_gmres_solve, dim3(1), b, 0, s, C);
     hipLaunchKernelGGL(dev::k_multi_update<TV>, gs, b, 0, s, w.x, Z, N, &C->ncols, C->y, N);
     hipLaunchKernelGGL((dev::k_convert<double, TV>), gs, b, 0, s, w.x, Z, N, fin);

@@ -127,27 +127,6 @@ __device__ __forceinline__ void multidot_rows(const TV* __restrict__ Vt, int64_t
   }
 }
 
-// w -= sum_j c_j V_j row by row, then the dots of the updated w with the same
-// K basis entries of the row, kept in registers.
-template <class TV, int K>
-__device__ __forceinline__ void axpy_multidot_rows(TV* __restrict__ w, const TV* __restrict__ V, int64_t stride,
-                                                   const double* cc, int64_t n, double (&acc)[kDotTile]) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    TV v[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) v[j] = V[j * stride + i];
-    double s = (double)w[i];
-#pragma unroll
-    for (int j = 0; j < K; ++j) s -= cc[j] * (double)v[j];
-    const TV st = (TV)s;
-    w[i] = st;
-    const double wi = (double)st;
-#pragma unroll
-    for (int j = 0; j < K; ++j) acc[j] += (double)v[j] * wi;
-  }
-}
-
 // part[j * gridDim.x + b] = partial sum over block b of V_j . w, j < k.
 // blockIdx.y picks a tile of kDotTile basis vectors (grid.y = ceil(k / kDotTile)).
 template <class TV>
@@ -164,27 +143,6 @@ __global__ __launch_bounds__(256) void k_multidot(const TV* __restrict__ V, int6
   for (int j = 0; j < kDotTile; ++j) acc[j] = 0;
   with_count<kDotTile>(kk, [&](auto KC) { multidot_rows<TV, decltype(KC)::value>(Vt, stride, w, n, acc); });
   block_reduce_sums<kDotTile>(acc, kk, shm, part + (int64_t)j0 * gridDim.x + blockIdx.x, gridDim.x);
-}
-
-// w -= sum_{j<k} c_j V_j, then part[j * gridDim.x + b] = partial sum over
-// block b of V_j . w (the updated w), for k <= kDotTile: the multi-axpy of
-// one Gram-Schmidt pass and the multi-dot of the next in one sweep over the
-// basis.  Row assignment, rounding of w and summation order are those of
-// k_multi_axpy followed by k_multidot, so the results are the same.
-template <class TV>
-__global__ __launch_bounds__(256) void k_axpy_multidot(TV* __restrict__ w, const TV* __restrict__ V,
-                                                       int64_t stride, int k, const double* __restrict__ c,
-                                                       int64_t n, double* __restrict__ part, const int* skip) {
-  if (skipped(skip)) return;
-  __shared__ double shm[4 * kDotTile];
-  __shared__ double cc[kDotTile];
-  for (int j = threadIdx.x; j < k; j += blockDim.x) cc[j] = c[j];
-  __syncthreads();
-  double acc[kDotTile];
-#pragma unroll
-  for (int j = 0; j < kDotTile; ++j) acc[j] = 0;
-  with_count<kDotTile>(k, [&](auto KC) { axpy_multidot_rows<TV, decltype(KC)::value>(w, V, stride, cc, n, acc); });
-  block_reduce_sums<kDotTile>(acc, k, shm, part + blockIdx.x, gridDim.x);
 }
 
 // sum over b = threadIdx.x, threadIdx.x + blockDim.x, ... < nb of p[b], added
@@ -217,55 +175,158 @@ __global__ void k_finish_sum(const double* __restrict__ part, int nb, int k, dou
   }
 }
 
+// k_finish_sum over a count held in device memory (*kn sums).
+__global__ void k_finish_sum_n(const double* __restrict__ part, int nb, const int* __restrict__ kn,
+                               double* __restrict__ out, const int* skip) {
+  if (skipped(skip)) return;
+  __shared__ double sh[4];
+  const int k = *kn;
+  for (int j = blockIdx.x; j < k; j += gridDim.x) {
+    double s = strided_sum(part + (int64_t)j * nb, nb);
+    s = block_reduce_sum(s, sh);
+    if (threadIdx.x == 0) out[j] = s;
+  }
+}
+
+// ------------------------------------- Gram-Schmidt with delayed second pass --
+// Arnoldi step k of GMRES uses classical Gram-Schmidt twice, but the second
+// pass of basis vector k runs in step k + 1, fused with the first pass of the
+// next vector (the delayed scheme of Bielich, Langou, Thomas, Swirydowicz,
+// Yamazaki and Boman, Parallel Computing 2022).  At the start of step k the
+// vectors V_0..V_{k-1} are final and V_k holds the provisional vector
+// v~_k (one pass, normalised by its provisional norm); w = J M^-1 v~_k.
+// One sweep over the basis gives s_j = V_j.v~_k, t_j = V_j.w, sigma = v~_k.v~_k
+// and tau = v~_k.w.  Then
+//   v_k = (v~_k - sum_j s_j V_j) / alpha,  alpha = sqrt(sigma - s.s),
+// column k-1 of the Hessenberg matrix takes its second-pass correction, and
+// by the linearity of J M^-1 the product with the final v_k is
+//   J M^-1 v_k = (w - V_{0..k} H_{0..k,0..k-1} s) / alpha,
+// whose first-pass coefficients h follow from t, tau and s without another
+// sweep.  A second sweep writes v_k and the new provisional vector w' = J M^-1 v_k
+// - V_{0..k} h.  Two sweeps over the basis per step instead of three.  The
+// stored preconditioned vectors are those of the provisional vectors, Z~ =
+// Z R with R the upper triangle of (s, alpha); the solution update uses
+// R^-1 y.
+constexpr int kDcTile = 16;  // basis vectors per dot workgroup (two sums each)
+
+template <class TV, int K, bool W>
+__device__ __forceinline__ void dc_dot_rows(const TV* __restrict__ Vt, int64_t stride, const TV* __restrict__ vk,
+                                            const TV* __restrict__ w, int64_t n, bool self,
+                                            double (&sa)[kDcTile], double (&ta)[kDcTile], double (&st)[2]) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    TV v[K > 0 ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; ++j) v[j] = Vt[j * stride + i];
+    const double x = (double)vk[i];
+    const double y = W ? (double)w[i] : 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      sa[j] += (double)v[j] * x;
+      if (W) ta[j] += (double)v[j] * y;
+    }
+    if (self) {
+      st[0] += x * x;
+      if (W) st[1] += x * y;
+    }
+  }
+}
+
+// Partial sums of step k (k from kdev when given): part[q * gridDim.x + b]
+// with q = j: V_j.V_k, q = k + j: V_j.w (j < k; blockIdx.y picks kDcTile of
+// them), q = 2k: V_k.V_k, q = 2k + 1: V_k.w (workgroups with blockIdx.y = 0).
+// w == nullptr: the V_j.V_k and V_k.V_k sums only.
+template <class TV>
+__global__ __launch_bounds__(256) void k_dc_dots(const TV* __restrict__ V, int64_t stride, int k,
+                                                 const int* __restrict__ kdev, const TV* __restrict__ w, int64_t n,
+                                                 double* __restrict__ part, const int* skip) {
+  if (skipped(skip)) return;
+  if (kdev) k = *kdev;
+  const int j0 = blockIdx.y * kDcTile;
+  if (blockIdx.y > 0 && j0 >= k) return;  // whole workgroup: no basis vector in this tile
+  __shared__ double shs[4 * kDcTile], sht[4 * kDcTile], shv[4 * 2];
+  const int kk = max(0, min(kDcTile, k - j0));
+  const bool self = blockIdx.y == 0;
+  const TV* Vt = V + (int64_t)j0 * stride;
+  const TV* vk = V + (int64_t)k * stride;
+  double sa[kDcTile], ta[kDcTile], st[2] = {0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < kDcTile; ++j) sa[j] = ta[j] = 0.0;
+  if (w) {
+    if (kk == 0)
+      dc_dot_rows<TV, 0, true>(Vt, stride, vk, w, n, self, sa, ta, st);
+    else
+      with_count<kDcTile>(kk, [&](auto KC) {
+        dc_dot_rows<TV, decltype(KC)::value, true>(Vt, stride, vk, w, n, self, sa, ta, st);
+      });
+  } else {
+    if (kk == 0)
+      dc_dot_rows<TV, 0, false>(Vt, stride, vk, w, n, self, sa, ta, st);
+    else
+      with_count<kDcTile>(kk, [&](auto KC) {
+        dc_dot_rows<TV, decltype(KC)::value, false>(Vt, stride, vk, w, n, self, sa, ta, st);
+      });
+  }
+  const int nb = gridDim.x;
+  block_reduce_sums<kDcTile>(sa, kk, shs, part + (int64_t)j0 * nb + blockIdx.x, nb);
+  block_reduce_sums<kDcTile>(ta, w ? kk : 0, sht, part + (int64_t)(k + j0) * nb + blockIdx.x, nb);
+  if (self) block_reduce_sums<2>(st, w ? 2 : 1, shv, part + (int64_t)(2 * k) * nb + blockIdx.x, nb);
+}
+
+// One row of the update sweep: v_k = (v~_k - sum_j s_j V_j) / alpha and
+// w' = w / alpha - sum_{j<k} g_j V_j - g_k v_k, then w'.w' (of the stored w').
+template <class TV, int K>
+__device__ __forceinline__ double dc_update_row(TV* __restrict__ V, int64_t stride, int k, TV* __restrict__ w,
+                                                int64_t i, const double* cs, const double* cg, double ia) {
+  double a = (double)V[(int64_t)k * stride + i];
+  double b = (double)w[i] * ia;
+  if constexpr (K >= 0) {
+    TV v[K > 0 ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; ++j) v[j] = V[j * stride + i];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      a -= cs[j] * (double)v[j];
+      b -= cg[j] * (double)v[j];
+    }
+  } else {
+#pragma unroll 8
+    for (int j = 0; j < k; ++j) {
+      const double v = (double)V[j * stride + i];
+      a -= cs[j] * v;
+      b -= cg[j] * v;
+    }
+  }
+  a *= ia;
+  b -= cg[k] * a;
+  const TV bs = (TV)b;
+  V[(int64_t)k * stride + i] = (TV)a;
+  w[i] = bs;
+  return (double)bs * (double)bs;
+}
+
+template <class TV, int K>
+__device__ __forceinline__ double dc_update_rows(TV* __restrict__ V, int64_t stride, int k, TV* __restrict__ w,
+                                                 int64_t n, const double* cs, const double* cg, double ia) {
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += dc_update_row<TV, K>(V, stride, k, w, i, cs, cg, ia);
+  return acc;
+}
+
+struct GmresCtl;
+template <class TV>
+__global__ __launch_bounds__(256) void k_dc_update(TV* __restrict__ V, int64_t stride, int k, TV* __restrict__ w,
+                                                   int64_t n, const GmresCtl* __restrict__ C,
+                                                   double* __restrict__ part, const int* skip);
+
 __global__ void k_finish_max(const double* __restrict__ part, int nb, double* __restrict__ out) {
   __shared__ double sh[4];
   double s = 0;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) s = nan_max(s, part[b]);
   s = block_reduce_max(s, sh);
   if (threadIdx.x == 0) out[0] = s;
-}
-
-// w -= sum_{j<k} c_j V_j  (c in device memory, staged in LDS)
-template <class TV>
-__global__ __launch_bounds__(256) void k_multi_axpy(TV* __restrict__ w, const TV* __restrict__ V,
-                                                    int64_t stride, int k, const double* __restrict__ c,
-                                                    int64_t n, const int* skip) {
-  if (skipped(skip)) return;
-  __shared__ double cc[kMaxBasis];
-  for (int j = threadIdx.x; j < k; j += blockDim.x) cc[j] = c[j];
-  __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    double s = (double)w[i];
-#pragma unroll 8
-    for (int j = 0; j < k; ++j) s -= cc[j] * (double)V[j * stride + i];
-    w[i] = (TV)s;
-  }
-}
-
-// w -= sum_{j<k} c_j V_j and the partial sums of w . w (slot 0)
-template <class TV>
-__global__ __launch_bounds__(256) void k_axpy_norm(TV* __restrict__ w, const TV* __restrict__ V,
-                                                   int64_t stride, int k, const double* __restrict__ c,
-                                                   int64_t n, double* __restrict__ part,
-                                                   const int* skip) {
-  if (skipped(skip)) return;
-  __shared__ double sh[4];
-  __shared__ double cc[kMaxBasis];
-  for (int j = threadIdx.x; j < k; j += blockDim.x) cc[j] = c[j];
-  __syncthreads();
-  double acc = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    double s = (double)w[i];
-#pragma unroll 8
-    for (int j = 0; j < k; ++j) s -= cc[j] * (double)V[j * stride + i];
-    const TV st = (TV)s;
-    w[i] = st;
-    acc += (double)st * (double)st;
-  }
-  const double t = block_reduce_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // x += sum_{j<*kp} c_j Z_j  (x in FP64; count and coefficients in device memory)
@@ -305,15 +366,23 @@ __global__ void k_scale_dev(TV* __restrict__ y, const TV* __restrict__ x, const 
 struct GmresCtl {
   int idle;      // 1: the Arnoldi steps still queued in this cycle do nothing
   int finished;  // 1: stopped (converged, breakdown, iteration cap or error)
-  int its;       // Arnoldi steps taken
+  int its;       // Arnoldi columns completed
   int err;       // 1: a norm was not finite
-  int kcols;     // Arnoldi columns of the current cycle
+  int kcols;     // completed Arnoldi columns of the current cycle
   int ncols;     // columns used by the last solution update
   int max_it, mres;
+  int kprov;   // the column whose second Gram-Schmidt pass is pending, -1: none
+  int noprov;  // 1 when kprov < 0 (the skip flag of the cycle's last pass)
+  int kfin;    // kprov + 1, the basis vector that pass reorthogonalises
+  int nfin;    // 2 kfin + 2, the count of its sums
   double rtol, bn, beta;
-  double inv_scale;  // 1/beta for V_0, then 1/h_{k+1,k} for V_{k+1}
-  double h1[kMaxBasis], h2[kMaxBasis];
-  double H[kMaxBasis * kMaxBasis];  // column k: H[i * kMaxBasis + k]
+  double inv_scale;  // 1/beta for V_0, then 1/(provisional norm) for V_{k+1}
+  double inv_alpha;  // 1/alpha of the step's reorthogonalised vector
+  double dsum[2 * kMaxBasis + 2];       // the step's sums (see k_dc_dots)
+  double cs_[kMaxBasis], cg_[kMaxBasis + 1];  // update coefficients s and g
+  double Hr[(kMaxBasis + 1) * kMaxBasis];  // Hessenberg columns as built: (i, j) at Hr[i * kMaxBasis + j]
+  double H[kMaxBasis * kMaxBasis];         // the rotated columns: (i, j) at H[i * kMaxBasis + j]
+  double R[kMaxBasis * kMaxBasis];         // provisional-to-final basis change, same layout
   double cs[kMaxBasis], sn[kMaxBasis], g[kMaxBasis + 1], y[kMaxBasis];
 };
 
@@ -333,6 +402,10 @@ __global__ void k_gmres_begin(GmresCtl* __restrict__ C, const double* __restrict
   C->err = 0;
   C->kcols = 0;
   C->ncols = 0;
+  C->kprov = -1;
+  C->noprov = 1;
+  C->kfin = 0;
+  C->nfin = 0;
   C->max_it = max_it;
   C->mres = mres;
   C->rtol = rtol;
@@ -347,54 +420,141 @@ __global__ void k_gmres_begin(GmresCtl* __restrict__ C, const double* __restrict
   if (!stop) C->inv_scale = 1.0 / bn;
 }
 
-// Closes Arnoldi step k: column k of H from the two Gram-Schmidt passes, the
-// new norm h_{k+1,k} from the partial sums of w . w, the Givens rotations and
-// the stopping test.  One workgroup; the rotation chain runs on thread 0 over
-// the column staged in LDS.
-__global__ __launch_bounds__(256) void k_arnoldi_close(GmresCtl* __restrict__ C, int k,
-                                                       const double* __restrict__ part, int nb) {
+// Column j of the Hessenberg matrix is final: rotate it by the previous
+// Givens rotations, make rotation j, advance the residual estimate g and test
+// for the end of the run.  Thread 0 only; col is scratch for kMaxBasis + 1.
+__device__ void close_column(GmresCtl* __restrict__ C, int j, double* col) {
+  const int ld = kMaxBasis;
+  for (int i = 0; i <= j + 1; ++i) col[i] = C->Hr[i * ld + j];
+  const double hn = col[j + 1];
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], b = col[i + 1];
+    col[i] = C->cs[i] * a + C->sn[i] * b;
+    col[i + 1] = -C->sn[i] * a + C->cs[i] * b;
+  }
+  const double a = col[j], b = col[j + 1];
+  const double den = hypot(a, b);
+  C->cs[j] = den > 0 ? a / den : 1.0;
+  C->sn[j] = den > 0 ? b / den : 0.0;
+  col[j] = den;
+  for (int i = 0; i <= j; ++i) C->H[i * ld + j] = col[i];
+  C->g[j + 1] = -C->sn[j] * C->g[j];
+  C->g[j] = C->cs[j] * C->g[j];
+  C->its += 1;
+  C->kcols = j + 1;
+  C->kprov = -1;
+  C->noprov = 1;
+  if (!isfinite(den)) C->err = 1;
+  if (C->err || fabs(C->g[j + 1]) <= C->rtol * C->bn || den == 0.0 || hn == 0.0 || C->its >= C->max_it) {
+    C->finished = 1;
+    C->idle = 1;
+  }
+}
+
+// The second pass of the provisional vector k from its sums (s_j = S[j],
+// sigma = S[2k]): alpha, the correction of column k - 1 and its closing, and
+// column k of R.  Thread 0 only; returns alpha.
+__device__ double dc_reorth(GmresCtl* __restrict__ C, int k, double* col) {
+  const int ld = kMaxBasis;
+  const double* S = C->dsum;
+  double ss = 0.0;
+  for (int j = 0; j < k; ++j) ss += S[j] * S[j];
+  const double a2 = S[2 * k] - ss;
+  if (!isfinite(a2)) C->err = 1;
+  const double alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
+  for (int j = 0; j < k; ++j) C->R[j * ld + k] = S[j];
+  C->R[k * ld + k] = alpha;
+  if (k == 0) {
+    C->g[0] *= alpha;  // r = beta v~_0 = beta alpha v_0
+    if (C->err || alpha == 0.0) {
+      C->finished = 1;
+      C->idle = 1;
+    }
+  } else {
+    const double hk = C->Hr[k * ld + k - 1];
+    for (int j = 0; j < k; ++j) C->Hr[j * ld + k - 1] += hk * S[j];
+    C->Hr[k * ld + k - 1] = hk * alpha;
+    close_column(C, k - 1, col);  // alpha = 0: the Krylov space is invariant, the run ends
+  }
+  return alpha;
+}
+
+// Step k after its dot sweep: the second pass of v~_k, then the first-pass
+// coefficients of J M^-1 v_k (column k of Hr) and the update coefficients.
+__global__ __launch_bounds__(256) void k_dc_coef(GmresCtl* __restrict__ C, int k) {
   if (C->idle) return;
   __shared__ double col[kMaxBasis + 1];
-  for (int j = threadIdx.x; j <= k; j += blockDim.x) col[j] = C->h1[j] + C->h2[j];
-  const double hh = sum_partials(part, nb);  // synchronises the workgroup
+  __shared__ double sh_alpha, sh_st;
+  __shared__ int stop;
+  const int ld = kMaxBasis;
+  const double* S = C->dsum;
+  if (threadIdx.x == 0) {
+    const double alpha = dc_reorth(C, k, col);
+    double st = 0.0;
+    for (int j = 0; j < k; ++j) st += S[j] * S[k + j];
+    sh_alpha = alpha;
+    sh_st = st;
+    stop = C->idle;
+  }
+  __syncthreads();
+  if (stop) return;
+  const double ia = 1.0 / sh_alpha;
+  for (int i = threadIdx.x; i <= k; i += blockDim.x) {
+    double c = 0.0;  // (H_{0..k,0..k-1} s)_i; H is upper Hessenberg
+    for (int j = i > 0 ? i - 1 : 0; j < k; ++j) c += C->Hr[i * ld + j] * S[j];
+    const double t = i < k ? S[k + i] : (S[2 * k + 1] - sh_st) * ia;  // v_i . w
+    const double h = (t - c) * ia;
+    C->Hr[i * ld + k] = h;
+    C->cg_[i] = c * ia + h;
+    if (i < k) C->cs_[i] = S[i];
+  }
+  if (threadIdx.x == 0) C->inv_alpha = ia;
+}
+
+// After the update sweep of step k: the provisional norm of w' (column k's
+// subdiagonal until the next step corrects it) from the partial sums of
+// w'.w'.  A zero norm ends the run with column k final.
+__global__ __launch_bounds__(256) void k_dc_norm(GmresCtl* __restrict__ C, int k, const double* __restrict__ part,
+                                                 int nb) {
+  if (C->idle) return;
+  __shared__ double col[kMaxBasis + 1];
+  const double ww = sum_partials(part, nb);  // synchronises the workgroup
   if (threadIdx.x != 0) return;
   const int ld = kMaxBasis;
-  double* H = C->H;
-  const double hn = sqrt(hh);
-  C->its += 1;
-  C->kcols = k + 1;
+  const double hn = sqrt(ww);
   if (!isfinite(hn)) {
     C->err = 1;
     C->finished = 1;
     C->idle = 1;
     return;
   }
+  C->Hr[(k + 1) * ld + k] = hn;
   C->inv_scale = hn > 0 ? 1.0 / hn : 0.0;
-  col[k + 1] = hn;
-  for (int j = 0; j < k; ++j) {
-    const double a = col[j], b = col[j + 1];
-    col[j] = C->cs[j] * a + C->sn[j] * b;
-    col[j + 1] = -C->sn[j] * a + C->cs[j] * b;
+  if (hn == 0.0) {
+    close_column(C, k, col);
+    return;
   }
-  const double a = col[k], b = col[k + 1];
-  const double den = hypot(a, b);
-  C->cs[k] = den > 0 ? a / den : 1.0;
-  C->sn[k] = den > 0 ? b / den : 0.0;
-  col[k] = den;
-  for (int j = 0; j <= k; ++j) H[j * ld + k] = col[j];
-  H[(k + 1) * ld + k] = 0.0;
-  C->g[k + 1] = -C->sn[k] * C->g[k];
-  C->g[k] = C->cs[k] * C->g[k];
-  if (fabs(C->g[k + 1]) <= C->rtol * C->bn || den == 0.0 || hn == 0.0 || C->its >= C->max_it) {
-    C->finished = 1;
-    C->idle = 1;
-  } else if (k + 1 >= C->mres) {
-    C->idle = 1;
-  }
+  // V_{k+1} <- w' / hn follows (k_scale_dev) even after the cycle's last step:
+  // the cycle's final pass (k_dc_final) reorthogonalises it
+  C->kprov = k;
+  C->noprov = 0;
+  C->kfin = k + 1;
+  C->nfin = 2 * (k + 1) + 2;
 }
 
-// Back substitution H y = g over the cycle's columns, column by column (one
-// workgroup: y_i on thread 0, then every thread updates the rows above).
+// End of a cycle whose last column is provisional: its second pass from the
+// sums of k_dc_dots (w == nullptr) and its closing.
+__global__ __launch_bounds__(256) void k_dc_final(GmresCtl* __restrict__ C) {
+  if (C->noprov) return;
+  __shared__ double col[kMaxBasis + 1];
+  if (threadIdx.x != 0) return;
+  dc_reorth(C, C->kfin, col);
+}
+
+// The solution coefficients of the cycle: back substitution H y = g over the
+// completed columns, then R y' = y (the stored vectors are Z~ = Z R), column
+// by column (one workgroup: y_i on thread 0, then every thread updates the
+// rows above).
 __global__ __launch_bounds__(256) void k_gmres_solve(GmresCtl* __restrict__ C) {
   __shared__ double gg[kMaxBasis + 1];
   __shared__ double yi;
@@ -405,16 +565,55 @@ __global__ __launch_bounds__(256) void k_gmres_solve(GmresCtl* __restrict__ C) {
     if (threadIdx.x == 0) {
       const double d = C->H[i * ld + i];
       yi = d != 0 ? gg[i] / d : 0.0;
-      C->y[i] = yi;
     }
     __syncthreads();
     for (int j = threadIdx.x; j < i; j += blockDim.x) gg[j] -= C->H[j * ld + i] * yi;
+    if (threadIdx.x == 0) gg[i] = yi;
+    __syncthreads();
+  }
+  for (int i = k - 1; i >= 0; --i) {
+    if (threadIdx.x == 0) {
+      const double d = C->R[i * ld + i];
+      yi = d != 0 ? gg[i] / d : 0.0;
+      C->y[i] = yi;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < i; j += blockDim.x) gg[j] -= C->R[j * ld + i] * yi;
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     C->ncols = k;
     C->kcols = 0;
   }
+}
+
+// The update sweep of step k: V_k <- v_k, w <- w' and the partial sums of
+// w'.w' (part[b]).  Up to kDotTile basis vectors a row's loads are issued
+// together; beyond, a loop reads them in order.
+template <class TV>
+__global__ __launch_bounds__(256) void k_dc_update(TV* __restrict__ V, int64_t stride, int k, TV* __restrict__ w,
+                                                   int64_t n, const GmresCtl* __restrict__ C,
+                                                   double* __restrict__ part, const int* skip) {
+  if (skipped(skip)) return;
+  __shared__ double sh[4];
+  __shared__ double cs[kMaxBasis], cg[kMaxBasis + 1];
+  for (int j = threadIdx.x; j <= k; j += blockDim.x) {
+    if (j < k) cs[j] = C->cs_[j];
+    cg[j] = C->cg_[j];
+  }
+  __syncthreads();
+  const double ia = C->inv_alpha;
+  double acc = 0.0;
+  if (k == 0)
+    acc = dc_update_rows<TV, 0>(V, stride, k, w, n, cs, cg, ia);
+  else if (k <= kDotTile)
+    with_count<kDotTile>(k, [&](auto KC) {
+      acc = dc_update_rows<TV, decltype(KC)::value>(V, stride, k, w, n, cs, cg, ia);
+    });
+  else
+    acc = dc_update_rows<TV, -1>(V, stride, k, w, n, cs, cg, ia);
+  const double t = block_reduce_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // New cycle from the partial sums of r . r, r = b - J x.
@@ -435,6 +634,8 @@ __global__ void k_gmres_restart(GmresCtl* __restrict__ C, const double* __restri
   }
   C->g[0] = beta;
   C->inv_scale = 1.0 / beta;
+  C->kprov = -1;
+  C->noprov = 1;
   C->idle = 0;
 }
 

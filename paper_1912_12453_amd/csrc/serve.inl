@@ -53,7 +53,7 @@ int64_t lin_footprint(const chns_mesh* m, const chns_solver_opts& o) {
 int64_t workspace_footprint(int64_t n, const chns_solver_opts& o) {
   const int64_t N = n * (o.coupled ? 6 : 4), m = o.gmres_restart;
   const int64_t nb = grid_stride(N, 256, 1024);
-  int64_t b = (3 * 6 * n + 2 * N + 2 * 16 * n) * 8 + 16 * n * 4 + nb * (dev::kMaxBasis + 1) * 8 +
+  int64_t b = (3 * 6 * n + 2 * N + 2 * 16 * n) * 8 + 16 * n * 4 + nb * (2 * dev::kMaxBasis + 2) * 8 +
               (dev::kMaxBasis + 1) * 8 + 4 + (int64_t)sizeof(dev::GmresCtl) +
               (4 + 8) * n * 8 + (4 + 8) * n * 4;  // CH block inverses and the coupled pack buffers
   if (o.precision == 0)
