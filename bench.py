@@ -11,7 +11,7 @@ One timed step is one pass of the whole hot path over that input: for the
 Navier-Stokes block and then the Cahn-Hilliard block, one Newton iteration
 with a fixed-length GMRES(30) cycle (residual and its FP64 norm, node-block
 diagonal and its inversion, 30 preconditioned JVPs with classical
-Gram-Schmidt twice and FP64 dot products, the Newton update, the new
+Gram-Schmidt twice (second pass delayed) and FP64 dot products, the Newton update, the new
 residual), followed by the integral of phi and the total energy.  `value`
 counts the DoF that the 60 JVPs of a step touch (30 x 4 per node for NS,
 30 x 2 per node for CH) per second of wall time: JVP GDoF/s inside the

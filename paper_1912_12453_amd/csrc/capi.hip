@@ -929,9 +929,11 @@ struct Solver {
   }
 
   // Right-preconditioned restarted GMRES(mres) with classical Gram-Schmidt
-  // twice, all control on the device (GmresCtl).  A cycle is enqueued in
-  // parts: Arnoldi steps [k0, k1), then the tail (least-squares update
-  // x += Z y, the true residual b - J x and the start of the next cycle).
+  // twice, the second pass delayed into the next step (k_dc_* in
+  // linalg.hpp), all control on the device (GmresCtl).  A cycle is enqueued in
+  // parts: Arnoldi steps [k0, k1), then the tail (the last provisional
+  // vector's second pass, the least-squares update x += Z~ R^-1 y, the true
+  // residual b - J x and the start of the next cycle).
   // Steps after the stop test has fired return at once; nothing is read back
   // here.
   static constexpr int kSegment = 16;  // Arnoldi steps between host checks
