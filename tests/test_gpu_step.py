@@ -85,6 +85,29 @@ def test_drop16_step(torch, chns, orc, precision):
     assert max(e[0], e[2], e[3], e[4]) < step_tol(precision)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_short_restart_step_matches_oracle(torch, chns, orc, precision):
+    """GMRES(8) under the multigrid V-cycle: every linear solve of the step
+    runs several restart cycles, so the second Gram-Schmidt pass that closes
+    each cycle and the R^-1 y update of the stored preconditioned vectors
+    carry the result; the step still reaches the oracle's step (GMRES(30),
+    Jacobi) within the solver tolerance."""
+    w, pm, om, U = drop(chns, orc, 4)
+    print(f"case drop16 GMRES(8) precision={precision}", flush=True)
+    p = chns.make_params(w.physics)
+    d = torch.tensor(U, device="cuda:0")
+    opts = chns.make_opts(precision=precision, gmres_restart=8, gmres_max_it=5000, precond=2,
+                          gmres_rtol=1e-7 if precision == 0 else 1e-5)
+    rc, st = pm.step(p, opts, d)
+    print(st.as_dict(), flush=True)
+    assert rc == chns.CHNS_OK and st.converged
+    assert st.newton_its[1] > 0 and st.gmres_its[1] > 8 * st.newton_its[1]  # restarted solves
+    Uo, _ = om.step(orc.Params.make(**vars(w.physics)), orc.SolverOpts.make(), U)
+    e = field_err(d.cpu().numpy(), Uo)
+    print("field rel errors vs oracle", ["%.1e" % v for v in e], flush=True)
+    assert max(e[0], e[2], e[3], e[4]) < step_tol(precision)
+
+
 def test_energy_decays_over_steps(torch, chns, orc):
     w, pm, om, U = drop(chns, orc, 4)
     p = chns.make_params(w.physics)
