@@ -958,8 +958,6 @@ struct Solver {
       hipLaunchKernelGGL(dev::k_dc_coef, dim3(1), b, 0, s, C, k);
       hipLaunchKernelGGL(dev::k_dc_update<TV>, dim3(w.nb_part), b, 0, s, V, N, k, wv, N, C, w.part, idle);
       hipLaunchKernelGGL(dev::k_dc_norm, dim3(1), b, 0, s, C, k, w.part, w.nb_part);
-      hipLaunchKernelGGL(dev::k_scale_dev<TV>, gs, b, 0, s, V + (int64_t)(k + 1) * N, wv, &C->inv_scale, N,
-                         idle);
     }
     HIPCHK(hipGetLastError());
     return CHNS_OK;

@@ -203,10 +203,11 @@ __global__ void k_finish_sum_n(const double* __restrict__ part, int nb, const in
 //   J M^-1 v_k = (w - V_{0..k} H_{0..k,0..k-1} s) / alpha,
 // whose first-pass coefficients h follow from t, tau and s without another
 // sweep.  A second sweep writes v_k and the new provisional vector w' = J M^-1 v_k
-// - V_{0..k} h.  Two sweeps over the basis per step instead of three.  The
-// stored preconditioned vectors are those of the provisional vectors, Z~ =
-// Z R with R the upper triangle of (s, alpha); the solution update uses
-// R^-1 y.
+// - V_{0..k} h, unscaled, into V_{k+1}: its norm b (bprov) divides the next
+// step's sums instead of a scaling pass.  Two sweeps over the basis per
+// step instead of three.  The stored preconditioned vectors are those of the
+// stored provisional vectors, Z~ = Z R with R the upper triangle of
+// (b s, b alpha); the solution update uses R^-1 y.
 constexpr int kDcTile = 16;  // basis vectors per dot workgroup (two sums each)
 
 template <class TV, int K, bool W>
@@ -273,13 +274,16 @@ __global__ __launch_bounds__(256) void k_dc_dots(const TV* __restrict__ V, int64
   if (self) block_reduce_sums<2>(st, w ? 2 : 1, shv, part + (int64_t)(2 * k) * nb + blockIdx.x, nb);
 }
 
-// One row of the update sweep: v_k = (v~_k - sum_j s_j V_j) / alpha and
-// w' = w / alpha - sum_{j<k} g_j V_j - g_k v_k, then w'.w' (of the stored w').
+// One row of the update sweep: v_k = (V_k / b - sum_j s_j V_j) / alpha into
+// V_k and w' = w / (b alpha) - sum_{j<k} g_j V_j - g_k v_k into V_{k+1} (the
+// stored vectors are b times the unit provisional vector and J M^-1 of it),
+// then w'.w' (of the stored w').
 template <class TV, int K>
-__device__ __forceinline__ double dc_update_row(TV* __restrict__ V, int64_t stride, int k, TV* __restrict__ w,
-                                                int64_t i, const double* cs, const double* cg, double ia) {
-  double a = (double)V[(int64_t)k * stride + i];
-  double b = (double)w[i] * ia;
+__device__ __forceinline__ double dc_update_row(TV* __restrict__ V, int64_t stride, int k, const TV* __restrict__ w,
+                                                int64_t i, const double* cs, const double* cg, double ia,
+                                                double ib) {
+  double a = (double)V[(int64_t)k * stride + i] * ib;
+  double b = (double)w[i] * (ib * ia);
   if constexpr (K >= 0) {
     TV v[K > 0 ? K : 1];
 #pragma unroll
@@ -301,25 +305,27 @@ __device__ __forceinline__ double dc_update_row(TV* __restrict__ V, int64_t stri
   b -= cg[k] * a;
   const TV bs = (TV)b;
   V[(int64_t)k * stride + i] = (TV)a;
-  w[i] = bs;
+  V[(int64_t)(k + 1) * stride + i] = bs;
   return (double)bs * (double)bs;
 }
 
 template <class TV, int K>
-__device__ __forceinline__ double dc_update_rows(TV* __restrict__ V, int64_t stride, int k, TV* __restrict__ w,
-                                                 int64_t n, const double* cs, const double* cg, double ia) {
+__device__ __forceinline__ double dc_update_rows(TV* __restrict__ V, int64_t stride, int k,
+                                                 const TV* __restrict__ w, int64_t n, const double* cs,
+                                                 const double* cg, double ia, double ib) {
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    acc += dc_update_row<TV, K>(V, stride, k, w, i, cs, cg, ia);
+    acc += dc_update_row<TV, K>(V, stride, k, w, i, cs, cg, ia, ib);
   return acc;
 }
 
 struct GmresCtl;
 template <class TV>
-__global__ __launch_bounds__(256) void k_dc_update(TV* __restrict__ V, int64_t stride, int k, TV* __restrict__ w,
-                                                   int64_t n, const GmresCtl* __restrict__ C,
-                                                   double* __restrict__ part, const int* skip);
+__global__ __launch_bounds__(256) void k_dc_update(TV* __restrict__ V, int64_t stride, int k,
+                                                   const TV* __restrict__ w, int64_t n,
+                                                   const GmresCtl* __restrict__ C, double* __restrict__ part,
+                                                   const int* skip);
 
 __global__ void k_finish_max(const double* __restrict__ part, int nb, double* __restrict__ out) {
   __shared__ double sh[4];
@@ -376,8 +382,10 @@ struct GmresCtl {
   int kfin;    // kprov + 1, the basis vector that pass reorthogonalises
   int nfin;    // 2 kfin + 2, the count of its sums
   double rtol, bn, beta;
-  double inv_scale;  // 1/beta for V_0, then 1/(provisional norm) for V_{k+1}
+  double inv_scale;  // 1/beta for V_0
   double inv_alpha;  // 1/alpha of the step's reorthogonalised vector
+  double bprov;      // norm of the stored provisional vector (1 for V_0)
+  double inv_b;      // 1/bprov for the update sweep
   double dsum[2 * kMaxBasis + 2];       // the step's sums (see k_dc_dots)
   double cs_[kMaxBasis], cg_[kMaxBasis + 1];  // update coefficients s and g
   double Hr[(kMaxBasis + 1) * kMaxBasis];  // Hessenberg columns as built: (i, j) at Hr[i * kMaxBasis + j]
@@ -406,6 +414,7 @@ __global__ void k_gmres_begin(GmresCtl* __restrict__ C, const double* __restrict
   C->noprov = 1;
   C->kfin = 0;
   C->nfin = 0;
+  C->bprov = 1.0;
   C->max_it = max_it;
   C->mres = mres;
   C->rtol = rtol;
@@ -456,14 +465,15 @@ __device__ void close_column(GmresCtl* __restrict__ C, int j, double* col) {
 // column k of R.  Thread 0 only; returns alpha.
 __device__ double dc_reorth(GmresCtl* __restrict__ C, int k, double* col) {
   const int ld = kMaxBasis;
-  const double* S = C->dsum;
+  const double* S = C->dsum;  // sums of the stored vector, bprov times the unit one
+  const double b = C->bprov, ib = 1.0 / b;
   double ss = 0.0;
-  for (int j = 0; j < k; ++j) ss += S[j] * S[j];
-  const double a2 = S[2 * k] - ss;
+  for (int j = 0; j < k; ++j) ss += (S[j] * ib) * (S[j] * ib);
+  const double a2 = S[2 * k] * ib * ib - ss;
   if (!isfinite(a2)) C->err = 1;
   const double alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
   for (int j = 0; j < k; ++j) C->R[j * ld + k] = S[j];
-  C->R[k * ld + k] = alpha;
+  C->R[k * ld + k] = b * alpha;
   if (k == 0) {
     C->g[0] *= alpha;  // r = beta v~_0 = beta alpha v_0
     if (C->err || alpha == 0.0) {
@@ -472,7 +482,7 @@ __device__ double dc_reorth(GmresCtl* __restrict__ C, int k, double* col) {
     }
   } else {
     const double hk = C->Hr[k * ld + k - 1];
-    for (int j = 0; j < k; ++j) C->Hr[j * ld + k - 1] += hk * S[j];
+    for (int j = 0; j < k; ++j) C->Hr[j * ld + k - 1] += hk * (S[j] * ib);
     C->Hr[k * ld + k - 1] = hk * alpha;
     close_column(C, k - 1, col);  // alpha = 0: the Krylov space is invariant, the run ends
   }
@@ -488,10 +498,11 @@ __global__ __launch_bounds__(256) void k_dc_coef(GmresCtl* __restrict__ C, int k
   __shared__ int stop;
   const int ld = kMaxBasis;
   const double* S = C->dsum;
+  const double ib = 1.0 / C->bprov;  // the sums below are of the unit provisional vector
   if (threadIdx.x == 0) {
     const double alpha = dc_reorth(C, k, col);
     double st = 0.0;
-    for (int j = 0; j < k; ++j) st += S[j] * S[k + j];
+    for (int j = 0; j < k; ++j) st += (S[j] * ib) * (S[k + j] * ib);
     sh_alpha = alpha;
     sh_st = st;
     stop = C->idle;
@@ -501,14 +512,17 @@ __global__ __launch_bounds__(256) void k_dc_coef(GmresCtl* __restrict__ C, int k
   const double ia = 1.0 / sh_alpha;
   for (int i = threadIdx.x; i <= k; i += blockDim.x) {
     double c = 0.0;  // (H_{0..k,0..k-1} s)_i; H is upper Hessenberg
-    for (int j = i > 0 ? i - 1 : 0; j < k; ++j) c += C->Hr[i * ld + j] * S[j];
-    const double t = i < k ? S[k + i] : (S[2 * k + 1] - sh_st) * ia;  // v_i . w
+    for (int j = i > 0 ? i - 1 : 0; j < k; ++j) c += C->Hr[i * ld + j] * (S[j] * ib);
+    const double t = i < k ? S[k + i] * ib : (S[2 * k + 1] * ib * ib - sh_st) * ia;  // v_i . w / bprov
     const double h = (t - c) * ia;
     C->Hr[i * ld + k] = h;
     C->cg_[i] = c * ia + h;
-    if (i < k) C->cs_[i] = S[i];
+    if (i < k) C->cs_[i] = S[i] * ib;
   }
-  if (threadIdx.x == 0) C->inv_alpha = ia;
+  if (threadIdx.x == 0) {
+    C->inv_alpha = ia;
+    C->inv_b = ib;
+  }
 }
 
 // After the update sweep of step k: the provisional norm of w' (column k's
@@ -534,8 +548,9 @@ __global__ __launch_bounds__(256) void k_dc_norm(GmresCtl* __restrict__ C, int k
     close_column(C, k, col);
     return;
   }
-  // V_{k+1} <- w' / hn follows (k_scale_dev) even after the cycle's last step:
-  // the cycle's final pass (k_dc_final) reorthogonalises it
+  // V_{k+1} holds w' unscaled, even after the cycle's last step: the next
+  // step's sums, or the cycle's final pass (k_dc_final), divide by bprov
+  C->bprov = hn;
   C->kprov = k;
   C->noprov = 0;
   C->kfin = k + 1;
@@ -587,13 +602,14 @@ __global__ __launch_bounds__(256) void k_gmres_solve(GmresCtl* __restrict__ C) {
   }
 }
 
-// The update sweep of step k: V_k <- v_k, w <- w' and the partial sums of
-// w'.w' (part[b]).  Up to kDotTile basis vectors a row's loads are issued
-// together; beyond, a loop reads them in order.
+// The update sweep of step k: V_k <- v_k, V_{k+1} <- w' (unscaled) and the
+// partial sums of w'.w' (part[b]).  Up to kDotTile basis vectors a row's
+// loads are issued together; beyond, a loop reads them in order.
 template <class TV>
-__global__ __launch_bounds__(256) void k_dc_update(TV* __restrict__ V, int64_t stride, int k, TV* __restrict__ w,
-                                                   int64_t n, const GmresCtl* __restrict__ C,
-                                                   double* __restrict__ part, const int* skip) {
+__global__ __launch_bounds__(256) void k_dc_update(TV* __restrict__ V, int64_t stride, int k,
+                                                   const TV* __restrict__ w, int64_t n,
+                                                   const GmresCtl* __restrict__ C, double* __restrict__ part,
+                                                   const int* skip) {
   if (skipped(skip)) return;
   __shared__ double sh[4];
   __shared__ double cs[kMaxBasis], cg[kMaxBasis + 1];
@@ -602,16 +618,16 @@ __global__ __launch_bounds__(256) void k_dc_update(TV* __restrict__ V, int64_t s
     cg[j] = C->cg_[j];
   }
   __syncthreads();
-  const double ia = C->inv_alpha;
+  const double ia = C->inv_alpha, ib = C->inv_b;
   double acc = 0.0;
   if (k == 0)
-    acc = dc_update_rows<TV, 0>(V, stride, k, w, n, cs, cg, ia);
+    acc = dc_update_rows<TV, 0>(V, stride, k, w, n, cs, cg, ia, ib);
   else if (k <= kDotTile)
     with_count<kDotTile>(k, [&](auto KC) {
-      acc = dc_update_rows<TV, decltype(KC)::value>(V, stride, k, w, n, cs, cg, ia);
+      acc = dc_update_rows<TV, decltype(KC)::value>(V, stride, k, w, n, cs, cg, ia, ib);
     });
   else
-    acc = dc_update_rows<TV, -1>(V, stride, k, w, n, cs, cg, ia);
+    acc = dc_update_rows<TV, -1>(V, stride, k, w, n, cs, cg, ia, ib);
   const double t = block_reduce_sum(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
@@ -636,6 +652,7 @@ __global__ void k_gmres_restart(GmresCtl* __restrict__ C, const double* __restri
   C->inv_scale = 1.0 / beta;
   C->kprov = -1;
   C->noprov = 1;
+  C->bprov = 1.0;
   C->idle = 0;
 }
 
