@@ -945,7 +945,7 @@ struct Solver {
     const int64_t N = n * nf;
     dev::GmresCtl* C = w.ctl;
     const int* idle = &C->idle;
-    const dim3 gs(grid_stride(N)), b(256);
+    const dim3 b(256);
     int rc;
     for (int k = k0; k < k1; ++k) {
       TV* Vk = V + (int64_t)k * N;
