@@ -555,6 +555,20 @@ __global__ __launch_bounds__(256) void k_dc_norm(GmresCtl* __restrict__ C, int k
   C->noprov = 0;
   C->kfin = k + 1;
   C->nfin = 2 * (k + 1) + 2;
+  // The stop test of column k with its provisional entries (the second pass
+  // changes them by rounding-level amounts): when it passes, or the next
+  // column would reach the iteration cap, no further step is taken and the
+  // cycle's final pass closes column k with its exact test.
+  for (int i = 0; i <= k; ++i) col[i] = C->Hr[i * ld + k];
+  col[k + 1] = hn;
+  for (int i = 0; i < k; ++i) {
+    const double a = col[i], b = col[i + 1];
+    col[i] = C->cs[i] * a + C->sn[i] * b;
+    col[i + 1] = -C->sn[i] * a + C->cs[i] * b;
+  }
+  const double den = hypot(col[k], col[k + 1]);
+  const double gk1 = den > 0 ? fabs(col[k + 1] / den * C->g[k]) : 0.0;
+  if (gk1 <= C->rtol * C->bn || C->its + 1 >= C->max_it) C->idle = 1;
 }
 
 // End of a cycle whose last column is provisional: its second pass from the
