@@ -193,10 +193,10 @@ __global__ void k_finish_sum_n(const double* __restrict__ part, int nb, const in
 // pass of basis vector k runs in step k + 1, fused with the first pass of the
 // next vector (the delayed scheme of Bielich, Langou, Thomas, Swirydowicz,
 // Yamazaki and Boman, Parallel Computing 2022).  At the start of step k the
-// vectors V_0..V_{k-1} are final and V_k holds the provisional vector
-// v~_k (one pass, normalised by its provisional norm); w = J M^-1 v~_k.
-// One sweep over the basis gives s_j = V_j.v~_k, t_j = V_j.w, sigma = v~_k.v~_k
-// and tau = v~_k.w.  Then
+// vectors V_0..V_{k-1} are final and V_k holds b v~_k: the provisional vector
+// v~_k (one pass, unit norm) times its norm b (1 for V_0).  With
+// w = J M^-1 v~_k, one sweep over the basis gives (divided by b or b^2)
+// s_j = V_j.v~_k, t_j = V_j.w, sigma = v~_k.v~_k and tau = v~_k.w.  Then
 //   v_k = (v~_k - sum_j s_j V_j) / alpha,  alpha = sqrt(sigma - s.s),
 // column k-1 of the Hessenberg matrix takes its second-pass correction, and
 // by the linearity of J M^-1 the product with the final v_k is
