@@ -65,7 +65,7 @@ ALG_NS_JVP_BYTES_PER_ELEMENT = {"fp64": 170, "mixed": 100}
 # direction, the 4 cached nodal midpoints and the 4-value result).
 NS_LIN = 7
 NS_MID = 4
-NS_JVP_FLOPS_PER_ELEMENT = {"fp64": 5284, "mixed": 5076}
+NS_JVP_FLOPS_PER_ELEMENT = {"fp64": 5260, "mixed": 5076}
 NS_JVP_BYTES_PER_NODE = {"fp64": (4 + NS_MID + 4) * 8, "mixed": (4 + NS_MID + 4) * 4}
 NS_JVP_BYTES_PER_ELEMENT = {"fp64": NS_LIN * 8 * 8 + 8 * 4 + 1, "mixed": NS_LIN * 8 * 4 + 8 * 4 + 1}
 
@@ -78,15 +78,15 @@ NS_JVP_BYTES_PER_ELEMENT = {"fp64": NS_LIN * 8 * 8 + 8 * 4 + 1, "mixed": NS_LIN 
 # Key: bench.py's kernel timing name; value: (flops, bytes/node, bytes/element,
 # peak).  ns_lin_* also launches k_ns_mid (its reads and writes per node).
 ELEMENT_KERNELS = {
-    "ch_residual": (1656, (10 + 2) * 8, 33, "fp64"),
-    "ns_residual": (4920, (12 + 4) * 8, 33, "fp64"),
-    "ch_jvp_f64": (1696, (10 + 2 + 2) * 8, 33, "fp64"),
+    "ch_residual": (1592, (10 + 2) * 8, 33, "fp64"),
+    "ns_residual": (4792, (12 + 4) * 8, 33, "fp64"),
+    "ch_jvp_f64": (1640, (10 + 2 + 2) * 8, 33, "fp64"),
     "ch_jvp_f32": (1704, 10 * 8 + (2 + 2) * 4, 33, "mixed"),
-    "ns_jvp_f64": (6568, (12 + 4 + 4) * 8, 33, "fp64"),
+    "ns_jvp_f64": (6544, (12 + 4 + 4) * 8, 33, "fp64"),
     "ns_jvp_f32": (6344, 12 * 8 + (4 + 4) * 4, 33, "mixed"),
     "ch_lin_f64": (568, 10 * 8, 33 + 4 * 8 * 8, "fp64"),
     "ch_lin_f32": (568, 10 * 8, 33 + 4 * 8 * 4, "mixed"),
-    "ch_jvp_lin_f64": (1160, (2 + 2) * 8, 33 + 4 * 8 * 8, "fp64"),
+    "ch_jvp_lin_f64": (1104, (2 + 2) * 8, 33 + 4 * 8 * 8, "fp64"),
     "ch_jvp_lin_f32": (1168, (2 + 2) * 4, 33 + 4 * 8 * 4, "mixed"),
     "ns_lin_f64": (2597, 12 * 8 + (8 + 4) * 8, 33 + NS_LIN * 8 * 8, "fp64"),
     "ns_lin_f32": (2455, 12 * 8 + 8 * 8 + 4 * 4, 33 + NS_LIN * 8 * 4, "mixed"),

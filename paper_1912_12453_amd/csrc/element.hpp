@@ -149,6 +149,22 @@ __device__ __forceinline__ T test_contract(T c, T Fx, T Fy, T Fz, const Lane<T>&
   return c2 + B * (xchg<kXor1>(c2) - c2) + L.sxh * (Fx2 + xchg<kXor1>(Fx2));
 }
 
+// FP64: each 64-bit exchange is two DPP moves, so the partner's share of a
+// stage is formed on the partner and moved once.  Across an axis the two
+// lanes differ only in that axis' sign s, so B c_P + s (F_P) = B c_P - s_P F_P:
+// per contraction 6 exchanges instead of 9, the same arithmetic count.
+template <>
+__device__ __forceinline__ double test_contract<double>(double c, double Fx, double Fy, double Fz,
+                                                        const Lane<double>& L) {
+  const double A = kA, B = kB;
+  const double c1 = A * c + L.szh * Fz + xchg<kXor7>(B * c - L.szh * Fz);
+  const double Fx1 = A * Fx + xchg<kXor7>(B * Fx);
+  const double Fy1 = A * Fy + xchg<kXor7>(B * Fy);
+  const double c2 = A * c1 + L.syh * Fy1 + xchg<kXor2>(B * c1 - L.syh * Fy1);
+  const double Fx2 = A * Fx1 + xchg<kXor2>(B * Fx1);
+  return A * c2 + L.sxh * Fx2 + xchg<kXor1>(B * c2 - L.sxh * Fx2);
+}
+
 // Sum of a value over the 8 lanes of an element (every lane gets the sum).
 template <class T>
 __device__ __forceinline__ T group_sum(T v) {
